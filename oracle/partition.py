@@ -1,0 +1,122 @@
+"""Spectral partitioning: Algorithm 1 (window counts and shifts) and
+Algorithm 2 (combine partitions, remove redundancies, test for holes).
+
+Test infrastructure only (see oracle/__init__.py).
+
+Readings where the paper is silent or garbled:
+  * round() is half away from zero ("standard rounding", Section 2.2);
+  * for odd p the middle partition of Algorithm 1 refers to itself; it gets
+    ceil(ceil(2 n_r / p) / 2);
+  * Algorithm 1's E_{S,0} and n_{r,0} are E_min and 0, so that
+    E_{S,1} = E_min + Delta n_{r,1} / 2 (the interval-midpoint practice of
+    Section 3);
+  * Algorithm 2's equality test is |lambda_m - lambda_k| <= tau with
+    tau = 1e-6 ||A||_G; the projection uses the unconjugated product
+    (v_k -= v_m (v_m^T v_k), v_m already c-normalised); a pair is removed
+    when ||v_k||_2 after the projections is below 1e-3 of its value before,
+    and kept pairs are c-normalised (u^T u = 1) rather than scaled by |v_k|,
+    because the transport formula needs U^T U = I;
+  * the garbled flag index holes_{k-1} is read as the interface between the
+    partitions that own lambda_m and lambda_k, when they are adjacent.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+from .eigen import order_real
+
+
+def round_half_away(x: float) -> int:
+    return int(math.floor(abs(x) + 0.5)) * (1 if x >= 0 else -1)
+
+
+def alg1_counts(n_r: int, p: int) -> List[int]:
+    """n_{r,j} of Algorithm 1: fewer eigenpairs for partitions deeper in the
+    spectrum; n_{r,j} + n_{r,p-j+1} = ceil(2 n_r / p)."""
+    if p < 1 or n_r < 1:
+        raise ValueError("need p >= 1 and n_r >= 1")
+    counts = [0] * (p + 1)  # 1-based
+    top = math.ceil(2 * n_r / p)
+    for j in range(1, p + 1):
+        if j <= p / 2:
+            counts[j] = round_half_away(2.0 / (1.5 + (j - 1) / p) * n_r / p)
+    for j in range(1, p + 1):
+        if j > p / 2:
+            mirror = p - j + 1
+            if mirror == j:
+                counts[j] = math.ceil(top / 2)
+            else:
+                counts[j] = top - counts[mirror]
+    return counts[1:]
+
+
+def equal_counts(n_r: int, p: int) -> List[int]:
+    base = n_r // p
+    return [base + (1 if j < n_r - base * p else 0) for j in range(p)]
+
+
+def alg1_shifts(counts: Sequence[int], e_min: float, e_max: float, n: int) -> List[float]:
+    """E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N) (n_{r,j} + n_{r,j-1}) / 2."""
+    delta = (e_max - e_min) / n
+    shifts = []
+    prev_s, prev_n = e_min, 0
+    for c in counts:
+        s = prev_s + delta * (c + prev_n) / 2.0
+        shifts.append(s)
+        prev_s, prev_n = s, c
+    return shifts
+
+
+@dataclass
+class Combined:
+    eps: np.ndarray          # ascending real part
+    U: np.ndarray            # N x n, c-normalised
+    owner: np.ndarray        # partition index of each kept pair
+    holes: np.ndarray        # bool, p-1 interface flags (True = hole suspected)
+    removed: int
+
+
+def combine(windows: Sequence[Tuple[np.ndarray, np.ndarray]], norm_a: float,
+            tau_rel: float = 1e-6, drop_ratio: float = 1e-3,
+            keep_lowest: int = 0) -> Combined:
+    """Algorithm 2 over all computed eigenpairs, partition by partition."""
+    p = len(windows)
+    tau = tau_rel * norm_a
+    holes = np.ones(max(p - 1, 0), dtype=bool)
+    kept_eps: List[complex] = []
+    kept_vec: List[np.ndarray] = []
+    kept_own: List[int] = []
+    removed = 0
+    for j, (eps_j, U_j) in enumerate(windows):
+        for i in range(len(eps_j)):
+            lam = complex(eps_j[i])
+            v = np.array(U_j[:, i], dtype=np.complex128, copy=True)
+            before = np.linalg.norm(v)
+            partners = []
+            for m in range(len(kept_eps)):
+                if abs(kept_eps[m] - lam) <= tau:
+                    vm = kept_vec[m]
+                    v = v - vm * (vm @ v)
+                    partners.append(kept_own[m])
+            after = np.linalg.norm(v)
+            if partners and after < drop_ratio * before:
+                removed += 1
+                for o in partners:
+                    if abs(o - j) == 1:
+                        holes[min(o, j)] = False
+                continue
+            kept_eps.append(lam)
+            kept_vec.append(v / np.sqrt(v @ v))
+            kept_own.append(j)
+    eps = np.array(kept_eps, dtype=np.complex128)
+    U = np.stack(kept_vec, axis=1) if kept_vec else np.zeros((0, 0), np.complex128)
+    own = np.array(kept_own, dtype=np.int64)
+    o = order_real(eps)
+    eps, U, own = eps[o], U[:, o], own[o]
+    if keep_lowest and len(eps) > keep_lowest:
+        eps, U, own = eps[:keep_lowest], U[:, :keep_lowest], own[:keep_lowest]
+    return Combined(eps, U, own, holes, removed)
