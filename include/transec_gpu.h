@@ -1,0 +1,207 @@
+/* libtransec_gpu: partitioned shift-without-invert eigensolution of the
+ * complex-symmetric real-space operator A = H - i(Gamma_L + Gamma_R) and the
+ * transmission T(E), on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: B. Feldman and Y. Zhou, "A partitioned shift-without-invert
+ * algorithm to improve parallel eigensolution efficiency in real-space
+ * electronic transport", arXiv:1606.01139.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a tsg_status and never aborts or throws.  On any
+ *     status other than TSG_OK, tsg_last_error() describes the failure.
+ *   - The caller owns every input array; the library copies what it needs
+ *     during the call and keeps no pointer to caller memory.
+ *   - Outputs go to caller-allocated arrays with an explicit capacity;
+ *     TSG_ECAPACITY reports that the capacity was too small and sets the
+ *     count output to the size needed.
+ *   - "host" arrays are in CPU memory; "device" arrays are in the GPU memory
+ *     of the device that is current when the context is built.
+ *   - Grid vectors are indexed n = x + nx (y + ny z) (x fastest); a block of
+ *     B vectors is stored point-major: element (n, c) at ptr[n * ld + c].
+ *   - Complex numbers are pairs (re, im) of the stated real type.
+ *   - Units are Hartree and bohr.
+ *   - A context is used by one host thread at a time; distinct contexts are
+ *     independent.  All GPU work of a context runs on its stream.
+ */
+#ifndef TRANSEC_GPU_H
+#define TRANSEC_GPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSG_OK = 0,
+  TSG_EINVAL = 1,      /* invalid argument (null pointer, size, non-finite value) */
+  TSG_ENOMEM = 2,      /* device or host allocation failed */
+  TSG_ENOCONV = 3,     /* a window did not converge within max_restarts; the converged subset is kept */
+  TSG_EBREAKDOWN = 4,  /* block orthogonalisation lost rank and could not recover */
+  TSG_EDEVICE = 5,     /* HIP runtime error, or no usable gfx950 device */
+  TSG_ESTATE = 6,      /* call out of order (e.g. transmission before a solve) */
+  TSG_ECAPACITY = 7    /* output capacity too small; count output holds the size needed */
+} tsg_status;
+
+enum { TSG_FP64 = 0, TSG_FP32_BULK = 1 };                 /* tsg_opts.precision */
+enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1 };           /* tsg_plan_windows mode */
+enum { TSG_SELECT_NEAREST = 0, TSG_SELECT_SMALLEST_REAL = 1, TSG_SELECT_LARGEST_REAL = 2 };
+enum { TSG_C128 = 0, TSG_C64 = 1 };                       /* element types of device blocks */
+
+typedef struct tsg_ctx tsg_ctx;
+
+/* Uniform real-space grid (Section 1: N ~ V / h^3 points, spacing h).
+ * fd_radius R in 1..6 selects the central difference of order 2R for the
+ * Laplacian (default 6). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+  int32_t fd_radius;
+} tsg_grid;
+
+/* Gaussian absorbers (Section 1; Section 3 gives amplitude and standard
+ * deviation): Gamma_X(z) = amp_X exp(-(z - z_X)^2 / (2 width_X^2)). */
+typedef struct {
+  double amp_L, width_L, z_L;
+  double amp_R, width_R, z_R;
+} tsg_absorber;
+
+/* One spectral partition (Eq. (3)): real shift E_{S,j} and count n_{r,j}. */
+typedef struct {
+  double shift;
+  int32_t nev;
+} tsg_window;
+
+/* Solver options.  tsg_default_opts() fills every field. */
+typedef struct {
+  int32_t precision;    /* TSG_FP64, or TSG_FP32_BULK: complex64 block work then an FP64 polish */
+  double tol;           /* backward error ||A u - theta u|| / (||A||_G ||u||) to reach (default 1e-8) */
+  int32_t block;        /* vectors per block step b (default 16) */
+  int32_t basis;        /* basis size m per window (0: automatic, about 6 n_{r,j}) */
+  int32_t keep;         /* vectors kept at a restart k (0: automatic, about m/2) */
+  int32_t max_restarts; /* per window (default 2000) */
+  uint64_t seed;        /* start-vector seed */
+  int32_t keep_lowest;  /* combine keeps only the n lowest by real part (0: keep all) */
+  int32_t select;       /* TSG_SELECT_NEAREST ('SM' on the shifted operator), or an exterior selection */
+  double bulk_tol;      /* TSG_FP32_BULK: backward error the complex64 phase stops at (default 1e-5) */
+} tsg_opts;
+
+/* Per-window solver statistics of the last solve. */
+typedef struct {
+  double shift;
+  int32_t nev;
+  int32_t n_conv;
+  int32_t restarts;
+  int64_t matvecs;          /* single-vector operator applications */
+  double max_backward_error;
+  int32_t restarts_bulk;    /* FP32-bulk: restarts spent in the complex64 phase */
+} tsg_window_stats;
+
+/* Fills *opts with the defaults listed in tsg_opts. */
+void tsg_default_opts(tsg_opts* opts);
+
+/* Builds the operator of Eq. (1) on the current device and returns a new
+ * context in *out.
+ *   grid:       grid sizes (each >= 1), spacing h > 0, fd_radius 1..6;
+ *   V:          host, N = nx ny nz finite doubles, the local potential V(r);
+ *   ab:         absorber parameters (amplitudes >= 0, widths > 0, finite);
+ *   hip_stream: hipStream_t the context uses (NULL: the null stream).
+ * Errors: TSG_EINVAL, TSG_ENOMEM, TSG_EDEVICE.  On error *out is NULL. */
+tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab,
+                              void* hip_stream, tsg_ctx** out);
+
+/* Algorithm 1, first part (Section 2.2): estimates the extremal real parts
+ * E_min, E_max with two exterior solves (one eigenpair of smallest and of
+ * largest real part), then n_{r,j} (mode TSG_PLAN_ALG1: the load-balancing
+ * formula; TSG_PLAN_EQUAL: n_r/p each) and the shifts
+ *   E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N)(n_{r,j} + n_{r,j-1})/2,
+ * with E_{S,0} = E_min and n_{r,0} = 0.
+ *   out:     host, capacity p windows;
+ *   e_range: host, 2 doubles {E_min, E_max}, or NULL.
+ * Errors: TSG_EINVAL (n_r < 1, p < 1), TSG_ENOCONV, TSG_EDEVICE. */
+tsg_status tsg_plan_windows(tsg_ctx* ctx, int32_t n_r, int32_t p, int32_t mode, const tsg_opts* opts,
+                            tsg_window* out, double* e_range);
+
+/* Solves one partition of Eq. (3): the win.nev eigenpairs of A closest to
+ * win.shift (Section 2.1, 'SM' on the shifted operator, no inversion), and
+ * appends it to the context's list of partitions (a continuation run in the
+ * sense of Section 2).  *n_conv gets the number converged.
+ * Errors: TSG_EINVAL, TSG_ENOCONV (converged subset kept), TSG_EDEVICE. */
+tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opts, int32_t* n_conv);
+
+/* Clears the partition list, solves all p windows together (one batched
+ * iteration on the device), then combines them (tsg_combine).
+ *   windows:    host, p entries;
+ *   n_unique:   host, count after redundancy removal;
+ *   hole_flags: host, p-1 bytes (1 = no redundancy found between partitions
+ *               j and j+1, i.e. a suspected hole), or NULL.
+ * Errors: as tsg_solve_partition. */
+tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int32_t p, const tsg_opts* opts,
+                                    int32_t* n_unique, uint8_t* hole_flags);
+
+/* Algorithm 2 (Section 2.2) over the stored partitions in order: pairs
+ * whose eigenvalues agree within 1e-6 ||A||_G are Gram-Schmidt
+ * bi-orthogonalised under the unconjugated product; a pair whose vector
+ * norm falls below 1e-3 of its value is removed and clears the hole flag of
+ * the interface between the two partitions.  The result is sorted by real
+ * part and c-normalised (u^T u = 1); keep_lowest > 0 truncates it.
+ *   hole_flags: host, (number of partitions - 1) bytes, or NULL.
+ * Errors: TSG_ESTATE (no partitions), TSG_EDEVICE. */
+tsg_status tsg_combine(tsg_ctx* ctx, int32_t keep_lowest, int32_t* n_unique, uint8_t* hole_flags);
+
+/* Combined eigenvalues, ascending real part.
+ *   re_im: host, capacity cap pairs (2*cap doubles).  *n gets the count.
+ * Errors: TSG_ESTATE (no combined set), TSG_ECAPACITY. */
+tsg_status tsg_get_eigenvalues(tsg_ctx* ctx, double* re_im, int32_t cap, int32_t* n);
+
+/* Combined eigenvectors: borrowed device view, complex128, point-major
+ * N x n with leading dimension *ld; valid until the next solve, combine or
+ * tsg_destroy.  Each column satisfies u^T u = 1.
+ * Errors: TSG_ESTATE. */
+tsg_status tsg_get_eigenvectors(tsg_ctx* ctx, void** dev_ptr, int64_t* ld, int32_t* n);
+
+/* Eigenpairs of stored partition j (0-based), ascending real part; vectors
+ * as in tsg_get_eigenvectors (borrowed, complex128, c-normalised).
+ *   re_im: host, capacity cap pairs; dev_ptr, ld: may be NULL.
+ * Errors: TSG_EINVAL (j out of range), TSG_ECAPACITY. */
+tsg_status tsg_get_partition(tsg_ctx* ctx, int32_t j, double* re_im, int32_t cap, int32_t* n, void** dev_ptr,
+                             int64_t* ld);
+
+/* Statistics of stored partition j.  Errors: TSG_EINVAL. */
+tsg_status tsg_get_stats(tsg_ctx* ctx, int32_t j, tsg_window_stats* stats);
+
+/* Transmission (Section 1) T(E) = Tr{G Gamma_R G^dagger Gamma_L} with G
+ * built from the combined eigenpairs, G(E) = sum_k u_k u_k^T / (E - eps_k):
+ *   T(E) = sum_kl g_k conj(g_l) (U^T Gamma_R conj U)_kl (U^T Gamma_L conj U)_kl.
+ *   E: host, nE energies; T: host, nE outputs.
+ * Errors: TSG_EINVAL (nE < 1, null), TSG_ESTATE (no combined set). */
+tsg_status tsg_transmission(tsg_ctx* ctx, const double* E, int32_t nE, double* T);
+
+/* Y = A X for a block of ncols vectors (the stencil matrix-vector product of
+ * Section 1, used by every iteration).  X, Y: device, point-major N x ncols
+ * with leading dimension ld >= ncols, element type dtype (TSG_C128 or
+ * TSG_C64); X and Y must not overlap.  Runs on the context stream; returns
+ * without synchronising.  Errors: TSG_EINVAL. */
+tsg_status tsg_apply_operator(tsg_ctx* ctx, const void* X, void* Y, int32_t ncols, int64_t ld, int32_t dtype);
+
+/* Dense eigen-decomposition of `batch` general complex m x m matrices (the
+ * small Rayleigh-Ritz problem inside each window iteration).  H: device,
+ * batch row-major m x m complex128 matrices, overwritten; theta: device,
+ * batch*m complex128 eigenvalues; Y: device, batch row-major m x m, unit
+ * 2-norm eigenvector columns; info: device, batch int32 (0 = converged).
+ * hip_stream as in tsg_build_operator.  Errors: TSG_EINVAL, TSG_ENOMEM,
+ * TSG_EDEVICE. */
+tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info, void* hip_stream);
+
+/* Message for the last failed call on ctx (or for the last failed call
+ * without a context when ctx is NULL).  Never NULL. */
+const char* tsg_last_error(const tsg_ctx* ctx);
+
+/* Releases the context and all its device memory.  NULL is ignored. */
+void tsg_destroy(tsg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRANSEC_GPU_H */

@@ -1,0 +1,10 @@
+"""MI355X-native partitioned shift-without-invert eigensolver and T(E).
+
+The computation lives in the HIP library libtransec_gpu (csrc/, C-ABI in
+include/transec_gpu.h); `binding` marshals arguments to it.
+"""
+from .binding import (Operator, TsgError, default_opts, dense_eig, load, FP64, FP32_BULK, PLAN_ALG1,
+                      PLAN_EQUAL, SELECT_NEAREST, SELECT_SMALLEST_REAL, SELECT_LARGEST_REAL, EXPORTS)
+
+__all__ = ["Operator", "TsgError", "default_opts", "dense_eig", "load", "FP64", "FP32_BULK", "PLAN_ALG1",
+           "PLAN_EQUAL", "SELECT_NEAREST", "SELECT_SMALLEST_REAL", "SELECT_LARGEST_REAL", "EXPORTS"]

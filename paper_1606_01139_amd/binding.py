@@ -1,0 +1,300 @@
+"""ctypes binding of libtransec_gpu (include/transec_gpu.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and the stream for the calls that
+take device buffers.  There is no fallback: if the library is missing or no
+gfx950 device is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .build import library_path
+
+TSG_OK, TSG_EINVAL, TSG_ENOMEM, TSG_ENOCONV, TSG_EBREAKDOWN, TSG_EDEVICE, TSG_ESTATE, TSG_ECAPACITY = range(8)
+STATUS_NAMES = ["TSG_OK", "TSG_EINVAL", "TSG_ENOMEM", "TSG_ENOCONV", "TSG_EBREAKDOWN", "TSG_EDEVICE",
+                "TSG_ESTATE", "TSG_ECAPACITY"]
+FP64, FP32_BULK = 0, 1
+PLAN_ALG1, PLAN_EQUAL = 0, 1
+SELECT_NEAREST, SELECT_SMALLEST_REAL, SELECT_LARGEST_REAL = 0, 1, 2
+C128, C64 = 0, 1
+
+# Every symbol include/transec_gpu.h declares.
+EXPORTS = [
+    "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
+    "tsg_solve_all_partitions", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
+    "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_apply_operator", "tsg_dense_eig",
+    "tsg_last_error", "tsg_destroy",
+]
+
+
+class TsgGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+                ("fd_radius", C.c_int32)]
+
+
+class TsgAbsorber(C.Structure):
+    _fields_ = [("amp_L", C.c_double), ("width_L", C.c_double), ("z_L", C.c_double),
+                ("amp_R", C.c_double), ("width_R", C.c_double), ("z_R", C.c_double)]
+
+
+class TsgWindow(C.Structure):
+    _fields_ = [("shift", C.c_double), ("nev", C.c_int32)]
+
+
+class TsgOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("basis", C.c_int32),
+                ("keep", C.c_int32), ("max_restarts", C.c_int32), ("seed", C.c_uint64),
+                ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double)]
+
+
+class TsgWindowStats(C.Structure):
+    _fields_ = [("shift", C.c_double), ("nev", C.c_int32), ("n_conv", C.c_int32), ("restarts", C.c_int32),
+                ("matvecs", C.c_int64), ("max_backward_error", C.c_double), ("restarts_bulk", C.c_int32)]
+
+
+class TsgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+        self.status = status
+
+
+_LIB: Optional[C.CDLL] = None
+
+
+def load(path: Optional[str] = None) -> C.CDLL:
+    """Loads the built library; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    p = path or library_path()
+    if not os.path.exists(p):
+        raise RuntimeError(f"libtransec_gpu is not built ({p} missing); run __graft_entry__.build()")
+    lib = C.CDLL(p)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.tsg_default_opts.argtypes = [C.POINTER(TsgOpts)]
+    lib.tsg_default_opts.restype = None
+    lib.tsg_build_operator.argtypes = [C.POINTER(TsgGrid), dp, C.POINTER(TsgAbsorber), vp, C.POINTER(vp)]
+    lib.tsg_plan_windows.argtypes = [vp, i32, i32, i32, C.POINTER(TsgOpts), C.POINTER(TsgWindow), dp]
+    lib.tsg_solve_partition.argtypes = [vp, TsgWindow, C.POINTER(TsgOpts), C.POINTER(i32)]
+    lib.tsg_solve_all_partitions.argtypes = [vp, C.POINTER(TsgWindow), i32, C.POINTER(TsgOpts), C.POINTER(i32),
+                                             C.POINTER(C.c_uint8)]
+    lib.tsg_combine.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_uint8)]
+    lib.tsg_get_eigenvalues.argtypes = [vp, dp, i32, C.POINTER(i32)]
+    lib.tsg_get_eigenvectors.argtypes = [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i32)]
+    lib.tsg_get_partition.argtypes = [vp, i32, dp, i32, C.POINTER(i32), C.POINTER(vp), C.POINTER(i64)]
+    lib.tsg_get_stats.argtypes = [vp, i32, C.POINTER(TsgWindowStats)]
+    lib.tsg_transmission.argtypes = [vp, dp, i32, dp]
+    lib.tsg_apply_operator.argtypes = [vp, vp, vp, i32, i64, i32]
+    lib.tsg_dense_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.tsg_last_error.argtypes = [vp]
+    lib.tsg_last_error.restype = C.c_char_p
+    lib.tsg_destroy.argtypes = [vp]
+    lib.tsg_destroy.restype = None
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if f.restype is C.c_int:  # default restype
+            f.restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(lib, ctx, status: int, allow=()):
+    if status != TSG_OK and status not in allow:
+        raise TsgError(status, lib.tsg_last_error(ctx).decode(errors="replace"))
+    return status
+
+
+def default_opts(**kw) -> TsgOpts:
+    lib = load()
+    o = TsgOpts()
+    lib.tsg_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"tsg_opts has no field {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None  # the library reports the missing device itself
+        return torch.cuda.current_stream().cuda_stream or None
+    return int(stream)
+
+
+class _DevView:
+    """__cuda_array_interface__ wrapper for a borrowed device pointer."""
+
+    def __init__(self, ptr: int, shape, typestr: str, strides=None):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2,
+                                         "strides": strides}
+
+
+def _complex_view(ptr: int, rows: int, cols: int, ld: int):
+    import torch
+    if rows * cols == 0 or not ptr:
+        return torch.zeros((rows, cols), dtype=torch.complex128, device="cuda")
+    v = _DevView(ptr, (rows, cols), "<c16", (ld * 16, 16))
+    return torch.as_tensor(v, device="cuda")
+
+
+@dataclass
+class WindowStats:
+    shift: float
+    nev: int
+    n_conv: int
+    restarts: int
+    matvecs: int
+    max_backward_error: float
+    restarts_bulk: int
+
+
+class Operator:
+    """A context: the operator of Eq. (1) plus the partitions solved on it."""
+
+    def __init__(self, nx: int, ny: int, nz: int, h: float, V: np.ndarray, absorber: Sequence[float],
+                 fd_radius: int = 6, stream=None):
+        self.lib = load()
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        g = TsgGrid(nx, ny, nz, h, fd_radius)
+        ab = TsgAbsorber(*[float(x) for x in absorber])
+        ctx = C.c_void_p()
+        st = _stream_handle(stream)
+        s = self.lib.tsg_build_operator(C.byref(g), V.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ab),
+                                        C.c_void_p(st) if st else None, C.byref(ctx))
+        _check(self.lib, None, s)
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.tsg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- K1
+    def apply(self, X, Y, ld: Optional[int] = None):
+        import torch
+        assert X.is_cuda and Y.is_cuda and X.dim() == 2 and X.shape[0] == self.N and Y.shape == X.shape
+        assert X.is_contiguous() and Y.is_contiguous()
+        dt = {torch.complex128: C128, torch.complex64: C64}[X.dtype]
+        assert Y.dtype == X.dtype
+        s = self.lib.tsg_apply_operator(self.ctx, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                        X.shape[1], ld or X.shape[1], dt)
+        _check(self.lib, self.ctx, s)
+
+    # -- Algorithm 1 planning
+    def plan_windows(self, n_r: int, p: int, mode: int = PLAN_ALG1, opts: Optional[TsgOpts] = None):
+        out = (TsgWindow * p)()
+        er = (C.c_double * 2)()
+        s = self.lib.tsg_plan_windows(self.ctx, n_r, p, mode, C.byref(opts) if opts else None, out, er)
+        _check(self.lib, self.ctx, s)
+        return [(w.shift, w.nev) for w in out], (er[0], er[1])
+
+    def solve_partition(self, shift: float, nev: int, opts: Optional[TsgOpts] = None, allow_noconv=False) -> int:
+        n = C.c_int32()
+        s = self.lib.tsg_solve_partition(self.ctx, TsgWindow(shift, nev), C.byref(opts) if opts else None,
+                                         C.byref(n))
+        _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
+        return n.value
+
+    def solve_all_partitions(self, windows: Sequence[Tuple[float, int]], opts: Optional[TsgOpts] = None,
+                             allow_noconv=False):
+        p = len(windows)
+        arr = (TsgWindow * p)(*[TsgWindow(float(s), int(n)) for s, n in windows])
+        n = C.c_int32()
+        holes = (C.c_uint8 * max(p - 1, 1))()
+        s = self.lib.tsg_solve_all_partitions(self.ctx, arr, p, C.byref(opts) if opts else None, C.byref(n),
+                                              holes)
+        status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
+        return n.value, [bool(holes[i]) for i in range(p - 1)], status
+
+    def combine(self, keep_lowest: int = 0):
+        n = C.c_int32()
+        holes = (C.c_uint8 * 4096)()
+        s = self.lib.tsg_combine(self.ctx, keep_lowest, C.byref(n), holes)
+        _check(self.lib, self.ctx, s)
+        return n.value, holes
+
+    def eigenvalues(self) -> np.ndarray:
+        n = C.c_int32()
+        s = self.lib.tsg_get_eigenvalues(self.ctx, None, 0, C.byref(n))
+        if s not in (TSG_OK, TSG_ECAPACITY):
+            _check(self.lib, self.ctx, s)
+        buf = np.zeros(2 * max(n.value, 1))
+        s = self.lib.tsg_get_eigenvalues(self.ctx, buf.ctypes.data_as(C.POINTER(C.c_double)), n.value,
+                                         C.byref(n))
+        _check(self.lib, self.ctx, s)
+        return buf[0:2 * n.value:2] + 1j * buf[1:2 * n.value:2]
+
+    def eigenvectors(self):
+        """Borrowed zero-copy torch view (N x n complex128) of the combined set."""
+        p = C.c_void_p()
+        ld = C.c_int64()
+        n = C.c_int32()
+        s = self.lib.tsg_get_eigenvectors(self.ctx, C.byref(p), C.byref(ld), C.byref(n))
+        _check(self.lib, self.ctx, s)
+        return _complex_view(p.value or 0, self.N, n.value, ld.value)
+
+    def partition(self, j: int):
+        n = C.c_int32()
+        s = self.lib.tsg_get_partition(self.ctx, j, None, 0, C.byref(n), None, None)
+        _check(self.lib, self.ctx, s)
+        buf = np.zeros(2 * max(n.value, 1))
+        p = C.c_void_p()
+        ld = C.c_int64()
+        s = self.lib.tsg_get_partition(self.ctx, j, buf.ctypes.data_as(C.POINTER(C.c_double)), n.value,
+                                       C.byref(n), C.byref(p), C.byref(ld))
+        _check(self.lib, self.ctx, s)
+        eps = buf[0:2 * n.value:2] + 1j * buf[1:2 * n.value:2]
+        return eps, _complex_view(p.value or 0, self.N, n.value, ld.value)
+
+    def stats(self, j: int) -> WindowStats:
+        st = TsgWindowStats()
+        s = self.lib.tsg_get_stats(self.ctx, j, C.byref(st))
+        _check(self.lib, self.ctx, s)
+        return WindowStats(st.shift, st.nev, st.n_conv, st.restarts, st.matvecs, st.max_backward_error,
+                           st.restarts_bulk)
+
+    def transmission(self, energies: Sequence[float]) -> np.ndarray:
+        E = np.ascontiguousarray(energies, dtype=np.float64)
+        T = np.zeros(len(E))
+        s = self.lib.tsg_transmission(self.ctx, E.ctypes.data_as(C.POINTER(C.c_double)), len(E),
+                                      T.ctypes.data_as(C.POINTER(C.c_double)))
+        _check(self.lib, self.ctx, s)
+        return T
+
+
+def dense_eig(H, stream=None):
+    """Batched dense eigen-decomposition on the device (K4).
+
+    H: torch complex128 CUDA tensor (batch, m, m), row-major; overwritten.
+    Returns (theta (batch, m), Y (batch, m, m) unit-norm eigenvector columns, info (batch,))."""
+    import torch
+    lib = load()
+    assert H.is_cuda and H.dtype == torch.complex128 and H.dim() == 3 and H.is_contiguous()
+    b, m, _ = H.shape
+    theta = torch.empty((b, m), dtype=torch.complex128, device=H.device)
+    Y = torch.empty((b, m, m), dtype=torch.complex128, device=H.device)
+    info = torch.empty((b,), dtype=torch.int32, device=H.device)
+    st = _stream_handle(stream)
+    s = lib.tsg_dense_eig(C.c_void_p(H.data_ptr()), m, b, C.c_void_p(theta.data_ptr()),
+                          C.c_void_p(Y.data_ptr()), C.c_void_p(info.data_ptr()), C.c_void_p(st) if st else None)
+    _check(lib, None, s)
+    return theta, Y, info

@@ -1,0 +1,472 @@
+// Batched tall-skinny dense kernels for the window solver:
+//   gram        C = X^H Y        (block orthogonalisation, Rayleigh-Ritz)
+//   gemm_rows   Y = b Y + X B    (orthogonalisation update, restart rotation)
+//   residuals, c-products, start vectors, copies, small Cholesky.
+// Section 1 of Feldman & Zhou: the orthogonalisation of the growing subspace
+// and the Rayleigh-Ritz rotations are the O(N n^2) part of the eigensolve.
+//
+// All reductions over the grid index go through per-chunk partial sums and a
+// second fixed-order pass, so results are bitwise reproducible run to run.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace tsg {
+
+namespace {
+
+constexpr int kGT = 32;   // gram tile (rows and columns of C)
+constexpr int kGK = 16;   // rows of X, Y staged per step
+
+inline int gram_chunks(int64_t N, int r, int s, int nwin) {
+  const int64_t tiles = int64_t((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT) * nwin;
+  int64_t want = (4096 + tiles - 1) / tiles;
+  int64_t maxc = (N + 255) / 256;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  return int(want);
+}
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                           const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
+                                                           int64_t N, int r, int s, int nchunk,
+                                                           c128* __restrict__ P, const int* __restrict__ wmap) {
+  __shared__ c128 Xs[kGK][kGT];
+  __shared__ c128 Ys[kGK][kGT];
+  const int wz = blockIdx.z;
+  const int w = wmap ? wmap[wz] : wz;
+  const int tilesJ = (s + kGT - 1) / kGT;
+  const int ti = blockIdx.y / tilesJ, tj = blockIdx.y % tilesJ;
+  const int chunk = blockIdx.x;
+  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  const int64_t n0 = chunk * rows_per;
+  const int64_t n1 = min(N, n0 + rows_per);
+  const int t = threadIdx.x;
+  const int tx = t % 16, ty = t / 16;
+  const int i0 = ti * kGT, j0 = tj * kGT;
+  X += int64_t(w) * wsx;
+  Y += int64_t(w) * wsy;
+  c128 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = c128{0.0, 0.0};
+  for (int64_t nb = n0; nb < n1; nb += kGK) {
+    // stage kGK rows x 32 columns of X and Y (512 each, 2 per thread)
+    for (int e = t; e < kGK * kGT; e += 256) {
+      const int rr = e / kGT, cc = e % kGT;
+      const int64_t n = nb + rr;
+      c128 xv{0.0, 0.0}, yv{0.0, 0.0};
+      if (n < n1) {
+        if (i0 + cc < r) { cplx<TX> v = X[n * ldx + i0 + cc]; xv = c128{double(v.re), double(v.im)}; }
+        if (j0 + cc < s) { cplx<TY> v = Y[n * ldy + j0 + cc]; yv = c128{double(v.re), double(v.im)}; }
+      }
+      Xs[rr][cc] = xv;
+      Ys[rr][cc] = yv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kGK; ++k) {
+      c128 x0 = Xs[k][2 * ty], x1 = Xs[k][2 * ty + 1];
+      c128 y0 = Ys[k][2 * tx], y1 = Ys[k][2 * tx + 1];
+      fma_cacc(acc[0][0], x0, y0);
+      fma_cacc(acc[0][1], x0, y1);
+      fma_cacc(acc[1][0], x1, y0);
+      fma_cacc(acc[1][1], x1, y1);
+    }
+    __syncthreads();
+  }
+  c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int i = i0 + 2 * ty + a, j = j0 + 2 * tx + b;
+      if (i < r && j < s) Pw[int64_t(i) * s + j] = acc[a][b];
+    }
+}
+
+__global__ void gram_reduce_kernel(const c128* __restrict__ P, int nchunk, int r, int s, c128* __restrict__ C,
+                                   int64_t ldc, int64_t wsc, const int* __restrict__ wmap) {
+  const int wz = blockIdx.y;
+  const int w = wmap ? wmap[wz] : wz;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t rs = int64_t(r) * s;
+  if (e >= rs) return;
+  const c128* Pw = P + int64_t(wz) * nchunk * rs + e;
+  c128 acc{0.0, 0.0};
+  for (int c = 0; c < nchunk; ++c) acc = acc + Pw[int64_t(c) * rs];
+  const int i = int(e / s), j = int(e % s);
+  C[int64_t(w) * wsc + int64_t(i) * ldc + j] = acc;
+}
+
+// ------------------------------------------------------------- gemm_rows
+template <typename T, int TS>
+__global__ __launch_bounds__(256) void gemm_rows_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                        const c128* __restrict__ B, int64_t ldb, int64_t wsb,
+                                                        cplx<T>* __restrict__ Y, int64_t ldy, int64_t wsy,
+                                                        int64_t N, int r, int s, T beta, T alpha,
+                                                        const int* __restrict__ wmap) {
+  constexpr int TR = 64, KC = 16;
+  constexpr int RPT = TR * TS / 256;  // rows per thread
+  __shared__ cplx<T> Xs[TR][KC + 1];
+  __shared__ cplx<T> Bs[KC][TS];
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  const int64_t r0 = int64_t(blockIdx.x) * TR;
+  const int j0 = blockIdx.y * TS;
+  const int t = threadIdx.x;
+  const int j = t % TS, rg = t / TS;
+  X += int64_t(w) * wsx;
+  Y += int64_t(w) * wsy;
+  B += int64_t(w) * wsb;
+  cplx<T> acc[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) acc[q] = cplx<T>{T(0), T(0)};
+  for (int k0 = 0; k0 < r; k0 += KC) {
+    for (int e = t; e < TR * KC; e += 256) {
+      const int rr = e / KC, kk = e % KC;
+      const int64_t n = r0 + rr;
+      Xs[rr][kk] = (n < N && k0 + kk < r) ? X[n * ldx + k0 + kk] : cplx<T>{T(0), T(0)};
+    }
+    for (int e = t; e < KC * TS; e += 256) {
+      const int kk = e / TS, jj = e % TS;
+      c128 v = (k0 + kk < r && j0 + jj < s) ? B[int64_t(k0 + kk) * ldb + j0 + jj] : c128{0.0, 0.0};
+      Bs[kk][jj] = cplx<T>{T(v.re), T(v.im)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const cplx<T> b = Bs[kk][j];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) fma_acc(acc[q], Xs[rg * RPT + q][kk], b);
+    }
+    __syncthreads();
+  }
+  if (j0 + j < s) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int64_t n = r0 + rg * RPT + q;
+      if (n < N) {
+        cplx<T>* y = Y + n * ldy + j0 + j;
+        cplx<T> v = alpha * acc[q];
+        if (beta != T(0)) v = v + beta * (*y);
+        *y = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- residuals
+constexpr int kRC = 64;  // columns per workgroup in column-sum kernels
+
+inline int colsum_chunks(int64_t N, int s, int nwin) {
+  const int64_t groups = int64_t((s + kRC - 1) / kRC) * nwin;
+  int64_t want = (2048 + groups - 1) / groups;
+  int64_t maxc = (N + 1023) / 1024;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  return int(want);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void residual_partial_kernel(const cplx<T>* __restrict__ U, int64_t ldu, int64_t wsu,
+                                                               const cplx<T>* __restrict__ AU, int64_t lda, int64_t wsa,
+                                                               const c128* __restrict__ theta, int64_t wst, int64_t N,
+                                                               int s, int nchunk, double* __restrict__ P,
+                                                               const int* __restrict__ wmap) {
+  __shared__ double red[2][4][kRC];
+  const int wz = blockIdx.z;
+  const int w = wmap ? wmap[wz] : wz;
+  const int chunk = blockIdx.x;
+  const int jj = threadIdx.x % kRC, lane = threadIdx.x / kRC;
+  const int j = blockIdx.y * kRC + jj;
+  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
+  double r2 = 0.0, u2 = 0.0;
+  if (j < s) {
+    U += int64_t(w) * wsu + j;
+    AU += int64_t(w) * wsa + j;
+    const c128 th = theta[int64_t(w) * wst + j];
+    for (int64_t n = n0 + lane; n < n1; n += 4) {
+      cplx<T> u = U[n * ldu], au = AU[n * lda];
+      double ur = u.re, ui = u.im;
+      double rr = double(au.re) - (th.re * ur - th.im * ui);
+      double ri = double(au.im) - (th.re * ui + th.im * ur);
+      r2 += rr * rr + ri * ri;
+      u2 += ur * ur + ui * ui;
+    }
+  }
+  red[0][lane][jj] = r2;
+  red[1][lane][jj] = u2;
+  __syncthreads();
+  if (lane == 0 && j < s) {
+    double a = red[0][0][jj] + red[0][1][jj] + red[0][2][jj] + red[0][3][jj];
+    double b = red[1][0][jj] + red[1][1][jj] + red[1][2][jj] + red[1][3][jj];
+    double* Pw = P + ((int64_t(wz) * nchunk + chunk) * s + j) * 2;
+    Pw[0] = a;
+    Pw[1] = b;
+  }
+}
+
+__global__ void colsum_reduce_kernel(const double* __restrict__ P, int nchunk, int s, int width, double* __restrict__ out,
+                                     const int* __restrict__ wmap) {
+  const int wz = blockIdx.y;
+  const int w = wmap ? wmap[wz] : wz;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= s * width) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += P[(int64_t(wz) * nchunk + c) * s * width + e];
+  out[int64_t(w) * s * width + e] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cdot_partial_kernel(const cplx<T>* __restrict__ U, int64_t ldu, int64_t wsu,
+                                                           const cplx<T>* __restrict__ AU, int64_t lda, int64_t wsa,
+                                                           int64_t N, int s, int nchunk, double* __restrict__ P,
+                                                           const int* __restrict__ wmap) {
+  __shared__ double red[4][4][kRC];
+  const int wz = blockIdx.z;
+  const int w = wmap ? wmap[wz] : wz;
+  const int chunk = blockIdx.x;
+  const int jj = threadIdx.x % kRC, lane = threadIdx.x / kRC;
+  const int j = blockIdx.y * kRC + jj;
+  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
+  c128 ua{0.0, 0.0}, uu{0.0, 0.0};
+  if (j < s) {
+    U += int64_t(w) * wsu + j;
+    AU += int64_t(w) * wsa + j;
+    for (int64_t n = n0 + lane; n < n1; n += 4) {
+      cplx<T> u = U[n * ldu], au = AU[n * lda];
+      c128 ud{double(u.re), double(u.im)}, ad{double(au.re), double(au.im)};
+      fma_acc(ua, ud, ad);
+      fma_acc(uu, ud, ud);
+    }
+  }
+  red[0][lane][jj] = ua.re;
+  red[1][lane][jj] = ua.im;
+  red[2][lane][jj] = uu.re;
+  red[3][lane][jj] = uu.im;
+  __syncthreads();
+  if (lane == 0 && j < s) {
+    double* Pw = P + ((int64_t(wz) * nchunk + chunk) * s + j) * 4;
+    for (int q = 0; q < 4; ++q) Pw[q] = red[q][0][jj] + red[q][1][jj] + red[q][2][jj] + red[q][3][jj];
+  }
+}
+
+// ------------------------------------------------------------- misc
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void random_kernel(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, uint64_t seed,
+                              const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= N * s) return;
+  const int64_t n = e / s;
+  const int j = int(e % s);
+  uint64_t h = mix64(seed ^ mix64(uint64_t(w) * 0x100000001B3ull + uint64_t(j)) ^ mix64(uint64_t(n) + 0x5851F42Dull));
+  double u = double(h >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+  X[int64_t(w) * wsx + n * ldx + j] = cplx<T>{T(2.0 * u - 1.0), T(0)};
+}
+
+template <typename TX, typename TY>
+__global__ void copy_kernel(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy,
+                            int64_t N, int s, const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= N * s) return;
+  const int64_t n = e / s;
+  const int j = int(e % s);
+  cplx<TX> v = X[int64_t(w) * wsx + n * ldx + j];
+  Y[int64_t(w) * wsy + n * ldy + j] = cplx<TY>{TY(v.re), TY(v.im)};
+}
+
+template <typename T>
+__global__ void scale_kernel(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s,
+                             const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= N * s) return;
+  const int64_t n = e / s;
+  const int j = int(e % s);
+  c128 f = scale[int64_t(w) * s + j];
+  cplx<T>* y = Y + int64_t(w) * wsy + n * ldy + j;
+  cplx<T> v = *y;
+  *y = cplx<T>{T(f.re * v.re - f.im * v.im), T(f.re * v.im + f.im * v.re)};
+}
+
+// One workgroup per window; thread 0 factors G = R^H R (b small) and then
+// the workgroup forms R^{-1} column by column.  A pivot that is not
+// positive relative to the trace flags a rank-deficient block.
+__global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags,
+                                    const int* __restrict__ wmap) {
+  extern __shared__ c128 L[];  // b*b: R (upper), row-major
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  const c128* Gw = G + int64_t(w) * wsg;
+  c128* Ri = Rinv + int64_t(w) * wsr;
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += blockDim.x) L[e] = Gw[e];
+  __syncthreads();
+  __shared__ int bad;
+  if (t == 0) {
+    bad = 0;
+    double tr = 0.0;
+    for (int i = 0; i < b; ++i) tr += L[i * b + i].re;
+    const double floor = 1e-26 * (tr > 0 ? tr : 1.0);
+    for (int k = 0; k < b; ++k) {
+      double d = L[k * b + k].re;
+      for (int p = 0; p < k; ++p) d -= norm2(L[p * b + k]);
+      if (!(d > floor)) { bad = 1; d = floor > 0 ? floor : 1e-300; }
+      d = sqrt(d);
+      L[k * b + k] = c128{d, 0.0};
+      for (int j = k + 1; j < b; ++j) {
+        c128 v = L[k * b + j];
+        for (int p = 0; p < k; ++p) v = v - conj(L[p * b + k]) * L[p * b + j];
+        L[k * b + j] = (1.0 / d) * v;
+      }
+      for (int i = k + 1; i < b; ++i) L[i * b + k] = c128{0.0, 0.0};
+    }
+    flags[w] = bad;
+  }
+  __syncthreads();
+  // R^{-1}: solve R x = e_j for each column j (thread j)
+  for (int j = t; j < b; j += blockDim.x) {
+    for (int i = b - 1; i >= 0; --i) {
+      c128 v = (i == j) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+      for (int p = i + 1; p <= j; ++p) v = v - L[i * b + p] * Ri[int64_t(p) * b + j];
+      Ri[int64_t(i) * b + j] = (i > j) ? c128{0.0, 0.0} : (1.0 / L[i * b + i].re) * v;
+    }
+  }
+}
+
+}  // namespace
+
+// Sized for every active-window count 1..nwin (the chunk count depends on it).
+int64_t gram_workspace(int64_t N, int r, int s, int nwin) {
+  int64_t best = 0;
+  for (int q = 1; q <= nwin; ++q) best = std::max<int64_t>(best, int64_t(gram_chunks(N, r, s, q)) * q);
+  return best * r * s;
+}
+
+template <typename TX, typename TY>
+void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy, int64_t N,
+          int r, int s, c128* C, int64_t ldc, int64_t wsc, int nwin, c128* partials, int64_t cap, hipStream_t st,
+          const int* wmap) {
+  if (nwin <= 0 || r <= 0 || s <= 0) return;
+  const int64_t per = int64_t(nwin) * r * s;
+  if (cap < per) throw DeviceError("gram: partial workspace too small");
+  const int nchunk = int(std::min<int64_t>(gram_chunks(N, r, s, nwin), cap / per));
+  const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
+  hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
+                     ldy, wsy, N, r, s, nchunk, partials, wmap);
+  const int64_t rs = int64_t(r) * s;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(unsigned((rs + 255) / 256), nwin), dim3(256), 0, st, partials, nchunk,
+                     r, s, C, ldc, wsc, wmap);
+}
+
+template <typename T>
+void gemm_rows(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb, cplx<T>* Y,
+               int64_t ldy, int64_t wsy, int64_t N, int r, int s, double beta, int nwin, hipStream_t st,
+               const int* wmap, double alpha) {
+  if (nwin <= 0 || s <= 0) return;
+  const unsigned rt = unsigned((N + 63) / 64);
+  if (s <= 16) {
+    hipLaunchKernelGGL((gemm_rows_kernel<T, 16>), dim3(rt, 1, nwin), dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y,
+                       ldy, wsy, N, r, s, T(beta), T(alpha), wmap);
+  } else {
+    hipLaunchKernelGGL((gemm_rows_kernel<T, 32>), dim3(rt, unsigned((s + 31) / 32), nwin), dim3(256), 0, st, X, ldx,
+                       wsx, B, ldb, wsb, Y, ldy, wsy, N, r, s, T(beta), T(alpha), wmap);
+  }
+}
+
+int64_t residual_workspace(int64_t N, int s, int nwin) {
+  int64_t best = 0;
+  for (int q = 1; q <= nwin; ++q) best = std::max<int64_t>(best, int64_t(colsum_chunks(N, s, q)) * q);
+  return best * s * 4;
+}
+
+template <typename T>
+void residual_norms(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
+                    const c128* theta, int64_t wst, int64_t N, int s, int nwin, double* out, double* partials,
+                    int64_t cap, hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  const int64_t per = int64_t(nwin) * s * 2;
+  if (cap < per) throw DeviceError("residual_norms: partial workspace too small");
+  const int nchunk = int(std::min<int64_t>(colsum_chunks(N, s, nwin), cap / per));
+  hipLaunchKernelGGL((residual_partial_kernel<T>), dim3(nchunk, (s + kRC - 1) / kRC, nwin), dim3(256), 0, st, U, ldu,
+                     wsu, AU, lda, wsa, theta, wst, N, s, nchunk, partials, wmap);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((2 * s + 255) / 256, nwin), dim3(256), 0, st, partials, nchunk, s, 2,
+                     out, wmap);
+}
+
+template <typename T>
+void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa, int64_t N, int s,
+           int nwin, c128* out, double* partials, int64_t cap, hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  const int64_t per = int64_t(nwin) * s * 4;
+  if (cap < per) throw DeviceError("cdots: partial workspace too small");
+  const int nchunk = int(std::min<int64_t>(colsum_chunks(N, s, nwin), cap / per));
+  double* P = partials;
+  hipLaunchKernelGGL((cdot_partial_kernel<T>), dim3(nchunk, (s + kRC - 1) / kRC, nwin), dim3(256), 0, st, U, ldu, wsu,
+                     AU, lda, wsa, N, s, nchunk, P, wmap);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((4 * s + 255) / 256, nwin), dim3(256), 0, st, P, nchunk, s, 4,
+                     reinterpret_cast<double*>(out), wmap);
+}
+
+template <typename T>
+void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, int nwin, uint64_t seed, hipStream_t st,
+                  const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  hipLaunchKernelGGL((random_kernel<T>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, X, ldx, wsx, N,
+                     s, seed, wmap);
+}
+
+template <typename TX, typename TY>
+void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy, int64_t N, int s,
+                int nwin, hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  hipLaunchKernelGGL((copy_kernel<TX, TY>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, X, ldx, wsx,
+                     Y, ldy, wsy, N, s, wmap);
+}
+
+template <typename T>
+void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s, int nwin, hipStream_t st,
+                const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  hipLaunchKernelGGL((scale_kernel<T>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, Y, ldy, wsy,
+                     scale, N, s, wmap);
+}
+
+void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
+                  const int* wmap) {
+  if (nwin <= 0) return;
+  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(nwin), dim3(64), size_t(b) * b * sizeof(c128), st, G, wsg, b, Rinv,
+                     wsr, flags, wmap);
+}
+
+#define TSG_INST_T(T)                                                                                              \
+  template void gemm_rows<T>(const cplx<T>*, int64_t, int64_t, const c128*, int64_t, int64_t, cplx<T>*, int64_t,  \
+                             int64_t, int64_t, int, int, double, int, hipStream_t, const int*, double);                               \
+  template void residual_norms<T>(const cplx<T>*, int64_t, int64_t, const cplx<T>*, int64_t, int64_t, const c128*, \
+                                  int64_t, int64_t, int, int, double*, double*, int64_t, hipStream_t, const int*);                     \
+  template void cdots<T>(const cplx<T>*, int64_t, int64_t, const cplx<T>*, int64_t, int64_t, int64_t, int, int,    \
+                         c128*, double*, int64_t, hipStream_t, const int*);                                                               \
+  template void random_block<T>(cplx<T>*, int64_t, int64_t, int64_t, int, int, uint64_t, hipStream_t, const int*); \
+  template void scale_cols<T>(cplx<T>*, int64_t, int64_t, const c128*, int64_t, int, int, hipStream_t, const int*);
+TSG_INST_T(double)
+TSG_INST_T(float)
+
+#define TSG_INST_2(TX, TY)                                                                                           \
+  template void gram<TX, TY>(const cplx<TX>*, int64_t, int64_t, const cplx<TY>*, int64_t, int64_t, int64_t, int, \
+                             int, c128*, int64_t, int64_t, int, c128*, int64_t, hipStream_t, const int*);         \
+  template void copy_block<TX, TY>(const cplx<TX>*, int64_t, int64_t, cplx<TY>*, int64_t, int64_t, int64_t, int,  \
+                                   int, hipStream_t, const int*);
+TSG_INST_2(double, double)
+TSG_INST_2(float, float)
+TSG_INST_2(float, double)
+TSG_INST_2(double, float)
+
+}  // namespace tsg

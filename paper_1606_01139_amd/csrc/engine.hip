@@ -1,0 +1,720 @@
+// Host engine: operator set-up, the batched per-window shift-without-invert
+// iteration, the FP64 finish of each eigenpair, Algorithm 2 and T(E).
+//
+// The window iteration (Section 2.1 of Feldman & Zhou): for each partition j
+// a restarted Krylov method is applied to A - E_{S,j} without inversion and
+// the Ritz values of smallest magnitude of the shifted operator (nearest the
+// shift) are kept ('SM').  Here every window of a solve advances together:
+//   expansion    Y = A X on the newest block of every window (K1), then the
+//                block is orthogonalised against its window's basis (two
+//                passes of classical Gram-Schmidt, Cholesky-QR inside);
+//   projection   H = V^H (A V)  (FP64 accumulation);
+//   small eig    eigenpairs of H (K4), ordered by |theta - E_{S,j}|;
+//   restart      keep the k nearest Ritz vectors (thick restart, the
+//                Krylov-Schur form of ARPACK's implicit restart) and continue
+//                from the component of A X_last orthogonal to the basis;
+//   convergence  backward error of the n_{r,j} nearest Ritz pairs.
+// In TSG_FP32_BULK mode the blocks are complex64 until the backward error
+// reaches bulk_tol, then the kept basis is promoted to complex128 and the
+// iteration continues in FP64 to tol.  Every converged pair is finished in
+// FP64: a fresh matrix-vector product, the c-Rayleigh quotient u^T A u/u^T u
+// and c-normalisation u^T u = 1 (the bi-orthogonality of Section 1).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "engine.h"
+
+namespace tsg {
+
+namespace {
+
+double fd_coef(int R, int m) {
+  // c_m = 2 (-1)^(m+1) (R!)^2 / (m^2 (R-m)! (R+m)!)
+  auto fact = [](int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; };
+  const double fr = fact(R);
+  const double v = 2.0 * fr * fr / (double(m) * m * fact(R - m) * fact(R + m));
+  return (m % 2 == 1) ? v : -v;
+}
+
+template <typename T> const T* opV(const tsg_ctx* c);
+template <> const double* opV<double>(const tsg_ctx* c) { return c->V.p; }
+template <> const float* opV<float>(const tsg_ctx* c) { return c->Vf.p; }
+template <typename T> const T* opG(const tsg_ctx* c);
+template <> const double* opG<double>(const tsg_ctx* c) { return c->gam.p; }
+template <> const float* opG<float>(const tsg_ctx* c) { return c->gamf.p; }
+
+template <typename T>
+void stencil(const tsg_ctx* c, const cplx<T>* X, int64_t ldx, int64_t wsx, cplx<T>* Y, int64_t ldy, int64_t wsy,
+             int ncols, int nwin, const int* wmap) {
+  StencilArgs<T> a;
+  a.X = X; a.ldx = ldx; a.wsx = wsx;
+  a.Y = Y; a.ldy = ldy; a.wsy = wsy;
+  a.ncols = ncols;
+  a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.radius = c->R;
+  a.V = opV<T>(c);
+  a.gamma = opG<T>(c);
+  a.diag0 = T(c->diag0);
+  for (int m = 0; m < 7; ++m) a.coef[m] = T(c->coef[m]);
+  a.shifts = nullptr;
+  a.wmap = wmap;
+  const int64_t base = ((int64_t(c->nx) * c->ny * ncols + 255) / 256) * std::max(nwin, 1);
+  int64_t nzc = (2048 + base - 1) / base;
+  nzc = std::max<int64_t>(1, std::min<int64_t>(nzc, std::max(1, c->nz / 4)));
+  a.zchunk = int((c->nz + nzc - 1) / nzc);
+  launch_stencil<T>(a, nwin, c->st);
+}
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw DeviceError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int round_up(int x, int b) { return ((x + b - 1) / b) * b; }
+
+// TSG_TRACE=1 in the environment prints one line per restart and window.
+bool trace_on() {
+  static const bool on = [] { const char* v = std::getenv("TSG_TRACE"); return v && v[0] == '1'; }();
+  return on;
+}
+
+// ------------------------------------------------------------------ batch
+// Device state of one batched solve in storage precision T.  Window w's
+// basis V (N x m, point-major, ld m) starts at V + w * N * m; likewise AV and
+// the rotation targets Vr, AVr.  F holds each window's continuation block.
+template <typename T> struct Batch {
+  int nw = 0, m = 0, k = 0, b = 0, nv = 0;
+  int64_t N = 0;
+  DevArr<cplx<T>> V, AV, Vr, AVr, F, Ft;
+  DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, part;
+  DevArr<double> res, sig;
+  DevArr<int> flags, info, wmap;
+
+  void alloc(int nw_, int64_t N_, int m_, int k_, int b_, int nv_) {
+    nw = nw_; N = N_; m = m_; k = k_; b = b_; nv = nv_;
+    const size_t nm = size_t(N) * m * nw;
+    V.alloc(nm); AV.alloc(nm); Vr.alloc(nm); AVr.alloc(nm);
+    F.alloc(size_t(N) * b * nw); Ft.alloc(size_t(N) * b * nw);
+    H.alloc(size_t(m) * m * nw); Ys.alloc(size_t(m) * m * nw);
+    work.alloc(size_t(smalleig_workspace(m)) * nw);
+    theta.alloc(size_t(m) * nw);
+    Ysel.alloc(size_t(m) * (k + nv) * nw);
+    thsel.alloc(size_t(nv) * nw);
+    C.alloc(size_t(m) * b * nw);
+    G.alloc(size_t(b) * b * nw);
+    Rinv.alloc(size_t(b) * b * nw);
+    int64_t pw = gram_workspace(N, m, m, nw);
+    pw = std::max(pw, gram_workspace(N, m, b, nw));
+    pw = std::max(pw, gram_workspace(N, b, b, nw));
+    pw = std::max(pw, residual_workspace(N, nv, nw));
+    part.alloc(size_t(pw));
+    res.alloc(size_t(2) * nv * nw);
+    sig.alloc(size_t(nw));
+    flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw));
+  }
+  int64_t ws() const { return N * m; }
+};
+
+// dest (N x b per window, row stride ldd, window stride wsd) is made
+// orthonormal against the first J basis columns (CGS2) and within itself
+// (Cholesky-QR, twice).
+template <typename T>
+void orthonormalize(tsg_ctx* c, Batch<T>& B, cplx<T>* dest, int64_t ldd, int64_t wsd, int J, int na) {
+  const int b = B.b;
+  const int* wm = B.wmap.p;
+  for (int pass = 0; pass < 2 && J > 0; ++pass) {
+    gram<T, T>(B.V.p, B.m, B.ws(), dest, ldd, wsd, B.N, J, b, B.C.p, b, int64_t(B.m) * b, na, B.part.p,
+               int64_t(B.part.n), c->st, wm);
+    gemm_rows<T>(B.V.p, B.m, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.N, J, b, 1.0, na, c->st, wm, -1.0);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    cplx<T>* src = pass == 0 ? dest : B.Ft.p;
+    int64_t lds = pass == 0 ? ldd : b, wss = pass == 0 ? wsd : B.N * b;
+    cplx<T>* dst = pass == 0 ? B.Ft.p : dest;
+    int64_t ldo = pass == 0 ? b : ldd, wso = pass == 0 ? B.N * b : wsd;
+    gram<T, T>(src, lds, wss, src, lds, wss, B.N, b, b, B.G.p, b, int64_t(b) * b, na, B.part.p,
+               int64_t(B.part.n), c->st, wm);
+    cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, na, c->st, wm);
+    gemm_rows<T>(src, lds, wss, B.Rinv.p, b, int64_t(b) * b, dst, ldo, wso, B.N, b, b, 0.0, na, c->st, wm, 1.0);
+  }
+}
+
+struct WinOut {
+  bool done = false;
+  bool converged = false;
+  int restarts = 0;
+  int64_t matvecs = 0;
+  std::vector<c128> theta;   // selection order
+  std::vector<double> rho;
+};
+
+// Runs the batched iteration on windows of one precision.  init_from:
+// nullptr = random start; otherwise per-window [V_k | F] blocks (N x (k+b),
+// complex64, ld k+b) from a complex64 phase.  On convergence of window w,
+// `save` receives the current device state.
+template <typename T, typename Save>
+void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int mode, double tol, int max_restarts,
+             uint64_t seed, const cplx<float>* init_from, std::vector<WinOut>& out, Save&& save,
+             double stall_floor = 0.0) {
+  const int nw = B.nw, m = B.m, k = B.k, b = B.b, nv = B.nv;
+  const int64_t N = B.N, wsV = B.ws();
+  hipStream_t st = c->st;
+  std::vector<int> active(nw);
+  std::iota(active.begin(), active.end(), 0);
+  check(hipMemcpyAsync(B.wmap.p, active.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st), "wmap");
+  std::vector<double> shifts(nw);
+  for (int w = 0; w < nw; ++w) shifts[w] = wins[w].shift;
+  check(hipMemcpyAsync(B.sig.p, shifts.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st), "shifts");
+  out.assign(nw, WinOut{});
+  int na = nw;
+  int j0 = 0;
+  if (!init_from) {
+    random_block<T>(B.V.p, m, wsV, N, b, na, seed, st, B.wmap.p);
+    orthonormalize<T>(c, B, B.V.p, m, wsV, 0, na);
+  } else {
+    // promote the complex64 kept basis and continuation block, re-orthonormalise
+    // block by block in this precision and recompute A V for the kept part
+    copy_block<float, T>(init_from, k + b, int64_t(N) * (k + b), B.V.p, m, wsV, N, k + b, na, st, B.wmap.p);
+    for (int j = 0; j <= k; j += b) orthonormalize<T>(c, B, B.V.p + j, m, wsV, j, na);
+    stencil<T>(c, B.V.p, m, wsV, B.AV.p, m, wsV, k, na, B.wmap.p);
+    for (int w = 0; w < nw; ++w) out[w].matvecs += k;
+    j0 = k;
+  }
+  // complex64 phase: a window whose worst wanted backward error stops
+  // improving (no 5% gain in 8 restarts) below stall_floor is handed on, as
+  // complex64 storage bounds the attainable residual
+  std::vector<double> best(nw, 1e300);
+  std::vector<int> since(nw, 0);
+  std::vector<double> hres(size_t(2) * nv * nw);
+  std::vector<c128> hth(size_t(nv) * nw);
+  std::vector<int> hinfo(nw);
+  for (int cyc = 0; cyc < max_restarts && na > 0; ++cyc) {
+    const int* wm = B.wmap.p;
+    for (int j = j0; j < m; j += b) {
+      stencil<T>(c, B.V.p + j, m, wsV, B.AV.p + j, m, wsV, b, na, wm);
+      for (int q = 0; q < na; ++q) out[active[q]].matvecs += b;
+      const bool last = j + b >= m;
+      cplx<T>* dest = last ? B.F.p : B.V.p + j + b;
+      const int64_t ldd = last ? b : m, wsd = last ? N * b : wsV;
+      copy_block<T, T>(B.AV.p + j, m, wsV, dest, ldd, wsd, N, b, na, st, wm);
+      orthonormalize<T>(c, B, dest, ldd, wsd, j + b, na);
+    }
+    // Rayleigh-Ritz projection and small eigenproblem
+    gram<T, T>(B.V.p, m, wsV, B.AV.p, m, wsV, N, m, m, B.H.p, m, int64_t(m) * m, na, B.part.p,
+               int64_t(B.part.n), st, wm);
+    smalleig(B.H.p, int64_t(m) * m, m, B.theta.p, m, B.Ys.p, int64_t(m) * m, B.work.p, smalleig_workspace(m),
+             B.info.p, na, st, wm);
+    select_restart(B.theta.p, m, B.Ys.p, int64_t(m) * m, m, B.sig.p, mode, k, nv, B.Ysel.p, int64_t(m) * (k + nv),
+                   B.thsel.p, nv, na, st, wm);
+    // rotation: [V Q_k | V Y_nev] and the same for A V
+    gemm_rows<T>(B.V.p, m, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.Vr.p, m, wsV, N, m, k + nv, 0.0, na, st,
+                 wm);
+    gemm_rows<T>(B.AV.p, m, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.AVr.p, m, wsV, N, m, k + nv, 0.0, na,
+                 st, wm);
+    residual_norms<T>(B.Vr.p + k, m, wsV, B.AVr.p + k, m, wsV, B.thsel.p, nv, N, nv, na, B.res.p,
+                      reinterpret_cast<double*>(B.part.p), 2 * int64_t(B.part.n), st, wm);
+    check(hipMemcpyAsync(hres.data(), B.res.p, sizeof(double) * 2 * nv * nw, hipMemcpyDeviceToHost, st), "res");
+    check(hipMemcpyAsync(hth.data(), B.thsel.p, sizeof(c128) * nv * nw, hipMemcpyDeviceToHost, st), "theta");
+    check(hipMemcpyAsync(hinfo.data(), B.info.p, sizeof(int) * nw, hipMemcpyDeviceToHost, st), "info");
+    check(hipStreamSynchronize(st), "sync");
+    std::swap(B.V, B.Vr);
+    std::swap(B.AV, B.AVr);
+    std::vector<int> still;
+    for (int q = 0; q < na; ++q) {
+      const int w = active[q];
+      WinOut& o = out[w];
+      o.restarts = cyc + 1;
+      const int nev = wins[w].nev;
+      o.theta.assign(hth.begin() + size_t(w) * nv, hth.begin() + size_t(w) * nv + nev);
+      o.rho.resize(nev);
+      int nconv = 0;
+      for (int i = 0; i < nev; ++i) {
+        const double r2 = hres[(size_t(w) * nv + i) * 2], u2 = hres[(size_t(w) * nv + i) * 2 + 1];
+        const double rho = std::sqrt(std::max(r2, 0.0)) / (c->normA * std::sqrt(std::max(u2, 1e-300)));
+        o.rho[i] = std::isfinite(rho) ? rho : 1e300;
+        nconv += (o.rho[i] <= tol) ? 1 : 0;
+      }
+      const double worst = *std::max_element(o.rho.begin(), o.rho.end());
+      if (trace_on())
+        std::fprintf(stderr, "[tsg] %s cycle %d window %d nconv %d/%d worst %.3e info %d\n",
+                     sizeof(T) == 4 ? "c64" : "c128", cyc, w, nconv, nev, worst, hinfo[w]);
+      if (worst < 0.95 * best[w]) { best[w] = worst; since[w] = 0; } else { ++since[w]; }
+      const bool stalled = stall_floor > 0.0 && since[w] >= 8 && worst <= stall_floor;
+      if (nconv == nev || stalled) {
+        o.done = true;
+        o.converged = true;
+        save(w);
+      } else if (cyc + 1 == max_restarts) {
+        o.done = true;
+        o.converged = false;
+        save(w);
+      } else {
+        still.push_back(w);
+      }
+    }
+    active = still;
+    na = int(active.size());
+    if (na == 0) break;
+    check(hipMemcpyAsync(B.wmap.p, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, st), "wmap");
+    // next block: the continuation F, re-orthogonalised against the kept basis
+    copy_block<T, T>(B.F.p, b, N * b, B.V.p + k, m, wsV, N, b, na, st, B.wmap.p);
+    orthonormalize<T>(c, B, B.V.p + k, m, wsV, k, na);
+    j0 = k;
+  }
+}
+
+void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& b) {
+  b = o.block > 0 ? o.block : 16;
+  m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max(6 * nvmax, nvmax + 4 * b), b);
+  const int mcap = int(std::min<int64_t>(N / b, 4096) * b) - b;
+  if (m > mcap) m = std::max(mcap, 2 * b);
+  k = o.keep > 0 ? (o.keep / b) * b : ((m / 2) / b) * b;
+  if (k < round_up(nvmax, b)) k = round_up(nvmax, b);
+  if (k + b > m) throw InvalidArg("basis too small for the requested eigenpairs (need keep + block <= basis)");
+  if (k + nvmax > m) throw InvalidArg("basis too small: keep + nev must not exceed basis");
+}
+
+// FP64 finish of one window's nev vectors (device c128, ld nev): fresh
+// A u, c-Rayleigh quotient, backward error, c-normalisation, sort by real
+// part.  Returns the partition.
+Partition finish_window(tsg_ctx* c, const WindowSpec& ws, DevArr<c128>&& U, int nev, const WinOut& o,
+                        int restarts_bulk) {
+  const int64_t N = c->N;
+  hipStream_t st = c->st;
+  DevArr<c128> AU, dots, part, scale, Us;
+  DevArr<double> res;
+  AU.alloc(size_t(N) * nev);
+  stencil<double>(c, U.p, nev, 0, AU.p, nev, 0, nev, 1, nullptr);
+  dots.alloc(size_t(nev) * 2);
+  part.alloc(size_t(std::max(residual_workspace(N, nev, 1), int64_t(1))) * 2);
+  cdots<double>(U.p, nev, 0, AU.p, nev, 0, N, nev, 1, dots.p, reinterpret_cast<double*>(part.p),
+                2 * int64_t(part.n), st);
+  std::vector<c128> hd(size_t(nev) * 2);
+  check(hipMemcpyAsync(hd.data(), dots.p, sizeof(c128) * 2 * nev, hipMemcpyDeviceToHost, st), "dots");
+  check(hipStreamSynchronize(st), "sync");
+  std::vector<c128> thc(nev), sc(nev);
+  for (int i = 0; i < nev; ++i) {
+    const c128 uAu = hd[2 * i], uu = hd[2 * i + 1];
+    thc[i] = cdiv(uAu, uu);
+    const c128 r = csqrt(uu);
+    sc[i] = cdiv(c128{1.0, 0.0}, r);
+  }
+  DevArr<c128> thd;
+  thd.alloc(nev);
+  check(hipMemcpyAsync(thd.p, thc.data(), sizeof(c128) * nev, hipMemcpyHostToDevice, st), "thc");
+  res.alloc(size_t(2) * nev);
+  residual_norms<double>(U.p, nev, 0, AU.p, nev, 0, thd.p, 0, N, nev, 1, res.p, reinterpret_cast<double*>(part.p),
+                         2 * int64_t(part.n), st);
+  std::vector<double> hr(size_t(2) * nev);
+  check(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * 2 * nev, hipMemcpyDeviceToHost, st), "res");
+  check(hipStreamSynchronize(st), "sync");
+  // sort by real part (then imaginary part)
+  std::vector<int> ord(nev);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (thc[a].re != thc[b].re) return thc[a].re < thc[b].re;
+    return thc[a].im < thc[b].im;
+  });
+  Partition P;
+  P.shift = ws.shift;
+  P.nev = ws.nev;
+  double maxrho = 0.0;
+  for (int i = 0; i < nev; ++i) {
+    const double rho = std::sqrt(std::max(hr[2 * i], 0.0)) / (c->normA * std::sqrt(std::max(hr[2 * i + 1], 1e-300)));
+    maxrho = std::max(maxrho, std::isfinite(rho) ? rho : 1e300);
+  }
+  // gather sorted, c-normalised columns
+  std::vector<const c128*> srcs(nev);
+  std::vector<int64_t> lds(nev, nev);
+  std::vector<c128> scs(nev);
+  P.eps.resize(nev);
+  for (int i = 0; i < nev; ++i) {
+    srcs[i] = U.p + ord[i];
+    scs[i] = sc[ord[i]];
+    P.eps[i] = thc[ord[i]];
+  }
+  DevArr<const c128*> dsrc;
+  DevArr<int64_t> dld;
+  DevArr<c128> dsc;
+  dsrc.alloc(nev); dld.alloc(nev); dsc.alloc(nev);
+  check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nev, hipMemcpyHostToDevice, st), "srcs");
+  check(hipMemcpyAsync(dld.p, lds.data(), sizeof(int64_t) * nev, hipMemcpyHostToDevice, st), "lds");
+  check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nev, hipMemcpyHostToDevice, st), "sc");
+  P.U.alloc(size_t(N) * nev);
+  gather_columns(P.U.p, nev, dsrc.p, dld.p, dsc.p, nev, N, st);
+  check(hipStreamSynchronize(st), "sync");
+  P.stats.shift = ws.shift;
+  P.stats.nev = ws.nev;
+  P.stats.n_conv = o.converged ? nev : 0;
+  P.stats.restarts = o.restarts;
+  P.stats.matvecs = o.matvecs + nev;
+  P.stats.max_backward_error = maxrho;
+  P.stats.restarts_bulk = restarts_bulk;
+  return P;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ public
+void validate_build(const tsg_grid* g, const double* V, const tsg_absorber* ab) {
+  if (!g || !V || !ab) throw InvalidArg("null argument");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) throw InvalidArg("grid sizes must be >= 1");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) throw InvalidArg("h must be positive and finite");
+  const int R = g->fd_radius == 0 ? 6 : g->fd_radius;
+  if (R < 1 || R > 6) throw InvalidArg("fd_radius must be in 1..6");
+  const double vals[6] = {ab->amp_L, ab->width_L, ab->z_L, ab->amp_R, ab->width_R, ab->z_R};
+  for (double v : vals)
+    if (!std::isfinite(v)) throw InvalidArg("absorber parameters must be finite");
+  if (ab->amp_L < 0 || ab->amp_R < 0) throw InvalidArg("absorber amplitudes must be >= 0");
+  if (!(ab->width_L > 0) || !(ab->width_R > 0)) throw InvalidArg("absorber widths must be > 0");
+  const int64_t N = int64_t(g->nx) * g->ny * g->nz;
+  if (N > (int64_t(1) << 31)) throw InvalidArg("grid too large");
+  for (int64_t n = 0; n < N; ++n)
+    if (!std::isfinite(V[n])) throw InvalidArg("V contains a non-finite value at index " + std::to_string(n));
+}
+
+void build_context(tsg_ctx* c, const tsg_grid* g, const double* V, const tsg_absorber* ab, void* stream) {
+  validate_build(g, V, ab);
+  const int R = g->fd_radius == 0 ? 6 : g->fd_radius;
+  const int64_t N = int64_t(g->nx) * g->ny * g->nz;
+  double vmin = V[0], vmax = V[0], vabs = 0.0;
+  for (int64_t n = 0; n < N; ++n) {
+    vmin = std::min(vmin, V[n]);
+    vmax = std::max(vmax, V[n]);
+    vabs = std::max(vabs, std::fabs(V[n]));
+  }
+  int dev = 0;
+  check(hipGetDevice(&dev), "hipGetDevice");
+  c->nx = g->nx; c->ny = g->ny; c->nz = g->nz; c->R = R; c->h = g->h; c->N = N;
+  c->ab = *ab;
+  c->st = static_cast<hipStream_t>(stream);
+  const double s = -1.0 / (2.0 * g->h * g->h);
+  double c0 = 0.0, sabs = 0.0;
+  for (int m = 1; m <= R; ++m) {
+    const double cm = fd_coef(R, m);
+    c->coef[m] = s * cm;
+    c0 -= 2.0 * cm;
+    sabs += std::fabs(cm);
+  }
+  c->coef[0] = s * c0;
+  c->diag0 = 3.0 * s * c0;
+  std::vector<double> gL(g->nz), gR(g->nz), gam(g->nz);
+  double gmax = 0.0;
+  for (int k = 0; k < g->nz; ++k) {
+    const double z = k * g->h;
+    gL[k] = ab->amp_L * std::exp(-(z - ab->z_L) * (z - ab->z_L) / (2.0 * ab->width_L * ab->width_L));
+    gR[k] = ab->amp_R * std::exp(-(z - ab->z_R) * (z - ab->z_R) / (2.0 * ab->width_R * ab->width_R));
+    gam[k] = gL[k] + gR[k];
+    gmax = std::max(gmax, gam[k]);
+  }
+  c->normA = 3.0 * (std::fabs(c0) + 2.0 * sabs) / (2.0 * g->h * g->h) + vabs + gmax;
+  c->vmin = vmin; c->vmax = vmax; c->gmax = gmax;
+  c->V.alloc(N); c->Vf.alloc(N);
+  c->gam.alloc(g->nz); c->gamf.alloc(g->nz); c->gL.alloc(g->nz); c->gR.alloc(g->nz);
+  std::vector<float> Vf(V, V + N), gamf(gam.begin(), gam.end());
+  check(hipMemcpy(c->V.p, V, sizeof(double) * N, hipMemcpyHostToDevice), "upload V");
+  check(hipMemcpy(c->Vf.p, Vf.data(), sizeof(float) * N, hipMemcpyHostToDevice), "upload V");
+  check(hipMemcpy(c->gam.p, gam.data(), sizeof(double) * g->nz, hipMemcpyHostToDevice), "upload gamma");
+  check(hipMemcpy(c->gamf.p, gamf.data(), sizeof(float) * g->nz, hipMemcpyHostToDevice), "upload gamma");
+  check(hipMemcpy(c->gL.p, gL.data(), sizeof(double) * g->nz, hipMemcpyHostToDevice), "upload gamma");
+  check(hipMemcpy(c->gR.p, gR.data(), sizeof(double) * g->nz, hipMemcpyHostToDevice), "upload gamma");
+}
+
+void apply_operator(tsg_ctx* c, const void* X, void* Y, int ncols, int64_t ld, int dtype) {
+  if (!X || !Y) throw InvalidArg("null device pointer");
+  if (ncols < 1 || ld < ncols) throw InvalidArg("need 1 <= ncols <= ld");
+  if (dtype == TSG_C128) {
+    stencil<double>(c, static_cast<const c128*>(X), ld, 0, static_cast<c128*>(Y), ld, 0, ncols, 1, nullptr);
+  } else if (dtype == TSG_C64) {
+    stencil<float>(c, static_cast<const c64*>(X), ld, 0, static_cast<c64*>(Y), ld, 0, ncols, 1, nullptr);
+  } else {
+    throw InvalidArg("dtype must be TSG_C128 or TSG_C64");
+  }
+  check(hipGetLastError(), "stencil launch");
+}
+
+bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_opts& o) {
+  const int nw = int(wins.size());
+  if (nw < 1) throw InvalidArg("need at least one window");
+  int nvmax = 0;
+  for (const auto& w : wins) {
+    if (w.nev < 1) throw InvalidArg("nev must be >= 1");
+    if (!std::isfinite(w.shift)) throw InvalidArg("shift must be finite");
+    nvmax = std::max(nvmax, w.nev);
+  }
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) throw InvalidArg("tol must be positive");
+  if (o.max_restarts < 1) throw InvalidArg("max_restarts must be >= 1");
+  if (o.precision != TSG_FP64 && o.precision != TSG_FP32_BULK) throw InvalidArg("unknown precision");
+  if (o.select < 0 || o.select > 2) throw InvalidArg("unknown selection");
+  int m, k, b;
+  choose_sizes(c->N, nvmax, o, m, k, b);
+  if (int64_t(m) >= c->N) throw InvalidArg("grid too small for the basis size");
+  const int64_t N = c->N;
+  hipStream_t st = c->st;
+  c->have_combined = false;
+  c->have_grams = false;
+  std::vector<DevArr<c128>> results(nw);
+  std::vector<WinOut> outs;
+  std::vector<int> bulk_restarts(nw, 0);
+  std::vector<int64_t> bulk_mv(nw, 0);
+
+  if (o.precision == TSG_FP32_BULK) {
+    // complex64 phase to bulk_tol; keep [V_k | F] of each window for the FP64 phase
+    DevArr<c64> hand;
+    hand.alloc(size_t(N) * (k + b) * nw);
+    {
+      Batch<float> Bf;
+      Bf.alloc(nw, N, m, k, b, nvmax);
+      std::vector<WinOut> fo;
+      const double btol = std::max(o.bulk_tol > 0 ? o.bulk_tol : 1e-5, o.tol);
+      iterate<float>(c, Bf, wins, o.select, btol, o.max_restarts, o.seed, nullptr, fo, [&](int w) {
+        int one = w;
+        (void)one;
+        // V (already swapped) holds the kept basis in columns [0, k); F the continuation
+        check(hipMemcpy2DAsync(hand.p + size_t(w) * N * (k + b), sizeof(c64) * (k + b),
+                               Bf.V.p + size_t(w) * N * m, sizeof(c64) * m, sizeof(c64) * k, N,
+                               hipMemcpyDeviceToDevice, st), "handoff");
+        check(hipMemcpy2DAsync(hand.p + size_t(w) * N * (k + b) + k, sizeof(c64) * (k + b),
+                               Bf.F.p + size_t(w) * N * b, sizeof(c64) * b, sizeof(c64) * b, N,
+                               hipMemcpyDeviceToDevice, st), "handoff");
+      }, 100.0 * btol);
+      for (int w = 0; w < nw; ++w) { bulk_restarts[w] = fo[w].restarts; bulk_mv[w] = fo[w].matvecs; }
+    }
+    Batch<double> Bd;
+    Bd.alloc(nw, N, m, k, b, nvmax);
+    iterate<double>(c, Bd, wins, o.select, o.tol, o.max_restarts, o.seed + 1, hand.p, outs, [&](int w) {
+      results[w].alloc(size_t(N) * wins[w].nev);
+      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * wins[w].nev, Bd.V.p + size_t(w) * N * m + k,
+                             sizeof(c128) * m, sizeof(c128) * wins[w].nev, N, hipMemcpyDeviceToDevice, st),
+            "save");
+    });
+  } else {
+    Batch<double> Bd;
+    Bd.alloc(nw, N, m, k, b, nvmax);
+    iterate<double>(c, Bd, wins, o.select, o.tol, o.max_restarts, o.seed, nullptr, outs, [&](int w) {
+      results[w].alloc(size_t(N) * wins[w].nev);
+      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * wins[w].nev, Bd.V.p + size_t(w) * N * m + k,
+                             sizeof(c128) * m, sizeof(c128) * wins[w].nev, N, hipMemcpyDeviceToDevice, st),
+            "save");
+    });
+  }
+  check(hipStreamSynchronize(st), "sync");
+  bool all = true;
+  for (int w = 0; w < nw; ++w) {
+    outs[w].matvecs += bulk_mv[w];
+    Partition P = finish_window(c, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w]);
+    if (!outs[w].converged || P.stats.max_backward_error > o.tol) {
+      all = false;
+      P.stats.n_conv = 0;
+      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= o.tol;
+    }
+    c->parts.push_back(std::move(P));
+  }
+  return all;
+}
+
+void combine(tsg_ctx* c, int keep_lowest) {
+  const int p = int(c->parts.size());
+  if (p == 0) throw StateError("no partitions to combine");
+  const int64_t N = c->N;
+  hipStream_t st = c->st;
+  int total = 0;
+  for (auto& P : c->parts) total += int(P.eps.size());
+  const double tau = 1e-6 * c->normA;
+  DevArr<c128> Ucomb, v;
+  DevArr<double> out;
+  DevArr<int> partners;
+  Ucomb.alloc(size_t(N) * std::max(total, 1));
+  v.alloc(size_t(N));
+  out.alloc(4);
+  partners.alloc(size_t(std::max(total, 1)));
+  std::vector<c128> keps;
+  std::vector<int> kown;
+  std::vector<uint8_t> holes(std::max(p - 1, 0), 1);
+  // pending plain copies into Ucomb
+  std::vector<const c128*> psrc;
+  std::vector<int64_t> pld;
+  std::vector<c128> psc;
+  int pend_start = 0;
+  DevArr<const c128*> dsrc;
+  DevArr<int64_t> dld;
+  DevArr<c128> dsc;
+  dsrc.alloc(size_t(std::max(total, 1))); dld.alloc(size_t(std::max(total, 1))); dsc.alloc(size_t(std::max(total, 1)));
+  auto flush = [&]() {
+    const int n = int(psrc.size());
+    if (n == 0) return;
+    check(hipMemcpyAsync(dsrc.p, psrc.data(), sizeof(void*) * n, hipMemcpyHostToDevice, st), "srcs");
+    check(hipMemcpyAsync(dld.p, pld.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st), "lds");
+    check(hipMemcpyAsync(dsc.p, psc.data(), sizeof(c128) * n, hipMemcpyHostToDevice, st), "sc");
+    gather_columns(Ucomb.p + pend_start, total, dsrc.p, dld.p, dsc.p, n, N, st);
+    check(hipStreamSynchronize(st), "sync");
+    pend_start += n;
+    psrc.clear(); pld.clear(); psc.clear();
+  };
+  for (int j = 0; j < p; ++j) {
+    Partition& P = c->parts[j];
+    const int n = int(P.eps.size());
+    for (int i = 0; i < n; ++i) {
+      const c128 lam = P.eps[i];
+      std::vector<int> pt;
+      for (int q = 0; q < int(keps.size()); ++q)
+        if (cabs(keps[q] - lam) <= tau) pt.push_back(q);
+      if (pt.empty()) {
+        psrc.push_back(P.U.p + i);
+        pld.push_back(n);
+        psc.push_back(c128{1.0, 0.0});
+        keps.push_back(lam);
+        kown.push_back(j);
+        continue;
+      }
+      flush();
+      check(hipMemcpy2DAsync(v.p, sizeof(c128), P.U.p + i, sizeof(c128) * n, sizeof(c128), N,
+                             hipMemcpyDeviceToDevice, st), "copy v");
+      check(hipMemcpyAsync(partners.p, pt.data(), sizeof(int) * pt.size(), hipMemcpyHostToDevice, st), "partners");
+      project_out(v.p, Ucomb.p, total, partners.p, int(pt.size()), N, out.p, st);
+      double h[4];
+      check(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st), "norms");
+      check(hipStreamSynchronize(st), "sync");
+      if (h[1] < 1e-3 * h[0]) {
+        for (int q : pt) {
+          const int o = kown[q];
+          if (std::abs(o - j) == 1) holes[std::min(o, j)] = 0;
+        }
+        continue;
+      }
+      const c128 sc = cdiv(c128{1.0, 0.0}, csqrt(c128{h[2], h[3]}));
+      psrc.push_back(v.p);
+      pld.push_back(1);
+      psc.push_back(sc);
+      keps.push_back(lam);
+      kown.push_back(j);
+      flush();  // v is reused: materialise now
+    }
+  }
+  flush();
+  const int nk = int(keps.size());
+  std::vector<int> ord(nk);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (keps[a].re != keps[b].re) return keps[a].re < keps[b].re;
+    return keps[a].im < keps[b].im;
+  });
+  int nout = nk;
+  if (keep_lowest > 0 && keep_lowest < nk) nout = keep_lowest;
+  c->Uc.alloc(size_t(N) * std::max(nout, 1));
+  std::vector<const c128*> srcs(nout);
+  std::vector<int64_t> lds(nout, total);
+  std::vector<c128> scs(nout, c128{1.0, 0.0});
+  c->epsc.resize(nout);
+  c->ownerc.resize(nout);
+  for (int i = 0; i < nout; ++i) {
+    srcs[i] = Ucomb.p + ord[i];
+    c->epsc[i] = keps[ord[i]];
+    c->ownerc[i] = kown[ord[i]];
+  }
+  if (nout > 0) {
+    check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nout, hipMemcpyHostToDevice, st), "srcs");
+    check(hipMemcpyAsync(dld.p, lds.data(), sizeof(int64_t) * nout, hipMemcpyHostToDevice, st), "lds");
+    check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nout, hipMemcpyHostToDevice, st), "sc");
+    gather_columns(c->Uc.p, nout, dsrc.p, dld.p, dsc.p, nout, N, st);
+  }
+  check(hipStreamSynchronize(st), "sync");
+  c->nc = nout;
+  c->holes = holes;
+  c->have_combined = true;
+  c->have_grams = false;
+}
+
+void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
+                  double* e_range) {
+  if (n_r < 1 || p < 1) throw InvalidArg("need n_r >= 1 and p >= 1");
+  if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL) throw InvalidArg("unknown planning mode");
+  // two exterior eigenvalues (Section 2.2); solved as temporary partitions
+  const size_t keep_parts = c->parts.size();
+  tsg_opts oe = o;
+  oe.precision = TSG_FP64;
+  double ext[2];
+  for (int side = 0; side < 2; ++side) {
+    oe.select = side == 0 ? TSG_SELECT_SMALLEST_REAL : TSG_SELECT_LARGEST_REAL;
+    const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
+    const Partition& P = c->parts.back();
+    ext[side] = P.eps[0].re;
+    c->parts.resize(keep_parts);
+    if (!ok) throw StateError("exterior eigenvalue did not converge");
+  }
+  std::vector<int> counts(p);
+  if (mode == TSG_PLAN_EQUAL) {
+    const int base = n_r / p;
+    for (int j = 0; j < p; ++j) counts[j] = base + (j < n_r - base * p ? 1 : 0);
+  } else {
+    // Algorithm 1: n_{r,j} = round(2/(1.5 + (j-1)/p) n_r/p) for j <= p/2,
+    // ceil(2 n_r/p) - n_{r,p-j+1} otherwise (middle of odd p: half of it).
+    const long top = (2L * n_r + p - 1) / p;
+    for (int j = 1; j <= p; ++j) {
+      if (2 * j <= p) {
+        const double x = 2.0 / (1.5 + double(j - 1) / p) * double(n_r) / p;
+        counts[j - 1] = int(std::floor(x + 0.5));
+      }
+    }
+    for (int j = 1; j <= p; ++j) {
+      if (2 * j > p) {
+        const int mirror = p - j + 1;
+        counts[j - 1] = (mirror == j) ? int((top + 1) / 2) : int(top - counts[mirror - 1]);
+      }
+    }
+  }
+  const double delta = (ext[1] - ext[0]) / double(c->N);
+  out.resize(p);
+  double prev_s = ext[0];
+  int prev_n = 0;
+  for (int j = 0; j < p; ++j) {
+    const double s = prev_s + delta * (counts[j] + prev_n) / 2.0;
+    out[j] = WindowSpec{s, counts[j]};
+    prev_s = s;
+    prev_n = counts[j];
+  }
+  if (e_range) { e_range[0] = ext[0]; e_range[1] = ext[1]; }
+}
+
+void transmission(tsg_ctx* c, const double* E, int nE, double* T) {
+  if (!E || !T || nE < 1) throw InvalidArg("need energies and outputs, nE >= 1");
+  if (!c->have_combined) throw StateError("no combined eigenpairs: run a solve first");
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E[e])) throw InvalidArg("energies must be finite");
+  const int n = c->nc;
+  hipStream_t st = c->st;
+  if (n == 0) {
+    for (int e = 0; e < nE; ++e) T[e] = 0.0;
+    return;
+  }
+  if (!c->have_grams) {
+    const size_t nn = size_t(n) * n;
+    c->MR.alloc(nn); c->ML.alloc(nn); c->Wt.alloc(nn); c->epsd.alloc(n);
+    DevArr<c128> part;
+    part.alloc(size_t(gamma_gram_workspace(c->N, n)));
+    gamma_grams<double>(c->Uc.p, n, c->N, n, c->gL.p, c->gR.p, c->nx * c->ny, c->MR.p, c->ML.p, c->Wt.p, part.p, st);
+    check(hipMemcpyAsync(c->epsd.p, c->epsc.data(), sizeof(c128) * n, hipMemcpyHostToDevice, st), "eps");
+    check(hipStreamSynchronize(st), "sync");
+    c->have_grams = true;
+  }
+  DevArr<double> dE, dT;
+  dE.alloc(nE); dT.alloc(nE);
+  check(hipMemcpyAsync(dE.p, E, sizeof(double) * nE, hipMemcpyHostToDevice, st), "E");
+  transmission_sweep(c->Wt.p, n, c->epsd.p, dE.p, nE, dT.p, st);
+  check(hipMemcpyAsync(T, dT.p, sizeof(double) * nE, hipMemcpyDeviceToHost, st), "T");
+  check(hipStreamSynchronize(st), "sync");
+}
+
+void dense_eig(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st) {
+  if (!H || !theta || !Y || !info) throw InvalidArg("null device pointer");
+  if (m < 1 || batch < 1) throw InvalidArg("need m >= 1 and batch >= 1");
+  DevArr<c128> work;
+  work.alloc(size_t(smalleig_workspace(m)) * batch);
+  smalleig(static_cast<c128*>(H), int64_t(m) * m, m, static_cast<c128*>(theta), m, static_cast<c128*>(Y),
+           int64_t(m) * m, work.p, smalleig_workspace(m), info, batch, st);
+  check(hipStreamSynchronize(st), "sync");
+}
+
+}  // namespace tsg

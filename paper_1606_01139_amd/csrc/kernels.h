@@ -1,0 +1,116 @@
+// Internal kernel launchers of libtransec_gpu.  Not part of the C-ABI.
+#pragma once
+#include "tsg_common.h"
+
+namespace tsg {
+
+// ---------------------------------------------------------------- K1
+template <typename T> struct StencilArgs {
+  const cplx<T>* X; int64_t ldx, wsx;      // input block, row stride, window stride
+  cplx<T>* Y; int64_t ldy, wsy;            // output block
+  int ncols;                               // columns per window
+  int nx, ny, nz, radius, zchunk;
+  const T* V;                              // N, potential (precision T)
+  const T* gamma;                          // nz, Gamma_L + Gamma_R per plane
+  T diag0;                                 // 3 * (-c0 / (2 h^2))
+  T coef[7];                               // coef[m] = -c_m / (2 h^2)
+  const T* shifts;                         // per-window real shift, or null
+  const int* wmap;                         // launch slot -> window index, or null
+};
+template <typename T> void launch_stencil(const StencilArgs<T>& a, int nwin, hipStream_t s);
+
+// ---------------------------------------------------------------- dense
+// Batched tall-skinny products over the row index n < N.  Window w uses
+// X + w*wsx, etc.  All small matrices are FP64 complex, row-major.
+
+// C[w] (r x s, ldc) = X[w]^H Y[w] (rows 0..N-1), reduced deterministically.
+// `partials` holds `cap` c128 entries (at least nwin * r * s); the number of
+// row chunks is capped to fit.  gram_workspace() is a good size.
+template <typename TX, typename TY>
+void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy,
+          int64_t N, int r, int s, c128* C, int64_t ldc, int64_t wsc, int nwin, c128* partials, int64_t cap,
+          hipStream_t st, const int* wmap = nullptr);
+int64_t gram_workspace(int64_t N, int r, int s, int nwin);
+
+// Y[w] (N x s) = beta * Y[w] + alpha * X[w] (N x r) * B[w] (r x s, ldb).  Y must not alias X.
+template <typename T>
+void gemm_rows(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb,
+               cplx<T>* Y, int64_t ldy, int64_t wsy, int64_t N, int r, int s, double beta, int nwin,
+               hipStream_t st, const int* wmap = nullptr, double alpha = 1.0);
+
+// Per-column sums over rows of |AU - theta U|^2 and |U|^2 (FP64 partials,
+// reduced); out[w*s + j] = {res2, unorm2}.
+template <typename T>
+void residual_norms(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
+                    const c128* theta, int64_t wst, int64_t N, int s, int nwin, double* out, double* partials,
+                    int64_t cap, hipStream_t st, const int* wmap = nullptr);
+int64_t residual_workspace(int64_t N, int s, int nwin);
+
+// c-products u^T A u and u^T u of each column (unconjugated), FP64.
+template <typename T>
+void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
+           int64_t N, int s, int nwin, c128* out, double* partials, int64_t cap, hipStream_t st,
+           const int* wmap = nullptr);
+
+// Counter-based start vectors: real values uniform in [-1, 1) from a
+// 64-bit mix of (seed, window, row, column).
+template <typename T>
+void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, int nwin, uint64_t seed, hipStream_t st,
+                  const int* wmap = nullptr);
+
+// Y = X (columns), with precision conversion.
+template <typename TX, typename TY>
+void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy,
+                int64_t N, int s, int nwin, hipStream_t st, const int* wmap = nullptr);
+
+// Column scaling Y[:, j] *= scale[w*s + j] (complex FP64 factors).
+template <typename T>
+void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s, int nwin, hipStream_t st,
+                const int* wmap = nullptr);
+
+// Small per-window kernels on b x b Gram matrices (one workgroup per window):
+// G = R^H R (Cholesky), writes Rinv (upper triangular) and a breakdown flag.
+void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
+                  const int* wmap = nullptr);
+
+// ---------------------------------------------------------------- K4
+// Eigen-decomposition of general complex m x m matrices, one workgroup per
+// window.  H (row-major, ld m) is overwritten; theta gets the eigenvalues and
+// Y (row-major m x m) the unit-2-norm right eigenvectors (columns).
+// work must hold smalleig_workspace(m) c128 per window.
+void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, int64_t wsy, c128* work,
+              int64_t wsw, int* info, int nwin, hipStream_t st, const int* wmap = nullptr);
+int64_t smalleig_workspace(int m);
+// Schur form of upper Hessenberg H (in place) with Schur vectors accumulated
+// into Z (which holds the Hessenberg reduction's unitary on entry).
+void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta, int64_t wst, int* info, int nwin,
+                  hipStream_t st, const int* wmap);
+
+// Selection by |theta - sigma| (ties: Re, then Im) and restart basis:
+// out (m x (k + nev), row-major, ld = k + nev):
+//   columns [0, k): orthonormal basis of the k selected eigenvectors,
+//   columns [k, k + nev): the nev nearest eigenvectors (unit 2-norm).
+// theta_sel[w*(nev)] gets their eigenvalues (nearest first).
+void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const double* sigma,
+                    int mode, int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss,
+                    int nwin, hipStream_t st, const int* wmap = nullptr);
+
+// ---------------------------------------------------------------- K7/K8
+// Transmission: T[e] = Re sum_kl g_k conj(g_l) W_kl, g_k = 1/(E_e - eps_k).
+void transmission_sweep(const c128* W, int n, const c128* eps, const double* E, int nE, double* T,
+                        hipStream_t st);
+// M^X = U^T diag(gamma_X) conj(U) for X = L, R and W = M^R o M^L (Hadamard).
+template <typename T>
+void gamma_grams(const cplx<T>* U, int64_t ldu, int64_t N, int n, const double* gL, const double* gR,
+                 int plane, c128* MR, c128* ML, c128* W, c128* partials, hipStream_t st);
+int64_t gamma_gram_workspace(int64_t N, int n);
+
+// Combine (Algorithm 2): v -= U[:, m] (U[:, m]^T v) for each partner m in
+// order; out = {||v|| before, ||v|| after, Re v^T v, Im v^T v}.
+void project_out(c128* v, const c128* U, int64_t ldu, const int* partners, int np, int64_t N, double* out,
+                 hipStream_t st);
+// dst[:, j] = scale[j] * (column pointed to by srcs[j], row stride srcld[j]).
+void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const int64_t* srcld, const c128* scale, int n,
+                    int64_t N, hipStream_t st);
+
+}  // namespace tsg

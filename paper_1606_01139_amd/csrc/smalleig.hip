@@ -1,0 +1,273 @@
+// K4: eigenpairs of the small Rayleigh-Ritz matrix H (m x m, general complex,
+// FP64), one workgroup per window.
+//
+// The paper's solver (ARPACK, Section 2.1) extracts Ritz pairs from the
+// projected matrix with a dense QR algorithm; this is the same textbook route
+// (Golub & Van Loan, Matrix Computations, Ch. 7): Householder reduction to
+// upper Hessenberg form, the implicit single-shift complex QR iteration with
+// Wilkinson shifts and deflation (accumulating the Schur vectors), eigenvectors
+// of the triangular factor by back substitution, and back-transformation.
+//
+// Then select_restart orders the Ritz values by |theta - sigma| (the 'SM'
+// selection on the shifted operator, Eq. (3) and Section 2.1) and builds the
+// thick-restart basis.
+#include "kernels.h"
+
+namespace tsg {
+namespace {
+
+constexpr int kEigThreads = 512;
+
+__device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
+
+// Block-wide sum of doubles (blockDim.x == kEigThreads).
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int o = kEigThreads / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- Hessenberg
+__global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Zall,
+                                                                 int64_t wsz, const int* __restrict__ wmap) {
+  extern __shared__ c128 sm[];  // v[m], u[m]
+  __shared__ double red[kEigThreads];
+  c128* v = sm;
+  c128* u = sm + m;
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  c128* H = Hall + int64_t(w) * wsh;
+  c128* Z = Zall + int64_t(w) * wsz;
+  const int t = threadIdx.x;
+  for (int64_t e = t; e < int64_t(m) * m; e += kEigThreads) {
+    const int i = int(e / m), j = int(e % m);
+    Z[e] = c128{i == j ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    const int len = m - k - 1;  // rows k+1 .. m-1
+    double part = 0.0;
+    for (int i = t; i < len; i += kEigThreads) {
+      c128 x = H[int64_t(k + 1 + i) * m + k];
+      v[i] = x;
+      part += norm2(x);
+    }
+    const double alpha2 = block_sum(part, red);
+    const double alpha = sqrt(alpha2);
+    const c128 x0 = H[int64_t(k + 1) * m + k];
+    const double ax0 = cabs(x0);
+    // all threads agree on these scalars (same inputs)
+    double tailsq = alpha2 - ax0 * ax0;
+    if (alpha == 0.0 || tailsq <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) {
+      __syncthreads();
+      continue;  // already Hessenberg in this column
+    }
+    const c128 ph = ax0 > 0.0 ? c128{x0.re / ax0, x0.im / ax0} : c128{1.0, 0.0};
+    // v = x + ph * alpha e1; |v|^2 = 2 alpha (alpha + |x0|)
+    if (t == 0) v[0] = x0 + alpha * ph;
+    __syncthreads();
+    const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
+    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k
+    for (int j = k + t; j < m; j += kEigThreads) {
+      c128 s{0.0, 0.0};
+      for (int i = 0; i < len; ++i) fma_cacc(s, v[i], H[int64_t(k + 1 + i) * m + j]);
+      s = beta * s;
+      for (int i = 0; i < len; ++i) {
+        c128& h = H[int64_t(k + 1 + i) * m + j];
+        h = h - v[i] * s;
+      }
+    }
+    __syncthreads();
+    // right: H[i, k+1..] -= beta (H[i, k+1..] v) v^H for all rows; same on Z
+    for (int i = t; i < 2 * m; i += kEigThreads) {
+      c128* row = (i < m) ? (H + int64_t(i) * m) : (Z + int64_t(i - m) * m);
+      c128 s{0.0, 0.0};
+      for (int j = 0; j < len; ++j) fma_acc(s, row[k + 1 + j], v[j]);
+      s = beta * s;
+      for (int j = 0; j < len; ++j) {
+        c128& h = row[k + 1 + j];
+        h = h - s * conj(v[j]);
+      }
+    }
+    __syncthreads();
+    // exact zeros below the subdiagonal
+    for (int i = k + 2 + t; i < m; i += kEigThreads) H[int64_t(i) * m + k] = c128{0.0, 0.0};
+    __syncthreads();
+  }
+  (void)u;
+}
+
+// ---------------------------------------------------------------- vectors
+// X[:, j] = eigenvector of upper triangular T for T[j, j] (x_j = 1, x_i = 0 for i > j).
+__global__ void trevc_kernel(const c128* Tall, int64_t wst, int m, c128* Xall, int64_t wsx,
+                             const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const c128* T = Tall + int64_t(w) * wst;
+  c128* X = Xall + int64_t(w) * wsx;
+  const c128 lam = T[int64_t(j) * m + j];
+  double tnorm = 0.0;
+  for (int i = 0; i < m; ++i) tnorm = fmax(tnorm, cabs1(T[int64_t(i) * m + i]));
+  const double smin = fmax(2.220446049250313e-16 * tnorm, 1e-290);
+  for (int i = m - 1; i > j; --i) X[int64_t(i) * m + j] = c128{0.0, 0.0};
+  X[int64_t(j) * m + j] = c128{1.0, 0.0};
+  for (int i = j - 1; i >= 0; --i) {
+    c128 s{0.0, 0.0};
+    for (int p = i + 1; p <= j; ++p) fma_acc(s, T[int64_t(i) * m + p], X[int64_t(p) * m + j]);
+    c128 d = T[int64_t(i) * m + i] - lam;
+    if (cabs1(d) < smin) d = c128{smin, 0.0};
+    const c128 xi = cdiv(c128{-s.re, -s.im}, d);
+    X[int64_t(i) * m + j] = xi;
+    if (cabs1(xi) > 1e150) {  // rescale to keep the back substitution finite
+      for (int p = i; p <= j; ++p) X[int64_t(p) * m + j] = 1e-150 * X[int64_t(p) * m + j];
+    }
+  }
+}
+
+// Y = Z X (m x m, row-major, 16 x 16 tiles), then each column of Y is
+// normalised to unit 2-norm by colnorm_kernel.
+__global__ __launch_bounds__(256) void small_gemm_kernel(const c128* Zall, int64_t wsz, const c128* Xall,
+                                                         int64_t wsx, c128* Yall, int64_t wsy, int m,
+                                                         const int* __restrict__ wmap) {
+  __shared__ c128 As[16][17];
+  __shared__ c128 Bs[16][17];
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  const c128* Z = Zall + int64_t(w) * wsz;
+  const c128* X = Xall + int64_t(w) * wsx;
+  c128* Y = Yall + int64_t(w) * wsy;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  c128 acc{0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    As[ty][tx] = (i < m && k0 + tx < m) ? Z[int64_t(i) * m + k0 + tx] : c128{0.0, 0.0};
+    Bs[ty][tx] = (k0 + ty < m && j < m) ? X[int64_t(k0 + ty) * m + j] : c128{0.0, 0.0};
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) fma_acc(acc, As[ty][k], Bs[k][tx]);
+    __syncthreads();
+  }
+  if (i < m && j < m) Y[int64_t(i) * m + j] = acc;
+}
+
+__global__ void colnorm_kernel(c128* Yall, int64_t wsy, int m, const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  c128* Y = Yall + int64_t(w) * wsy;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += norm2(Y[int64_t(i) * m + j]);
+  const double f = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+  for (int i = 0; i < m; ++i) Y[int64_t(i) * m + j] = f * Y[int64_t(i) * m + j];
+}
+
+// ---------------------------------------------------------------- selection
+__device__ inline double sel_key(c128 th, double sigma, int mode) {
+  if (mode == 1) return th.re;        // smallest real part
+  if (mode == 2) return -th.re;       // largest real part
+  return cabs(c128{th.re - sigma, th.im});  // nearest the shift
+}
+
+__global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, int64_t wst, const c128* Yall,
+                                                             int64_t wsy, int m, const double* sigma, int mode, int k,
+                                                             int nev, c128* outall, int64_t wso, c128* thsel,
+                                                             int64_t wss, const int* __restrict__ wmap) {
+  extern __shared__ unsigned char smraw[];
+  int* order = reinterpret_cast<int*>(smraw);                       // m
+  c128* vec = reinterpret_cast<c128*>(smraw + ((m * sizeof(int) + 15) / 16) * 16);  // m
+  c128* coef = vec + m;                                              // k
+  __shared__ double red[256];
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  const c128* th = thall + int64_t(w) * wst;
+  const c128* Y = Yall + int64_t(w) * wsy;
+  c128* out = outall + int64_t(w) * wso;
+  const int ld = k + nev;
+  const double sg = sigma ? sigma[w] : 0.0;
+  const int t = threadIdx.x;
+  for (int i = t; i < m; i += 256) {
+    const double ki = sel_key(th[i], sg, mode);
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double kj = sel_key(th[j], sg, mode);
+      bool before = (kj < ki) || (kj == ki && (th[j].re < th[i].re || (th[j].re == th[i].re &&
+                    (th[j].im < th[i].im || (th[j].im == th[i].im && j < i)))));
+      rank += before ? 1 : 0;
+    }
+    order[rank] = i;
+  }
+  __syncthreads();
+  // nearest nev eigenvectors and their values
+  for (int q = 0; q < nev; ++q) {
+    const int src = order[q];
+    for (int i = t; i < m; i += 256) out[int64_t(i) * ld + k + q] = Y[int64_t(i) * m + src];
+    if (t == 0) thsel[int64_t(w) * wss + q] = th[src];
+  }
+  // orthonormal basis of the first k selected eigenvectors (CGS2)
+  for (int q = 0; q < k; ++q) {
+    const int src = order[q];
+    for (int i = t; i < m; i += 256) vec[i] = Y[int64_t(i) * m + src];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int p = t; p < q; p += 256) {
+        c128 s{0.0, 0.0};
+        for (int i = 0; i < m; ++i) fma_cacc(s, out[int64_t(i) * ld + p], vec[i]);
+        coef[p] = s;
+      }
+      __syncthreads();
+      for (int i = t; i < m; i += 256) {
+        c128 v = vec[i];
+        for (int p = 0; p < q; ++p) v = v - out[int64_t(i) * ld + p] * coef[p];
+        vec[i] = v;
+      }
+      __syncthreads();
+    }
+    double part = 0.0;
+    for (int i = t; i < m; i += 256) part += norm2(vec[i]);
+    red[t] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    __syncthreads();
+    const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = t; i < m; i += 256) out[int64_t(i) * ld + q] = f * vec[i];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int64_t smalleig_workspace(int m) { return 2 * int64_t(m) * m; }
+
+void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, int64_t wsy, c128* work, int64_t wsw,
+              int* info, int nwin, hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || m <= 0) return;
+  c128* Z = work;               // m*m per window at stride wsw
+  c128* X = work + int64_t(m) * m;
+  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), size_t(2 * m) * sizeof(c128), st, H, wsh, m,
+                     Z, wsw, wmap);
+  launch_schur(H, wsh, m, Z, wsw, theta, wst, info, nwin, st, wmap);
+  hipLaunchKernelGGL(trevc_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, H, wsh, m, X, wsw, wmap);
+  hipLaunchKernelGGL(small_gemm_kernel, dim3((m + 15) / 16, (m + 15) / 16, nwin), dim3(256), 0, st, Z, wsw, X, wsw,
+                     Y, wsy, m, wmap);
+  hipLaunchKernelGGL(colnorm_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, Y, wsy, m, wmap);
+}
+
+void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const double* sigma, int mode,
+                    int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss, int nwin, hipStream_t st,
+                    const int* wmap) {
+  if (nwin <= 0) return;
+  const size_t smem = ((m * sizeof(int) + 15) / 16) * 16 + size_t(m + k) * sizeof(c128);
+  hipLaunchKernelGGL(select_restart_kernel, dim3(nwin), dim3(256), smem, st, theta, wst, Y, wsy, m, sigma, mode, k,
+                     nev, out, wso, theta_sel, wss, wmap);
+}
+
+}  // namespace tsg

@@ -1,0 +1,367 @@
+// K4, QR phase: Schur form of an upper Hessenberg matrix (complex FP64),
+// one workgroup per window, accumulating the Schur vectors Z.
+//
+// The QR iteration (Golub & Van Loan, Matrix Computations, Sec. 7.5) is a
+// chain of dependent Givens rotations, so its speed on a GPU is set by the
+// latency of one rotation step.  Two paths:
+//   * block of at most kFin rows: the whole active block and its accumulated
+//     unitary live in LDS; single-shift (Wilkinson) sweeps with one barrier
+//     per rotation; then the unitary is applied to Z and to the parts of H
+//     outside the block as small matrix products;
+//   * larger blocks: multishift sweeps with a chain of bulges, three
+//     positions apart, chased together through global memory (Braman, Byers
+//     & Mathias, SIAM J. Matrix Anal. Appl. 23 (2002) 929), the shifts being
+//     the eigenvalues of the trailing block; rotations of different bulges
+//     touch disjoint row pairs (left) and column pairs (right), and left and
+//     right rotations commute, so each step applies all left rotations, then
+//     all right rotations.
+#include "kernels.h"
+
+namespace tsg {
+namespace {
+
+constexpr int kQT = 512;      // threads per workgroup
+constexpr int kFin = 64;      // largest block finished in LDS
+constexpr int kMaxShift = 64;
+
+__device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
+
+__device__ inline void givens(c128 x, c128 y, double& c, c128& s) {
+  // [c s; -conj(s) c] [x; y] = [r; 0], c real >= 0
+  const double ax = cabs(x), ay = cabs(y);
+  if (ay == 0.0) { c = 1.0; s = c128{0.0, 0.0}; return; }
+  if (ax == 0.0) { c = 0.0; s = c128{y.re / ay, -y.im / ay}; return; }
+  const double rho = hypot(ax, ay);
+  c = ax / rho;
+  s = (1.0 / rho) * (c128{x.re / ax, x.im / ax} * conj(y));
+}
+
+__device__ inline c128 wilkinson(c128 a, c128 b, c128 c2, c128 d) {
+  // eigenvalue of [[a b][c2 d]] closer to d
+  const c128 hd = 0.5 * (a - d);
+  const c128 disc = csqrt(hd * hd + b * c2);
+  const c128 mid = 0.5 * (a + d);
+  const c128 l1 = mid + disc, l2 = mid - disc;
+  return (cabs(l1 - d) <= cabs(l2 - d)) ? l1 : l2;
+}
+
+struct QRShared {
+  int lo, flag, iter;
+  double rc[2];
+  c128 rs[2];
+  c128 mu;
+  double red[kQT];
+  int ired[kQT];
+  c128 shift[kMaxShift];
+  double bc[kMaxShift];
+  c128 bs[kMaxShift];
+  int bp[kMaxShift];
+};
+
+// Single-shift QR on the n x n block B (LDS, row-major) until all its
+// eigenvalues are deflated, full Schur form of the block.  If Q is not null
+// the rotations are accumulated, Q <- Q G^H.  Returns false when the sweep
+// limit is hit.  All threads call it.
+__device__ bool lds_qr(c128* B, c128* Q, int n, QRShared& S) {
+  const int t = threadIdx.x;
+  const double ulp = 2.220446049250313e-16;
+  int ihi = n - 1;
+  int total = 0;
+  const int maxsweeps = 40 * n + 40;
+  if (t == 0) S.iter = 0;
+  __syncthreads();
+  while (ihi > 0) {
+    if (t == 0) {
+      int l = ihi;
+      while (l > 0) {
+        double tst = cabs1(B[(l - 1) * n + l - 1]) + cabs1(B[l * n + l]);
+        if (tst == 0.0) tst = 1.0;
+        if (cabs1(B[l * n + l - 1]) <= ulp * tst) break;
+        --l;
+      }
+      if (l > 0) B[l * n + l - 1] = c128{0.0, 0.0};
+      S.lo = l;
+      if (l < ihi) {
+        S.iter += 1;
+        c128 mu;
+        if (S.iter % 11 == 10) {
+          mu = B[ihi * n + ihi] + c128{0.75 * cabs1(B[ihi * n + ihi - 1]), 0.0};
+        } else {
+          mu = wilkinson(B[(ihi - 1) * n + ihi - 1], B[(ihi - 1) * n + ihi], B[ihi * n + ihi - 1], B[ihi * n + ihi]);
+        }
+        double c; c128 s;
+        givens(B[l * n + l] - mu, B[(l + 1) * n + l], c, s);
+        S.rc[0] = c;
+        S.rs[0] = s;
+      } else {
+        S.iter = 0;
+      }
+    }
+    __syncthreads();
+    const int l = S.lo;
+    if (l == ihi) { --ihi; continue; }
+    if (++total > maxsweeps) return false;
+    c128 bx{0.0, 0.0}, by{0.0, 0.0};  // thread 0: values the current rotation came from
+    for (int k = l; k < ihi; ++k) {
+      const int slot = (k - l) & 1;
+      const double c = S.rc[slot];
+      const c128 s = S.rs[slot];
+      const int imax = min(k + 2, ihi);
+      if (t == 0) {
+        // column k-1 (rows k, k+1): becomes (r, 0)
+        if (k > l) {
+          B[k * n + k - 1] = c * bx + s * by;
+          B[(k + 1) * n + k - 1] = c128{0.0, 0.0};
+        }
+        // 2 x 2 block rows k..k+1, cols k..k+1: left then right
+        c128 a = B[k * n + k], b = B[k * n + k + 1], cc = B[(k + 1) * n + k], d = B[(k + 1) * n + k + 1];
+        c128 a1 = c * a + s * cc, b1 = c * b + s * d;
+        c128 c1 = c * cc - conj(s) * a, d1 = c * d - conj(s) * b;
+        B[k * n + k] = c * a1 + conj(s) * b1;
+        B[k * n + k + 1] = c * b1 - s * a1;
+        const c128 nx = c * c1 + conj(s) * d1;
+        B[(k + 1) * n + k] = nx;
+        B[(k + 1) * n + k + 1] = c * d1 - s * c1;
+        // row k+2 (right rotation only): creates the bulge
+        if (k + 2 <= imax) {
+          const c128 e = B[(k + 2) * n + k], f = B[(k + 2) * n + k + 1];
+          const c128 ny = c * e + conj(s) * f;
+          B[(k + 2) * n + k] = ny;
+          B[(k + 2) * n + k + 1] = c * f - s * e;
+          if (k + 1 < ihi) {
+            double c2; c128 s2;
+            givens(nx, ny, c2, s2);
+            S.rc[slot ^ 1] = c2;
+            S.rs[slot ^ 1] = s2;
+            bx = nx;
+            by = ny;
+          }
+        }
+      } else {
+        // left: rows k, k+1, columns k+2 .. n-1
+        const int nl = n - (k + 2);
+        const int nr = k;  // right: rows 0 .. k-1 (rows k..k+2 are thread 0's)
+        const int nq = Q ? n : 0;
+        for (int it = t - 1; it < nl + nr + nq; it += kQT - 1) {
+          if (it < nl) {
+            const int j = k + 2 + it;
+            const c128 u = B[k * n + j], v = B[(k + 1) * n + j];
+            B[k * n + j] = c * u + s * v;
+            B[(k + 1) * n + j] = c * v - conj(s) * u;
+          } else if (it < nl + nr) {
+            const int i = it - nl;
+            const c128 u = B[i * n + k], v = B[i * n + k + 1];
+            B[i * n + k] = c * u + conj(s) * v;
+            B[i * n + k + 1] = c * v - s * u;
+          } else {
+            const int i = it - nl - nr;
+            const c128 u = Q[i * n + k], v = Q[i * n + k + 1];
+            Q[i * n + k] = c * u + conj(s) * v;
+            Q[i * n + k + 1] = c * v - s * u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
+// Y[rows, blk] = Y[rows, blk] Q for rows r0 <= r < r1 of a row-major matrix
+// with leading dimension ld; blk = [c0, c0+n).  Q in LDS (n x n).
+__device__ void apply_right(c128* Y, int64_t ld, int r0, int r1, int c0, const c128* Q, int n) {
+  const int t = threadIdx.x;
+  const int per = max(1, kQT / n);  // rows per pass
+  for (int rb = r0; rb < r1; rb += per) {
+    const int r = rb + t / n, j = t % n;
+    c128 acc{0.0, 0.0};
+    const bool ok = (t < per * n) && r < r1;
+    if (ok) {
+      const c128* row = Y + int64_t(r) * ld + c0;
+      for (int p = 0; p < n; ++p) fma_acc(acc, row[p], Q[p * n + j]);
+    }
+    __syncthreads();
+    if (ok) Y[int64_t(r) * ld + c0 + j] = acc;
+    __syncthreads();
+  }
+}
+
+// Y[blk, cols] = Q^H Y[blk, cols] for columns c0 <= col < c1; blk = [r0, r0+n).
+__device__ void apply_left(c128* Y, int64_t ld, int r0, int c0, int c1, const c128* Q, int n) {
+  const int t = threadIdx.x;
+  const int per = max(1, kQT / n);
+  for (int cb = c0; cb < c1; cb += per) {
+    const int col = cb + t / n, i = t % n;
+    c128 acc{0.0, 0.0};
+    const bool ok = (t < per * n) && col < c1;
+    if (ok) {
+      for (int p = 0; p < n; ++p) fma_cacc(acc, Q[p * n + i], Y[int64_t(r0 + p) * ld + col]);
+    }
+    __syncthreads();
+    if (ok) Y[int64_t(r0 + i) * ld + col] = acc;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
+                                                    c128* theta, int64_t wst, int* info, const int* __restrict__ wmap) {
+  extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
+  __shared__ QRShared S;
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  c128* H = Hall + int64_t(w) * wsh;
+  c128* Z = Zall + int64_t(w) * wsz;
+  c128* th = theta + int64_t(w) * wst;
+  const int t = threadIdx.x;
+  const double ulp = 2.220446049250313e-16;
+  int ihi = m - 1;
+  int sweeps = 0;
+  const int maxsweeps = 20 * m + 20;
+  bool failed = false;
+  while (ihi >= 0) {
+    // deflation scan: largest l in (0, ihi] with a negligible subdiagonal
+    int best = 0;
+    for (int l = 1 + t; l <= ihi; l += kQT) {
+      double tst = cabs1(H[int64_t(l - 1) * m + l - 1]) + cabs1(H[int64_t(l) * m + l]);
+      if (tst == 0.0) tst = 1.0;
+      if (cabs1(H[int64_t(l) * m + l - 1]) <= ulp * tst) best = max(best, l);
+    }
+    S.ired[t] = best;
+    __syncthreads();
+    for (int o = kQT / 2; o > 0; o >>= 1) {
+      if (t < o) S.ired[t] = max(S.ired[t], S.ired[t + o]);
+      __syncthreads();
+    }
+    const int lo = S.ired[0];
+    __syncthreads();
+    if (lo > 0 && t == 0) H[int64_t(lo) * m + lo - 1] = c128{0.0, 0.0};
+    const int n = ihi - lo + 1;
+    if (n == 1) {
+      if (t == 0) th[ihi] = H[int64_t(ihi) * m + ihi];
+      ihi -= 1;
+      __syncthreads();
+      continue;
+    }
+    if (n <= kFin) {
+      // finish the block in LDS
+      c128* B = lds;
+      c128* Q = lds + kFin * kFin;
+      for (int e = t; e < n * n; e += kQT) {
+        const int i = e / n, j = e % n;
+        B[e] = H[int64_t(lo + i) * m + lo + j];
+        Q[e] = c128{i == j ? 1.0 : 0.0, 0.0};
+      }
+      __syncthreads();
+      const bool ok = lds_qr(B, Q, n, S);
+      if (!ok) failed = true;
+      for (int e = t; e < n * n; e += kQT) {
+        const int i = e / n, j = e % n;
+        H[int64_t(lo + i) * m + lo + j] = B[e];
+      }
+      for (int i = t; i < n; i += kQT) th[lo + i] = B[i * n + i];
+      __syncthreads();
+      apply_right(Z, m, 0, m, lo, Q, n);
+      apply_right(H, m, 0, lo, lo, Q, n);
+      apply_left(H, m, lo, ihi + 1, m, Q, n);
+      ihi = lo - 1;
+      __syncthreads();
+      continue;
+    }
+    if (++sweeps > maxsweeps) { failed = true; break; }
+    // shifts: eigenvalues of the trailing ns x ns block (in LDS)
+    const int ns = min(kMaxShift, max(2, n / 2));
+    {
+      c128* B = lds;
+      const int b0 = ihi - ns + 1;
+      for (int e = t; e < ns * ns; e += kQT) {
+        const int i = e / ns, j = e % ns;
+        B[e] = H[int64_t(b0 + i) * m + b0 + j];
+      }
+      __syncthreads();
+      const bool ok = lds_qr(B, nullptr, ns, S);
+      if (t < ns) S.shift[t] = ok ? B[t * ns + t] : H[int64_t(b0 + t) * m + b0 + t];
+      if (t == 0 && sweeps % 6 == 5) {
+        // occasional exceptional shift against stagnation
+        S.shift[0] = H[int64_t(ihi) * m + ihi] + c128{0.75 * cabs1(H[int64_t(ihi) * m + ihi - 1]), 0.0};
+      }
+      __syncthreads();
+    }
+    // pipelined chase: bulge j sits at position lo + step - 3 j
+    const int nsteps = (ihi - lo) + 3 * (ns - 1);
+    for (int step = 0; step < nsteps; ++step) {
+      if (t < ns) {
+        const int p = lo + step - 3 * t;
+        if (p >= lo && p < ihi) {
+          c128 x, y;
+          if (p == lo) {
+            x = H[int64_t(lo) * m + lo] - S.shift[t];
+            y = H[int64_t(lo + 1) * m + lo];
+          } else {
+            x = H[int64_t(p) * m + p - 1];
+            y = H[int64_t(p + 1) * m + p - 1];
+          }
+          double c; c128 s;
+          givens(x, y, c, s);
+          S.bc[t] = c;
+          S.bs[t] = s;
+          S.bp[t] = p;
+        } else {
+          S.bp[t] = -1;
+        }
+      }
+      __syncthreads();
+      // all left rotations: rows p, p+1, columns from max(p-1, lo) to m-1
+      for (int j = 0; j < ns; ++j) {
+        const int p = S.bp[j];
+        if (p < 0) continue;
+        const double c = S.bc[j];
+        const c128 s = S.bs[j];
+        const int c0 = (p > lo) ? p - 1 : lo;
+        for (int col = c0 + t; col < m; col += kQT) {
+          c128* u = H + int64_t(p) * m + col;
+          c128* v = H + int64_t(p + 1) * m + col;
+          const c128 a = *u, b = *v;
+          *u = c * a + s * b;
+          *v = (col == p - 1) ? c128{0.0, 0.0} : c * b - conj(s) * a;
+        }
+      }
+      __syncthreads();
+      // all right rotations: columns p, p+1 for rows 0..min(p+2, ihi), and Z
+      for (int j = 0; j < ns; ++j) {
+        const int p = S.bp[j];
+        if (p < 0) continue;
+        const double c = S.bc[j];
+        const c128 s = S.bs[j];
+        const int rmax = min(p + 2, ihi);
+        for (int r = t; r <= rmax + m; r += kQT) {
+          c128* row = (r <= rmax) ? (H + int64_t(r) * m) : (Z + int64_t(r - rmax - 1) * m);
+          const c128 a = row[p], b = row[p + 1];
+          row[p] = c * a + conj(s) * b;
+          row[p + 1] = c * b - s * a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) info[w] = failed ? max(ihi + 1, 1) : 0;
+  if (failed) {
+    for (int i = t; i <= ihi; i += kQT) th[i] = H[int64_t(i) * m + i];
+  }
+}
+
+}  // namespace
+
+size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
+
+void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta, int64_t wst, int* info, int nwin,
+                  hipStream_t st, const int* wmap) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(schur_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(schur_lds_bytes()));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, theta, wst,
+                     info, wmap);
+}
+
+}  // namespace tsg

@@ -1,0 +1,87 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/transec_gpu.h declares, and rejects bad host arguments before
+touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1606_01139_amd as p
+    from paper_1606_01139_amd import build
+    if not os.path.exists(build.library_path()):
+        build.build(verbose=False)
+    p.load()
+    return p
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "transec_gpu.h")).read()
+    return sorted(set(re.findall(r"\b(tsg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_what_binding_lists(pkg):
+    assert sorted(pkg.EXPORTS) == _header_functions()
+
+
+def test_library_exports_every_declared_symbol(pkg):
+    lib = pkg.load()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_opts(pkg):
+    o = pkg.default_opts()
+    assert o.tol == 1e-8 and o.block == 16 and o.precision == pkg.FP64 and o.max_restarts > 0
+    assert o.bulk_tol == 1e-5 and o.select == pkg.SELECT_NEAREST
+
+
+@pytest.mark.parametrize("bad", ["nan_V", "inf_V", "neg_width", "zero_h", "radius7", "neg_amp", "zero_nx"])
+def test_build_rejects_bad_arguments(pkg, bad):
+    nx = ny = nz = 4
+    V = np.zeros(nx * ny * nz)
+    ab = [0.5, 2.0, 0.0, 0.5, 2.0, 1.5]
+    h, R = 0.5, 6
+    if bad == "nan_V":
+        V[5] = np.nan
+    elif bad == "inf_V":
+        V[0] = np.inf
+    elif bad == "neg_width":
+        ab[1] = -1.0
+    elif bad == "zero_h":
+        h = 0.0
+    elif bad == "radius7":
+        R = 7
+    elif bad == "neg_amp":
+        ab[3] = -0.1
+    elif bad == "zero_nx":
+        nx = 0
+        V = np.zeros(ny * nz)
+    with pytest.raises(pkg.TsgError) as e:
+        pkg.Operator(nx, ny, nz, h, V, ab, fd_radius=R)
+    assert e.value.status == 1  # TSG_EINVAL
+
+
+def test_null_context_calls_fail_cleanly(pkg):
+    import ctypes as C
+    lib = pkg.load()
+    n = C.c_int32()
+    assert lib.tsg_get_eigenvalues(None, None, 0, C.byref(n)) == 1
+    assert lib.tsg_transmission(None, None, 0, None) == 1
+    assert lib.tsg_combine(None, 0, None, None) == 1
+    assert b"NULL" in lib.tsg_last_error(None) or len(lib.tsg_last_error(None)) > 0
+    lib.tsg_destroy(None)  # NULL-safe
+
+
+def test_no_device_reports_edevice(pkg):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(pkg.TsgError) as e:
+        pkg.Operator(4, 4, 4, 0.5, np.zeros(64), [0.5, 2.0, 0.0, 0.5, 2.0, 1.5])
+    assert e.value.status == 5  # TSG_EDEVICE: no CPU fallback exists

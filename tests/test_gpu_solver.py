@@ -1,0 +1,142 @@
+"""GPU parity of the partitioned solve, combine and T(E) against the oracle.
+
+Tolerances (stated in the workload description): eigenvalues to
+1e-10 relative (|d eps| <= 1e-10 max(|eps|, 1 Ha)) in FP64; T(E) to 1e-6
+absolute; every eigenpair at backward error <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(w):
+    from oracle import operator as op, eigen
+    g = w.grid
+    ab = w.absorber.as_tuple()
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    A = op.assemble_dense(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    ea, Ua = eigen.dense_spectrum(A)
+    nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
+    return A, gL, gR, ea, Ua, nrm
+
+
+def _match_sets(got, ref, tol_rel):
+    assert len(got) == len(ref), (len(got), len(ref))
+    d = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    assert d.max() <= tol_rel, d.max()
+
+
+def _vector_tol(eps_all, eps_set, nrm, tol=1e-8):
+    # An eigenpair with backward error rho has ||A u - theta u|| <= rho ||A|| ||u||,
+    # so its vector is fixed only to about rho ||A|| / gap (gap to the nearest
+    # other eigenvalue of A); the check allows that with a factor 10.
+    gaps = [np.sort(np.abs(eps_all - e))[1] for e in eps_set]
+    return 10.0 * tol * nrm / min(gaps)
+
+
+def _check_vectors(U, Uref, A, eps, nrm, eps_all):
+    # c-normalised, bi-orthogonal, sign-free match, backward error
+    n = U.shape[1]
+    vt = _vector_tol(eps_all, eps, nrm)
+    np.testing.assert_allclose(np.diag(U.T @ U), np.ones(n), atol=1e-12)
+    np.testing.assert_allclose(U.T @ U, np.eye(n), atol=2 * vt)
+    for k in range(n):
+        dk = min(np.linalg.norm(U[:, k] - Uref[:, k]), np.linalg.norm(U[:, k] + Uref[:, k]))
+        assert dk <= vt, (k, dk, vt)
+        r = A @ U[:, k] - eps[k] * U[:, k]
+        assert np.linalg.norm(r) / (nrm * np.linalg.norm(U[:, k])) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c1_partitioned_solve_and_transmission(torch_cuda, precision):
+    from oracle import eigen, partition, transport
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import workload
+    print(f"c1 solve precision={precision}", flush=True)
+    w = workload("c1")
+    g = w.grid
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    # windows at the midpoints of two consecutive intervals of 20 eigenvalues
+    shifts = [0.5 * (ea[0].real + ea[19].real), 0.5 * (ea[20].real + ea[39].real)]
+    nev = w.nev_per_window
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    n, holes, _ = oper.solve_all_partitions([(s, nev) for s in shifts], default_opts(precision=precision))
+    ref = partition.combine([eigen.window_from_spectrum(ea, Ua, s, nev) for s in shifts], nrm)
+    eps = oper.eigenvalues()
+    _match_sets(eps, ref.eps, 1e-10)
+    assert holes == [bool(x) for x in ref.holes]
+    U = oper.eigenvectors().cpu().numpy()
+    _check_vectors(U, ref.U, A, eps, nrm, ea)
+    for j in range(2):
+        st = oper.stats(j)
+        assert st.n_conv == nev and st.max_backward_error <= 1e-8
+    E = transport.energy_grid(ref.eps, w.n_energies)
+    T = oper.transmission(E)
+    Tref = transport.transmission_spectral(ref.eps, ref.U, gL, gR, E)
+    assert np.abs(T - Tref).max() <= 1e-6
+    assert (T >= -1e-12).all()
+    oper.close()
+
+
+def test_single_partition_ragged_grid(torch_cuda):
+    from oracle import eigen
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import small_workload
+    w = small_workload(9, 7, 13, 3, seed=17)
+    g = w.grid
+    print("ragged single partition 9x7x13", flush=True)
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    sigma = float(ea[11].real) + 0.01
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    nconv = oper.solve_partition(sigma, 7, default_opts(basis=64, keep=32))
+    assert nconv == 7
+    eps, Ud = oper.partition(0)
+    e_ref, U_ref = eigen.window_from_spectrum(ea, Ua, sigma, 7)
+    _match_sets(eps, e_ref, 1e-10)
+    _check_vectors(Ud.cpu().numpy(), U_ref, A, eps, nrm, ea)
+    oper.close()
+
+
+def test_duplicate_windows_are_removed(torch_cuda):
+    from oracle import eigen, partition
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import small_workload
+    w = small_workload(8, 8, 12, 3, seed=4)
+    g = w.grid
+    print("duplicate windows", flush=True)
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    s = float(ea[6].real)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    n, holes, _ = oper.solve_all_partitions([(s, 6), (s, 6)], default_opts())
+    assert n == 6 and holes == [False]
+    e_ref, _ = eigen.window_from_spectrum(ea, Ua, s, 6)
+    _match_sets(oper.eigenvalues(), e_ref, 1e-10)
+    oper.close()
+
+
+def test_planner_matches_oracle(torch_cuda):
+    from oracle import partition, eigen
+    from paper_1606_01139_amd import Operator, PLAN_ALG1, PLAN_EQUAL
+    from synth.workloads import workload
+    w = workload("c1")
+    g = w.grid
+    print("planner c1", flush=True)
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    for mode, counts in ((PLAN_EQUAL, partition.equal_counts(40, 2)), (PLAN_ALG1, partition.alg1_counts(40, 2))):
+        wins, (emin, emax) = oper.plan_windows(40, 2, mode)
+        assert abs(emin - ea.real.min()) <= 1e-9 * max(abs(emin), 1.0)
+        assert abs(emax - ea.real.max()) <= 1e-9 * max(abs(emax), 1.0)
+        shifts = partition.alg1_shifts(counts, ea.real.min(), ea.real.max(), g.n)
+        assert [n for _, n in wins] == counts
+        np.testing.assert_allclose([s for s, _ in wins], shifts, rtol=0, atol=1e-9)
+    oper.close()
