@@ -30,11 +30,13 @@ def energy_grid(eps, n):
     return np.linspace(re.min(), re.max(), n) if n > 1 else np.array([re.mean()])
 
 
-def run_step(w, prec_code, n_r, p, opts, max_windows=None):
-    from paper_1606_01139_amd import Operator, PLAN_EQUAL
+def run_step(w, prec_code, n_r, p, opts, max_windows=None, plan="sampled"):
+    from paper_1606_01139_amd import Operator, PLAN_EQUAL, PLAN_SAMPLED
     g = w.grid
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
-    wins, erange = oper.plan_windows(n_r, p, PLAN_EQUAL, opts)
+    t0 = time.perf_counter()
+    wins, erange = oper.plan_windows(n_r, p, PLAN_SAMPLED if plan == "sampled" else PLAN_EQUAL, opts)
+    oper.plan_seconds = time.perf_counter() - t0
     if max_windows:
         wins = wins[:max_windows]
     n, holes, status = oper.solve_all_partitions(wins, opts, allow_noconv=True)
@@ -109,6 +111,8 @@ def main():
     ap.add_argument("--precision", default="bulk", choices=["fp64", "bulk"])
     ap.add_argument("--max-restarts", type=int, default=2000)
     ap.add_argument("--max-windows", type=int, default=0)
+    ap.add_argument("--plan", default="sampled", choices=["sampled", "alg1"])
+    ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
@@ -127,9 +131,11 @@ def main():
     n_r = p * nev
     prec = FP64 if args.precision == "fp64" else FP32_BULK
     opts = default_opts(precision=prec, tol=1e-8, max_restarts=args.max_restarts)
+    if args.block:
+        opts.block = args.block
     for i in range(args.warmup):
         t = time.perf_counter()
-        r = run_step(w, prec, n_r, p, opts, args.max_windows or None)
+        r = run_step(w, prec, n_r, p, opts, args.max_windows or None, args.plan)
         torch.cuda.synchronize()
         if args.verbose:
             print(f"warmup {i}: {time.perf_counter() - t:.2f} s, n={r[1]}", file=sys.stderr, flush=True)
@@ -139,7 +145,7 @@ def main():
     total = 0
     last = None
     for i in range(args.steps):
-        r = run_step(w, prec, n_r, p, opts, args.max_windows or None)
+        r = run_step(w, prec, n_r, p, opts, args.max_windows or None, args.plan)
         total += r[1]
         if last is not None:
             last[0].close()
@@ -150,7 +156,7 @@ def main():
     dt = time.perf_counter() - t0
     oper, n, holes, status, wins, erange, stats, T = last
     ms = dt / args.steps * 1e3
-    b = 16
+    b = opts.block
     roof = stencil_roofline(w, b * len(wins), "c64" if prec == FP32_BULK else "c128")
     out = {
         "metric": "converged eigenpairs/s at rel. residual 1e-8",
@@ -169,7 +175,9 @@ def main():
                                f"{len(w.wells)} Gaussian wells, {len(wins)} windows x {nev} eigenpairs, "
                                f"T(E) at {w.n_energies} energies",
                    "precision": args.precision, "unique_eigenpairs": n, "holes": holes,
-                   "status": int(status), "e_range": [round(x, 6) for x in erange]},
+                   "status": int(status), "e_range": [round(x, 6) for x in erange],
+                   "planner": args.plan, "plan_seconds_last_step": round(oper.plan_seconds, 3),
+                   "block": opts.block},
         "roofline": roof,
         "windows": [{"shift": round(s.shift, 6), "nev": s.nev, "n_conv": s.n_conv, "restarts": s.restarts,
                      "restarts_bulk": s.restarts_bulk, "matvecs": s.matvecs,

@@ -44,7 +44,7 @@ typedef enum {
 } tsg_status;
 
 enum { TSG_FP64 = 0, TSG_FP32_BULK = 1 };                 /* tsg_opts.precision */
-enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1 };           /* tsg_plan_windows mode */
+enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1, TSG_PLAN_SAMPLED = 2 }; /* tsg_plan_windows mode */
 enum { TSG_SELECT_NEAREST = 0, TSG_SELECT_SMALLEST_REAL = 1, TSG_SELECT_LARGEST_REAL = 2 };
 enum { TSG_C128 = 0, TSG_C64 = 1 };                       /* element types of device blocks */
 
@@ -76,7 +76,7 @@ typedef struct {
 typedef struct {
   int32_t precision;    /* TSG_FP64, or TSG_FP32_BULK: complex64 block work then an FP64 polish */
   double tol;           /* backward error ||A u - theta u|| / (||A||_G ||u||) to reach (default 1e-8) */
-  int32_t block;        /* vectors per block step b (default 16) */
+  int32_t block;        /* vectors per block step b (default 2) */
   int32_t basis;        /* basis size m per window (0: automatic, about 6 n_{r,j}) */
   int32_t keep;         /* vectors kept at a restart k (0: automatic, about m/2) */
   int32_t max_restarts; /* per window (default 2000) */
@@ -110,15 +110,23 @@ void tsg_default_opts(tsg_opts* opts);
 tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab,
                               void* hip_stream, tsg_ctx** out);
 
-/* Algorithm 1, first part (Section 2.2): estimates the extremal real parts
- * E_min, E_max with two exterior solves (one eigenpair of smallest and of
- * largest real part), then n_{r,j} (mode TSG_PLAN_ALG1: the load-balancing
- * formula; TSG_PLAN_EQUAL: n_r/p each) and the shifts
- *   E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N)(n_{r,j} + n_{r,j-1})/2,
- * with E_{S,0} = E_min and n_{r,0} = 0.
+/* Algorithm 1, first part (Section 2.2).  E_min is the real part of the
+ * eigenvalue of smallest real part (an exterior solve); E_max is the exact
+ * upper bound max V + 3 max|symbol|/(2h^2) on the real parts.  Modes:
+ *   TSG_PLAN_ALG1:    n_{r,j} from the load-balancing formula and
+ *                     E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N)(n_{r,j} + n_{r,j-1})/2,
+ *                     with E_{S,0} = E_min and n_{r,0} = 0;
+ *   TSG_PLAN_EQUAL:   the same shifts with n_{r,j} = n_r/p;
+ *   TSG_PLAN_SAMPLED: n_{r,j} = n_r/p; the local eigenvalue density is
+ *                     sampled by solving 8 eigenpairs at each of max(2p, 8)
+ *                     shifts (Section 2.2's density estimate) and the shifts
+ *                     are the midpoints of consecutive intervals of n_{r,j}
+ *                     eigenvalues of the integrated density.
  *   out:     host, capacity p windows;
  *   e_range: host, 2 doubles {E_min, E_max}, or NULL.
- * Errors: TSG_EINVAL (n_r < 1, p < 1), TSG_ENOCONV, TSG_EDEVICE. */
+ * Errors: TSG_EINVAL (n_r < 1, p < 1, mode), TSG_ESTATE (no convergence),
+ * TSG_EDEVICE.  Stored partitions are left unchanged; a combined set is
+ * discarded. */
 tsg_status tsg_plan_windows(tsg_ctx* ctx, int32_t n_r, int32_t p, int32_t mode, const tsg_opts* opts,
                             tsg_window* out, double* e_range);
 

@@ -17,7 +17,20 @@ Readings where the paper is silent or garbled:
     and kept pairs are c-normalised (u^T u = 1) rather than scaled by |v_k|,
     because the transport formula needs U^T U = I;
   * the garbled flag index holes_{k-1} is read as the interface between the
-    partitions that own lambda_m and lambda_k, when they are adjacent.
+    partitions that own lambda_m and lambda_k, when they are adjacent;
+  * E_max (Algorithm 1's upper extremal eigenvalue) is taken as the exact
+    upper bound on the real parts, max V + 3 max|symbol| / (2 h^2), instead of
+    a second exterior solve: Re eps = u^H (K + V) u / u^H u lies below it;
+  * density sampling (Section 2.2, "a few eigenpairs at several sample
+    points") is read as: 8 eigenpairs nearest each of S = max(2p, 8) shifts
+    spread evenly over [E_min, top], each giving a local density
+    (8 - 1)/(spread of their real parts) at the mean of their real parts;
+    the piecewise-linear density is integrated from E_min into a counting
+    function, and window j is centred between the points where it reaches
+    n_{r,1} + ... + n_{r,j-1} and n_{r,1} + ... + n_{r,j} (the interval
+    midpoints of Section 3); beyond the last sample the last density is
+    extended.  The region's top is guessed from the free-particle counting
+    function of the box (Weyl's law), which only decides where to sample.
 """
 from __future__ import annotations
 
@@ -68,6 +81,48 @@ def alg1_shifts(counts: Sequence[int], e_min: float, e_max: float, n: int) -> Li
         s = prev_s + delta * (c + prev_n) / 2.0
         shifts.append(s)
         prev_s, prev_n = s, c
+    return shifts
+
+
+def sample_shifts(e_min: float, n_r: int, p: int, box_lengths, n_samples: int = 0) -> List[float]:
+    """Sample shifts of the density-sampling planner (see module notes)."""
+    lx, ly, lz = box_lengths
+    kf = (6.0 * math.pi ** 2 * n_r / (lx * ly * lz)) ** (1.0 / 3.0)
+    top = max(0.5 * kf * kf, 0.0)
+    top = max(top, e_min + 0.25) * 1.25 + 0.25 * abs(e_min)
+    S = n_samples or max(2 * p, 8)
+    return [e_min + (top - e_min) * (i + 0.5) / S for i in range(S)]
+
+
+def sampled_windows(e_min: float, samples: Sequence[np.ndarray], counts: Sequence[int]) -> List[float]:
+    """Window shifts from sampled eigenvalues (each entry: the eigenvalues
+    nearest one sample shift)."""
+    pc = [e_min]
+    rho = [0.0]
+    for ev in samples:
+        re = np.sort(np.asarray(ev).real)
+        pc.append(float(re.mean()))
+        rho.append((len(re) - 1) / max(float(re[-1] - re[0]), 1e-12))
+    rho[0] = rho[1]
+    order = sorted(range(len(pc)), key=lambda i: pc[i])
+    xs = [pc[order[0]]]
+    cum = [0.0]
+    for q in range(1, len(order)):
+        x0, x1 = pc[order[q - 1]], pc[order[q]]
+        xs.append(x1)
+        cum.append(cum[-1] + 0.5 * (rho[order[q - 1]] + rho[order[q]]) * (x1 - x0))
+
+    def inverse(target):
+        for q in range(1, len(xs)):
+            if cum[q] >= target:
+                f = (target - cum[q - 1]) / max(cum[q] - cum[q - 1], 1e-300)
+                return xs[q - 1] + f * (xs[q] - xs[q - 1])
+        return xs[-1] + (target - cum[-1]) / max(rho[order[-1]], 1e-12)
+
+    shifts, acc = [], 0.0
+    for c in counts:
+        shifts.append(0.5 * (inverse(acc) + inverse(acc + c)))
+        acc += c
     return shifts
 
 

@@ -71,7 +71,7 @@ void tsg_default_opts(tsg_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = TSG_FP64;
   o->tol = 1e-8;
-  o->block = 16;
+  o->block = 2;
   o->basis = 0;
   o->keep = 0;
   o->max_restarts = 2000;

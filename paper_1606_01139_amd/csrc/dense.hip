@@ -251,6 +251,27 @@ __global__ __launch_bounds__(256) void cdot_partial_kernel(const cplx<T>* __rest
   }
 }
 
+// F[:, q] = AU[:, sel_q] - theta[sel_q] U[:, sel_q] (explicit residuals of
+// selected Ritz pairs); columns with sel_q < 0 are left unchanged.
+template <typename T>
+__global__ void resblock_kernel(const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ AU, int64_t ld, int64_t ws,
+                                const c128* __restrict__ theta, int64_t wst, const int* __restrict__ sel, int b,
+                                cplx<T>* __restrict__ F, int64_t ldf, int64_t wsf, int64_t N,
+                                const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= N * b) return;
+  const int64_t n = e / b;
+  const int q = int(e % b);
+  const int col = sel[w * b + q];
+  if (col < 0) return;
+  const c128 th = theta[int64_t(w) * wst + col];
+  const cplx<T> u = U[int64_t(w) * ws + n * ld + col], au = AU[int64_t(w) * ws + n * ld + col];
+  const double rr = double(au.re) - (th.re * double(u.re) - th.im * double(u.im));
+  const double ri = double(au.im) - (th.re * double(u.im) + th.im * double(u.re));
+  F[int64_t(w) * wsf + n * ldf + q] = cplx<T>{T(rr), T(ri)};
+}
+
 // ------------------------------------------------------------- misc
 __device__ inline uint64_t mix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -381,6 +402,19 @@ void gemm_rows(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_
                        wsx, B, ldb, wsb, Y, ldy, wsy, N, r, s, T(beta), T(alpha), wmap);
   }
 }
+
+template <typename T>
+void residual_block(const cplx<T>* U, const cplx<T>* AU, int64_t ld, int64_t ws, const c128* theta, int64_t wst,
+                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, int64_t N, int nwin, hipStream_t st,
+                    const int* wmap) {
+  if (nwin <= 0 || b <= 0) return;
+  hipLaunchKernelGGL((resblock_kernel<T>), dim3(unsigned((N * b + 255) / 256), nwin), dim3(256), 0, st, U, AU, ld,
+                     ws, theta, wst, sel, b, F, ldf, wsf, N, wmap);
+}
+template void residual_block<double>(const c128*, const c128*, int64_t, int64_t, const c128*, int64_t, const int*,
+                                     int, c128*, int64_t, int64_t, int64_t, int, hipStream_t, const int*);
+template void residual_block<float>(const c64*, const c64*, int64_t, int64_t, const c128*, int64_t, const int*, int,
+                                    c64*, int64_t, int64_t, int64_t, int, hipStream_t, const int*);
 
 int64_t residual_workspace(int64_t N, int s, int nwin) {
   int64_t best = 0;

@@ -90,7 +90,7 @@ template <typename T> struct Batch {
   DevArr<cplx<T>> V, AV, Vr, AVr, F, Ft;
   DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, part;
   DevArr<double> res, sig;
-  DevArr<int> flags, info, wmap;
+  DevArr<int> flags, info, wmap, sel;
 
   void alloc(int nw_, int64_t N_, int m_, int k_, int b_, int nv_) {
     nw = nw_; N = N_; m = m_; k = k_; b = b_; nv = nv_;
@@ -112,7 +112,7 @@ template <typename T> struct Batch {
     part.alloc(size_t(pw));
     res.alloc(size_t(2) * nv * nw);
     sig.alloc(size_t(nw));
-    flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw));
+    flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
   }
   int64_t ws() const { return N * m; }
 };
@@ -157,7 +157,7 @@ struct WinOut {
 template <typename T, typename Save>
 void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int mode, double tol, int max_restarts,
              uint64_t seed, const cplx<float>* init_from, std::vector<WinOut>& out, Save&& save,
-             double stall_floor = 0.0) {
+             double stall_floor = 0.0, bool davidson = false) {
   const int nw = B.nw, m = B.m, k = B.k, b = B.b, nv = B.nv;
   const int64_t N = B.N, wsV = B.ws();
   hipStream_t st = c->st;
@@ -258,6 +258,22 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
     na = int(active.size());
     if (na == 0) break;
     check(hipMemcpyAsync(B.wmap.p, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, st), "wmap");
+    if (davidson) {
+      // after a precision change the kept basis has a residual of full rank,
+      // so the next block is built from the explicit residuals of the b
+      // wanted Ritz pairs with the largest backward error
+      std::vector<int> hsel(size_t(nw) * b, -1);
+      for (int w : active) {
+        std::vector<int> ord(wins[w].nev);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(), [&](int a, int c2) { return out[w].rho[a] > out[w].rho[c2]; });
+        for (int q = 0; q < b && q < int(ord.size()); ++q) hsel[size_t(w) * b + q] = ord[q];
+      }
+      check(hipMemcpyAsync(B.sel.p, hsel.data(), sizeof(int) * hsel.size(), hipMemcpyHostToDevice, st), "sel");
+      residual_block<T>(B.V.p + k, B.AV.p + k, m, wsV, B.thsel.p, nv, B.sel.p, b, B.F.p, b, N * b, N, na, st,
+                        B.wmap.p);
+      check(hipStreamSynchronize(st), "sync");  // hsel is a host temporary
+    }
     // next block: the continuation F, re-orthogonalised against the kept basis
     copy_block<T, T>(B.F.p, b, N * b, B.V.p + k, m, wsV, N, b, na, st, B.wmap.p);
     orthonormalize<T>(c, B, B.V.p + k, m, wsV, k, na);
@@ -266,7 +282,7 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
 }
 
 void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& b) {
-  b = o.block > 0 ? o.block : 16;
+  b = o.block > 0 ? o.block : 2;
   m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max(6 * nvmax, nvmax + 4 * b), b);
   const int mcap = int(std::min<int64_t>(N / b, 4096) * b) - b;
   if (m > mcap) m = std::max(mcap, 2 * b);
@@ -489,7 +505,7 @@ bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_op
       check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * wins[w].nev, Bd.V.p + size_t(w) * N * m + k,
                              sizeof(c128) * m, sizeof(c128) * wins[w].nev, N, hipMemcpyDeviceToDevice, st),
             "save");
-    });
+    }, 0.0, true);
   } else {
     Batch<double> Bd;
     Bd.alloc(nw, N, m, k, b, nvmax);
@@ -627,55 +643,137 @@ void combine(tsg_ctx* c, int keep_lowest) {
   c->have_grams = false;
 }
 
-void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
-                  double* e_range) {
-  if (n_r < 1 || p < 1) throw InvalidArg("need n_r >= 1 and p >= 1");
-  if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL) throw InvalidArg("unknown planning mode");
-  // two exterior eigenvalues (Section 2.2); solved as temporary partitions
+namespace {
+
+std::vector<int> window_counts(int n_r, int p, int mode) {
+  std::vector<int> counts(p);
+  if (mode != TSG_PLAN_ALG1) {
+    const int base = n_r / p;
+    for (int j = 0; j < p; ++j) counts[j] = base + (j < n_r - base * p ? 1 : 0);
+    return counts;
+  }
+  // Algorithm 1: n_{r,j} = round(2/(1.5 + (j-1)/p) n_r/p) for j <= p/2,
+  // ceil(2 n_r/p) - n_{r,p-j+1} otherwise (middle of odd p: half of it).
+  const long top = (2L * n_r + p - 1) / p;
+  for (int j = 1; j <= p; ++j)
+    if (2 * j <= p) counts[j - 1] = int(std::floor(2.0 / (1.5 + double(j - 1) / p) * double(n_r) / p + 0.5));
+  for (int j = 1; j <= p; ++j)
+    if (2 * j > p) {
+      const int mirror = p - j + 1;
+      counts[j - 1] = (mirror == j) ? int((top + 1) / 2) : int(top - counts[mirror - 1]);
+    }
+  return counts;
+}
+
+double smallest_real_part(tsg_ctx* c, const tsg_opts& o) {
+  // the exterior eigenvalue of smallest real part (Section 2.2), as a
+  // temporary one-eigenpair partition
   const size_t keep_parts = c->parts.size();
   tsg_opts oe = o;
   oe.precision = TSG_FP64;
-  double ext[2];
-  for (int side = 0; side < 2; ++side) {
-    oe.select = side == 0 ? TSG_SELECT_SMALLEST_REAL : TSG_SELECT_LARGEST_REAL;
-    const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
-    const Partition& P = c->parts.back();
-    ext[side] = P.eps[0].re;
-    c->parts.resize(keep_parts);
-    if (!ok) throw StateError("exterior eigenvalue did not converge");
-  }
-  std::vector<int> counts(p);
-  if (mode == TSG_PLAN_EQUAL) {
-    const int base = n_r / p;
-    for (int j = 0; j < p; ++j) counts[j] = base + (j < n_r - base * p ? 1 : 0);
-  } else {
-    // Algorithm 1: n_{r,j} = round(2/(1.5 + (j-1)/p) n_r/p) for j <= p/2,
-    // ceil(2 n_r/p) - n_{r,p-j+1} otherwise (middle of odd p: half of it).
-    const long top = (2L * n_r + p - 1) / p;
-    for (int j = 1; j <= p; ++j) {
-      if (2 * j <= p) {
-        const double x = 2.0 / (1.5 + double(j - 1) / p) * double(n_r) / p;
-        counts[j - 1] = int(std::floor(x + 0.5));
-      }
-    }
-    for (int j = 1; j <= p; ++j) {
-      if (2 * j > p) {
-        const int mirror = p - j + 1;
-        counts[j - 1] = (mirror == j) ? int((top + 1) / 2) : int(top - counts[mirror - 1]);
-      }
-    }
-  }
-  const double delta = (ext[1] - ext[0]) / double(c->N);
+  oe.basis = 0;
+  oe.keep = 0;
+  oe.select = TSG_SELECT_SMALLEST_REAL;
+  const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
+  const double e = c->parts.back().eps[0].re;
+  c->parts.resize(keep_parts);
+  if (!ok) throw StateError("exterior eigenvalue did not converge");
+  return e;
+}
+
+}  // namespace
+
+double upper_bound_real(const tsg_ctx* c) {
+  // Re eps = u^H (K + V) u / u^H u <= max V + 3 max_theta s(theta) / (2 h^2); the
+  // radius-R symbol s(theta) = -(c_0 + 2 sum c_m cos m theta) peaks at theta = pi
+  // for these weights, where it equals |c_0| + 2 sum |c_m|.
+  double smax = std::fabs(c->coef[0]);
+  for (int m = 1; m <= c->R; ++m) smax += 2.0 * std::fabs(c->coef[m]);
+  return c->vmax + 3.0 * smax;
+}
+
+void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
+                  double* e_range) {
+  if (n_r < 1 || p < 1) throw InvalidArg("need n_r >= 1 and p >= 1");
+  if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL && mode != TSG_PLAN_SAMPLED)
+    throw InvalidArg("unknown planning mode");
+  const double e_min = smallest_real_part(c, o);
+  const double e_max = upper_bound_real(c);
+  const std::vector<int> counts = window_counts(n_r, p, mode == TSG_PLAN_ALG1 ? TSG_PLAN_ALG1 : TSG_PLAN_EQUAL);
   out.resize(p);
-  double prev_s = ext[0];
-  int prev_n = 0;
-  for (int j = 0; j < p; ++j) {
-    const double s = prev_s + delta * (counts[j] + prev_n) / 2.0;
-    out[j] = WindowSpec{s, counts[j]};
-    prev_s = s;
-    prev_n = counts[j];
+  if (mode != TSG_PLAN_SAMPLED) {
+    // E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N)(n_{r,j} + n_{r,j-1})/2
+    const double delta = (e_max - e_min) / double(c->N);
+    double prev_s = e_min;
+    int prev_n = 0;
+    for (int j = 0; j < p; ++j) {
+      const double s = prev_s + delta * (counts[j] + prev_n) / 2.0;
+      out[j] = WindowSpec{s, counts[j]};
+      prev_s = s;
+      prev_n = counts[j];
+    }
+  } else {
+    // Density sampling (Section 2.2): a few eigenpairs at sample shifts over
+    // the region of interest give the local eigenvalue density; its integral
+    // estimates the counting function, and the windows sit at the midpoints
+    // of consecutive intervals holding n_{r,j} eigenvalues (the placement of
+    // Section 3).  The region's top is first guessed from the free-particle
+    // counting function of the box.
+    const double lx = (c->nx + 1) * c->h, ly = (c->ny + 1) * c->h, lz = (c->nz + 1) * c->h;
+    const double kf = std::pow(6.0 * M_PI * M_PI * double(n_r) / (lx * ly * lz), 1.0 / 3.0);
+    double top = std::max(0.5 * kf * kf, 0.0);
+    top = std::max(top, e_min + 0.25) * 1.25 + 0.25 * std::fabs(e_min);
+    const int S = std::max(2 * p, 8), ns = 8;
+    std::vector<WindowSpec> probes(S);
+    for (int i = 0; i < S; ++i) probes[i] = WindowSpec{e_min + (top - e_min) * (i + 0.5) / S, ns};
+    const size_t keep_parts = c->parts.size();
+    tsg_opts op = o;
+    op.precision = TSG_FP64;
+    op.tol = std::max(o.tol, 1e-6);
+    op.basis = 0;
+    op.keep = 0;
+    op.select = TSG_SELECT_NEAREST;
+    (void)solve_windows(c, probes, op);
+    std::vector<double> pc(S + 1), rho(S + 1);
+    for (int i = 0; i < S; ++i) {
+      const Partition& P = c->parts[keep_parts + i];
+      double lo = P.eps[0].re, hi = P.eps[0].re, sum = 0.0;
+      for (const auto& e : P.eps) { lo = std::min(lo, e.re); hi = std::max(hi, e.re); sum += e.re; }
+      pc[i + 1] = sum / P.eps.size();
+      rho[i + 1] = double(P.eps.size() - 1) / std::max(hi - lo, 1e-12);
+    }
+    c->parts.resize(keep_parts);
+    pc[0] = e_min;
+    rho[0] = rho[1];
+    // order the sample points, then integrate the piecewise-linear density
+    std::vector<int> ord(S + 1);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b2) { return pc[a] < pc[b2]; });
+    std::vector<double> xs, cum;
+    xs.push_back(pc[ord[0]]);
+    cum.push_back(0.0);
+    for (int q = 1; q <= S; ++q) {
+      const double x0 = pc[ord[q - 1]], x1 = pc[ord[q]];
+      xs.push_back(x1);
+      cum.push_back(cum.back() + 0.5 * (rho[ord[q - 1]] + rho[ord[q]]) * (x1 - x0));
+    }
+    auto inverse = [&](double target) {
+      for (size_t q = 1; q < xs.size(); ++q)
+        if (cum[q] >= target) {
+          const double f = (target - cum[q - 1]) / std::max(cum[q] - cum[q - 1], 1e-300);
+          return xs[q - 1] + f * (xs[q] - xs[q - 1]);
+        }
+      const double last_rho = rho[ord[S]];
+      return xs.back() + (target - cum.back()) / std::max(last_rho, 1e-12);
+    };
+    double acc = 0.0;
+    for (int j = 0; j < p; ++j) {
+      const double a = inverse(acc), b2 = inverse(acc + counts[j]);
+      out[j] = WindowSpec{0.5 * (a + b2), counts[j]};
+      acc += counts[j];
+    }
   }
-  if (e_range) { e_range[0] = ext[0]; e_range[1] = ext[1]; }
+  if (e_range) { e_range[0] = e_min; e_range[1] = e_max; }
 }
 
 void transmission(tsg_ctx* c, const double* E, int nE, double* T) {

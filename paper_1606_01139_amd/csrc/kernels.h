@@ -46,6 +46,13 @@ void residual_norms(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* A
                     int64_t cap, hipStream_t st, const int* wmap = nullptr);
 int64_t residual_workspace(int64_t N, int s, int nwin);
 
+// F[:, q] = AU[:, sel[w*b+q]] - theta * U[:, sel[w*b+q]] (columns with a
+// negative selection are left unchanged).
+template <typename T>
+void residual_block(const cplx<T>* U, const cplx<T>* AU, int64_t ld, int64_t ws, const c128* theta, int64_t wst,
+                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, int64_t N, int nwin, hipStream_t st,
+                    const int* wmap = nullptr);
+
 // c-products u^T A u and u^T u of each column (unconjugated), FP64.
 template <typename T>
 void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,

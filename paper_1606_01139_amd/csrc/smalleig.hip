@@ -20,31 +20,39 @@ constexpr int kEigThreads = 512;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
-// Block-wide sum of doubles (blockDim.x == kEigThreads).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of doubles (blockDim.x == kEigThreads): wave reductions,
+// then one pass over the per-wave partials.
 __device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wv] = v;
   __syncthreads();
-  for (int o = kEigThreads / 2; o > 0; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = 0.0;
+  for (int q = 0; q < kEigThreads / 64; ++q) r += red[q];
   __syncthreads();
   return r;
 }
 
 // ---------------------------------------------------------------- Hessenberg
+// Householder reduction H <- P^H H P to upper Hessenberg form, Z <- Z P.
+// Column reductions (v^H H) run one thread per column; row reductions
+// (H v) run one wavefront per row so that every load is coalesced.
 __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Zall,
                                                                  int64_t wsz, const int* __restrict__ wmap) {
-  extern __shared__ c128 sm[];  // v[m], u[m]
-  __shared__ double red[kEigThreads];
+  extern __shared__ c128 sm[];  // v[m]
+  __shared__ double red[kEigThreads / 64];
   c128* v = sm;
-  c128* u = sm + m;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int NW = kEigThreads / 64;
   for (int64_t e = t; e < int64_t(m) * m; e += kEigThreads) {
     const int i = int(e / m), j = int(e % m);
     Z[e] = c128{i == j ? 1.0 : 0.0, 0.0};
@@ -54,53 +62,54 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
     const int len = m - k - 1;  // rows k+1 .. m-1
     double part = 0.0;
     for (int i = t; i < len; i += kEigThreads) {
-      c128 x = H[int64_t(k + 1 + i) * m + k];
+      const c128 x = H[int64_t(k + 1 + i) * m + k];
       v[i] = x;
       part += norm2(x);
     }
     const double alpha2 = block_sum(part, red);
-    const double alpha = sqrt(alpha2);
-    const c128 x0 = H[int64_t(k + 1) * m + k];
+    const c128 x0 = v[0];
+    __syncthreads();  // every thread has read v[0] before it is rewritten
     const double ax0 = cabs(x0);
-    // all threads agree on these scalars (same inputs)
-    double tailsq = alpha2 - ax0 * ax0;
-    if (alpha == 0.0 || tailsq <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) {
-      __syncthreads();
-      continue;  // already Hessenberg in this column
-    }
+    const double alpha = sqrt(alpha2);
+    if (alpha == 0.0 || alpha2 - ax0 * ax0 <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) continue;
     const c128 ph = ax0 > 0.0 ? c128{x0.re / ax0, x0.im / ax0} : c128{1.0, 0.0};
-    // v = x + ph * alpha e1; |v|^2 = 2 alpha (alpha + |x0|)
     if (t == 0) v[0] = x0 + alpha * ph;
     __syncthreads();
     const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
-    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k
+    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k (one thread per column)
     for (int j = k + t; j < m; j += kEigThreads) {
-      c128 s{0.0, 0.0};
-      for (int i = 0; i < len; ++i) fma_cacc(s, v[i], H[int64_t(k + 1 + i) * m + j]);
-      s = beta * s;
+      c128 sacc{0.0, 0.0};
+#pragma unroll 8
+      for (int i = 0; i < len; ++i) fma_cacc(sacc, v[i], H[int64_t(k + 1 + i) * m + j]);
+      sacc = beta * sacc;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) {
         c128& h = H[int64_t(k + 1 + i) * m + j];
-        h = h - v[i] * s;
+        h = h - v[i] * sacc;
       }
     }
     __syncthreads();
-    // right: H[i, k+1..] -= beta (H[i, k+1..] v) v^H for all rows; same on Z
-    for (int i = t; i < 2 * m; i += kEigThreads) {
-      c128* row = (i < m) ? (H + int64_t(i) * m) : (Z + int64_t(i - m) * m);
-      c128 s{0.0, 0.0};
-      for (int j = 0; j < len; ++j) fma_acc(s, row[k + 1 + j], v[j]);
-      s = beta * s;
-      for (int j = 0; j < len; ++j) {
+    // right: row r of H and of Z: row[k+1..] -= beta (row[k+1..] v) v^H (one wavefront per row)
+    for (int r = wv; r < 2 * m; r += NW) {
+      c128* row = (r < m) ? (H + int64_t(r) * m) : (Z + int64_t(r - m) * m);
+      double sr = 0.0, si = 0.0;
+      for (int j = lane; j < len; j += 64) {
+        const c128 a = row[k + 1 + j], b = v[j];
+        sr += a.re * b.re - a.im * b.im;
+        si += a.re * b.im + a.im * b.re;
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      const c128 sc = beta * c128{sr, si};
+      for (int j = lane; j < len; j += 64) {
         c128& h = row[k + 1 + j];
-        h = h - s * conj(v[j]);
+        h = h - sc * conj(v[j]);
       }
     }
     __syncthreads();
-    // exact zeros below the subdiagonal
     for (int i = k + 2 + t; i < m; i += kEigThreads) H[int64_t(i) * m + k] = c128{0.0, 0.0};
     __syncthreads();
   }
-  (void)u;
 }
 
 // ---------------------------------------------------------------- vectors
@@ -252,7 +261,7 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   if (nwin <= 0 || m <= 0) return;
   c128* Z = work;               // m*m per window at stride wsw
   c128* X = work + int64_t(m) * m;
-  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), size_t(2 * m) * sizeof(c128), st, H, wsh, m,
+  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), size_t(m) * sizeof(c128), st, H, wsh, m,
                      Z, wsw, wmap);
   launch_schur(H, wsh, m, Z, wsw, theta, wst, info, nwin, st, wmap);
   hipLaunchKernelGGL(trevc_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, H, wsh, m, X, wsw, wmap);

@@ -15,25 +15,46 @@
 //     touch disjoint row pairs (left) and column pairs (right), and left and
 //     right rotations commute, so each step applies all left rotations, then
 //     all right rotations.
+#include <cstdio>
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace tsg {
 namespace {
 
-constexpr int kQT = 512;      // threads per workgroup
+constexpr int kQT = 1024;     // threads per workgroup
 constexpr int kFin = 64;      // largest block finished in LDS
 constexpr int kMaxShift = 64;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
+// 1/sqrt(v): hardware estimate refined by two Newton steps (full FP64
+// accuracy, so that each rotation is unitary to rounding).
+__device__ inline double rsqrt_nr(double v) {
+  double r = __builtin_amdgcn_rsq(v);
+  r = r * (1.5 - 0.5 * v * r * r);
+  return r * (1.5 - 0.5 * v * r * r);
+}
+
 __device__ inline void givens(c128 x, c128 y, double& c, c128& s) {
-  // [c s; -conj(s) c] [x; y] = [r; 0], c real >= 0
-  const double ax = cabs(x), ay = cabs(y);
-  if (ay == 0.0) { c = 1.0; s = c128{0.0, 0.0}; return; }
-  if (ax == 0.0) { c = 0.0; s = c128{y.re / ay, -y.im / ay}; return; }
-  const double rho = hypot(ax, ay);
-  c = ax / rho;
-  s = (1.0 / rho) * (c128{x.re / ax, x.im / ax} * conj(y));
+  // [c s; -conj(s) c] [x; y] = [r; 0], c real >= 0, without divisions:
+  // c = |x| / r, s = (x / |x|) conj(y) / r, r = sqrt(|x|^2 + |y|^2)
+  const double nx2 = norm2(x), ny2 = norm2(y);
+  if (ny2 == 0.0) { c = 1.0; s = c128{0.0, 0.0}; return; }
+  if (nx2 == 0.0) { c = 0.0; s = rsqrt_nr(ny2) * conj(y); return; }
+  const double ir = rsqrt_nr(nx2 + ny2), ix = rsqrt_nr(nx2);
+  c = nx2 * ix * ir;
+  s = (ix * ir) * (x * conj(y));
+}
+
+// Synchronisation for the single-wavefront LDS sweeps: a wavefront runs in
+// lockstep and its LDS operations complete in order, so a fence plus a
+// wave barrier orders the lanes' LDS traffic.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ inline c128 wilkinson(c128 a, c128 b, c128 c2, c128 d) {
@@ -44,6 +65,10 @@ __device__ inline c128 wilkinson(c128 a, c128 b, c128 c2, c128 d) {
   const c128 l1 = mid + disc, l2 = mid - disc;
   return (cabs(l1 - d) <= cabs(l2 - d)) ? l1 : l2;
 }
+
+// Optional phase timers (wall clock, 100 MHz), summed over windows; read
+// and printed by the host when TSG_K4PROF=1.
+__device__ unsigned long long g_k4prof[8];
 
 struct QRShared {
   int lo, flag, iter;
@@ -61,15 +86,16 @@ struct QRShared {
 // Single-shift QR on the n x n block B (LDS, row-major) until all its
 // eigenvalues are deflated, full Schur form of the block.  If Q is not null
 // the rotations are accumulated, Q <- Q G^H.  Returns false when the sweep
-// limit is hit.  All threads call it.
+// limit is hit.  Run by the first wavefront only (threads 0..63).
 __device__ bool lds_qr(c128* B, c128* Q, int n, QRShared& S) {
+  constexpr int NT = 64;
   const int t = threadIdx.x;
   const double ulp = 2.220446049250313e-16;
   int ihi = n - 1;
   int total = 0;
   const int maxsweeps = 40 * n + 40;
   if (t == 0) S.iter = 0;
-  __syncthreads();
+  wave_sync();
   while (ihi > 0) {
     if (t == 0) {
       int l = ihi;
@@ -97,7 +123,7 @@ __device__ bool lds_qr(c128* B, c128* Q, int n, QRShared& S) {
         S.iter = 0;
       }
     }
-    __syncthreads();
+    wave_sync();
     const int l = S.lo;
     if (l == ihi) { --ihi; continue; }
     if (++total > maxsweeps) return false;
@@ -138,18 +164,22 @@ __device__ bool lds_qr(c128* B, c128* Q, int n, QRShared& S) {
           }
         }
       } else {
-        // left: rows k, k+1, columns k+2 .. n-1
-        const int nl = n - (k + 2);
-        const int nr = k;  // right: rows 0 .. k-1 (rows k..k+2 are thread 0's)
+        // left: rows k, k+1, columns k+2 .. n-1; right: rows 0 .. k-1 (rows
+        // k..k+2 are thread 0's).  Without Q only eigenvalues are wanted, so
+        // the rotations stay inside the active block [l, ihi].
+        const int cend = Q ? n : ihi + 1;
+        const int rbeg = Q ? 0 : l;
+        const int nl = max(0, cend - (k + 2));
+        const int nr = k - rbeg;
         const int nq = Q ? n : 0;
-        for (int it = t - 1; it < nl + nr + nq; it += kQT - 1) {
+        for (int it = t - 1; it < nl + nr + nq; it += NT - 1) {
           if (it < nl) {
             const int j = k + 2 + it;
             const c128 u = B[k * n + j], v = B[(k + 1) * n + j];
             B[k * n + j] = c * u + s * v;
             B[(k + 1) * n + j] = c * v - conj(s) * u;
           } else if (it < nl + nr) {
-            const int i = it - nl;
+            const int i = rbeg + it - nl;
             const c128 u = B[i * n + k], v = B[i * n + k + 1];
             B[i * n + k] = c * u + conj(s) * v;
             B[i * n + k + 1] = c * v - s * u;
@@ -161,7 +191,7 @@ __device__ bool lds_qr(c128* B, c128* Q, int n, QRShared& S) {
           }
         }
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   return true;
@@ -204,7 +234,8 @@ __device__ void apply_left(c128* Y, int64_t ld, int r0, int c0, int c1, const c1
 }
 
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
-                                                    c128* theta, int64_t wst, int* info, const int* __restrict__ wmap) {
+                                                    c128* theta, int64_t wst, int* info, const int* __restrict__ wmap,
+                                                    int prof) {
   extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
   __shared__ QRShared S;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
@@ -217,6 +248,14 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   int sweeps = 0;
   const int maxsweeps = 20 * m + 20;
   bool failed = false;
+  unsigned long long tp = wall_clock64();
+  auto tick = [&](int slot) {
+    if (prof && t == 0) {
+      const unsigned long long now = wall_clock64();
+      atomicAdd(&g_k4prof[slot], now - tp);
+      tp = now;
+    }
+  };
   while (ihi >= 0) {
     // deflation scan: largest l in (0, ihi] with a negligible subdiagonal
     int best = 0;
@@ -233,6 +272,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     }
     const int lo = S.ired[0];
     __syncthreads();
+    tick(0);
     if (lo > 0 && t == 0) H[int64_t(lo) * m + lo - 1] = c128{0.0, 0.0};
     const int n = ihi - lo + 1;
     if (n == 1) {
@@ -251,8 +291,13 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         Q[e] = c128{i == j ? 1.0 : 0.0, 0.0};
       }
       __syncthreads();
-      const bool ok = lds_qr(B, Q, n, S);
-      if (!ok) failed = true;
+      if (t < 64) {
+        const bool ok = lds_qr(B, Q, n, S);
+        if (t == 0) S.flag = ok ? 0 : 1;
+      }
+      __syncthreads();
+      tick(5);
+      if (S.flag) failed = true;
       for (int e = t; e < n * n; e += kQT) {
         const int i = e / n, j = e % n;
         H[int64_t(lo + i) * m + lo + j] = B[e];
@@ -262,13 +307,14 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       apply_right(Z, m, 0, m, lo, Q, n);
       apply_right(H, m, 0, lo, lo, Q, n);
       apply_left(H, m, lo, ihi + 1, m, Q, n);
+      tick(6);
       ihi = lo - 1;
       __syncthreads();
       continue;
     }
     if (++sweeps > maxsweeps) { failed = true; break; }
     // shifts: eigenvalues of the trailing ns x ns block (in LDS)
-    const int ns = min(kMaxShift, max(2, n / 2));
+    const int ns = min(48, max(2, n / 3));
     {
       c128* B = lds;
       const int b0 = ihi - ns + 1;
@@ -277,13 +323,19 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         B[e] = H[int64_t(b0 + i) * m + b0 + j];
       }
       __syncthreads();
-      const bool ok = lds_qr(B, nullptr, ns, S);
+      if (t < 64) {
+        const bool ok = lds_qr(B, nullptr, ns, S);
+        if (t == 0) S.flag = ok ? 0 : 1;
+      }
+      __syncthreads();
+      const bool ok = S.flag == 0;
       if (t < ns) S.shift[t] = ok ? B[t * ns + t] : H[int64_t(b0 + t) * m + b0 + t];
       if (t == 0 && sweeps % 6 == 5) {
         // occasional exceptional shift against stagnation
         S.shift[0] = H[int64_t(ihi) * m + ihi] + c128{0.75 * cabs1(H[int64_t(ihi) * m + ihi - 1]), 0.0};
       }
       __syncthreads();
+      tick(1);
     }
     // pipelined chase: bulge j sits at position lo + step - 3 j
     const int nsteps = (ihi - lo) + 3 * (ns - 1);
@@ -309,37 +361,97 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         }
       }
       __syncthreads();
-      // all left rotations: rows p, p+1, columns from max(p-1, lo) to m-1
-      for (int j = 0; j < ns; ++j) {
-        const int p = S.bp[j];
-        if (p < 0) continue;
-        const double c = S.bc[j];
-        const c128 s = S.bs[j];
-        const int c0 = (p > lo) ? p - 1 : lo;
-        for (int col = c0 + t; col < m; col += kQT) {
-          c128* u = H + int64_t(p) * m + col;
-          c128* v = H + int64_t(p + 1) * m + col;
-          const c128 a = *u, b = *v;
-          *u = c * a + s * b;
-          *v = (col == p - 1) ? c128{0.0, 0.0} : c * b - conj(s) * a;
+      tick(2);
+      // active bulges form the contiguous range [ja, jb]
+      // bulge j is at p = lo + step - 3 j, active while lo <= p <= ihi - 1
+      const int dd = step - (ihi - 1 - lo);
+      const int ja = dd > 0 ? (dd + 2) / 3 : 0;
+      const int jb = min(ns - 1, step / 3);
+      const int nact = jb >= ja ? jb - ja + 1 : 0;
+      // all left rotations: rows p, p+1, columns from max(p-1, lo) to m-1.
+      // Items (bulge, column), column fastest; each thread loads a batch of
+      // independent items before storing any.
+      {
+        const int W = m - lo;
+        const int total = nact * W;
+        for (int base = t; base < total; base += kQT * 4) {
+          c128 av[4], bv[4];
+          int pr[4], cl[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int idx = base + q * kQT;
+            pr[q] = -1;
+            if (idx < total) {
+              const int j = ja + idx / W, col = lo + idx % W;
+              const int p = S.bp[j];
+              const int c0 = (p > lo) ? p - 1 : lo;
+              if (p >= 0 && col >= c0) {
+                pr[q] = j;
+                cl[q] = col;
+                av[q] = H[int64_t(p) * m + col];
+                bv[q] = H[int64_t(p + 1) * m + col];
+              }
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (pr[q] < 0) continue;
+            const int j = pr[q], p = S.bp[j], col = cl[q];
+            const double c = S.bc[j];
+            const c128 sj = S.bs[j];
+            H[int64_t(p) * m + col] = c * av[q] + sj * bv[q];
+            H[int64_t(p + 1) * m + col] = (col == p - 1) ? c128{0.0, 0.0} : c * bv[q] - conj(sj) * av[q];
+          }
         }
       }
       __syncthreads();
-      // all right rotations: columns p, p+1 for rows 0..min(p+2, ihi), and Z
-      for (int j = 0; j < ns; ++j) {
-        const int p = S.bp[j];
-        if (p < 0) continue;
-        const double c = S.bc[j];
-        const c128 s = S.bs[j];
-        const int rmax = min(p + 2, ihi);
-        for (int r = t; r <= rmax + m; r += kQT) {
-          c128* row = (r <= rmax) ? (H + int64_t(r) * m) : (Z + int64_t(r - rmax - 1) * m);
-          const c128 a = row[p], b = row[p + 1];
-          row[p] = c * a + conj(s) * b;
-          row[p + 1] = c * b - s * a;
+      tick(3);
+      // all right rotations: columns p, p+1 for rows 0..min(p+2, ihi), and
+      // every row of Z.  Items (row, bulge), bulge fastest: neighbouring
+      // lanes touch nearby column pairs of the same row.
+      {
+        const int Rh = ihi + 1;
+        const int total = (Rh + m) * nact;
+        for (int base = t; base < total; base += kQT * 4) {
+          c128 av[4], bv[4];
+          c128* rp[4];
+          int pr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int idx = base + q * kQT;
+            pr[q] = -1;
+            if (idx < total && nact > 0) {
+              const int r = idx / nact, j = ja + idx % nact;
+              const int p = S.bp[j];
+              bool ok = p >= 0;
+              c128* row;
+              if (r < Rh) {
+                row = H + int64_t(r) * m;
+                ok = ok && r <= min(p + 2, ihi);
+              } else {
+                row = Z + int64_t(r - Rh) * m;
+              }
+              if (ok) {
+                pr[q] = j;
+                rp[q] = row;
+                av[q] = row[p];
+                bv[q] = row[p + 1];
+              }
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (pr[q] < 0) continue;
+            const int j = pr[q], p = S.bp[j];
+            const double c = S.bc[j];
+            const c128 sj = S.bs[j];
+            rp[q][p] = c * av[q] + conj(sj) * bv[q];
+            rp[q][p + 1] = c * bv[q] - sj * av[q];
+          }
         }
       }
       __syncthreads();
+      tick(4);
     }
   }
   if (t == 0) info[w] = failed ? max(ihi + 1, 1) : 0;
@@ -354,6 +466,11 @@ size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
 
 void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta, int64_t wst, int* info, int nwin,
                   hipStream_t st, const int* wmap) {
+  static const int prof = [] { const char* v = std::getenv("TSG_K4PROF"); return (v && v[0] == '1') ? 1 : 0; }();
+  if (prof) {
+    unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    (void)hipMemcpyToSymbolAsync(HIP_SYMBOL(g_k4prof), z, sizeof(z), 0, hipMemcpyHostToDevice, st);
+  }
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(schur_kernel),
@@ -361,7 +478,15 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta
     attr_set = true;
   }
   hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, theta, wst,
-                     info, wmap);
+                     info, wmap, prof);
+  if (prof) {
+    unsigned long long z[8];
+    (void)hipMemcpyFromSymbolAsync(z, HIP_SYMBOL(g_k4prof), sizeof(z), 0, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    std::fprintf(stderr, "[k4] m=%d nwin=%d us: scan %.0f shifts %.0f chaseA %.0f chaseB %.0f chaseC %.0f fin %.0f apply %.0f\n",
+                 m, nwin, z[0] / 100.0, z[1] / 100.0, z[2] / 100.0, z[3] / 100.0, z[4] / 100.0, z[5] / 100.0,
+                 z[6] / 100.0);
+  }
 }
 
 }  // namespace tsg

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(pkg):
 
 def test_default_opts(pkg):
     o = pkg.default_opts()
-    assert o.tol == 1e-8 and o.block == 16 and o.precision == pkg.FP64 and o.max_restarts > 0
+    assert o.tol == 1e-8 and o.block == 2 and o.precision == pkg.FP64 and o.max_restarts > 0
     assert o.bulk_tol == 1e-5 and o.select == pkg.SELECT_NEAREST
 
 

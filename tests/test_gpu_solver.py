@@ -124,19 +124,29 @@ def test_duplicate_windows_are_removed(torch_cuda):
 
 
 def test_planner_matches_oracle(torch_cuda):
-    from oracle import partition, eigen
-    from paper_1606_01139_amd import Operator, PLAN_ALG1, PLAN_EQUAL
+    from oracle import partition, eigen, operator as op
+    from paper_1606_01139_amd import Operator, PLAN_ALG1, PLAN_EQUAL, PLAN_SAMPLED
     from synth.workloads import workload
     w = workload("c1")
     g = w.grid
     print("planner c1", flush=True)
     A, gL, gR, ea, Ua, nrm = _setup(w)
+    emax_bound = op.kinetic_upper_bound(g.h) + w.V.max()
+    assert ea.real.max() <= emax_bound
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
     for mode, counts in ((PLAN_EQUAL, partition.equal_counts(40, 2)), (PLAN_ALG1, partition.alg1_counts(40, 2))):
         wins, (emin, emax) = oper.plan_windows(40, 2, mode)
         assert abs(emin - ea.real.min()) <= 1e-9 * max(abs(emin), 1.0)
-        assert abs(emax - ea.real.max()) <= 1e-9 * max(abs(emax), 1.0)
-        shifts = partition.alg1_shifts(counts, ea.real.min(), ea.real.max(), g.n)
+        assert abs(emax - emax_bound) <= 1e-9 * emax_bound
+        shifts = partition.alg1_shifts(counts, ea.real.min(), emax_bound, g.n)
         assert [n for _, n in wins] == counts
         np.testing.assert_allclose([s for s, _ in wins], shifts, rtol=0, atol=1e-9)
+    # density sampling: the same placement from the oracle's exact eigenvalues
+    wins, (emin, _) = oper.plan_windows(40, 2, PLAN_SAMPLED)
+    box = ((g.nx + 1) * g.h, (g.ny + 1) * g.h, (g.nz + 1) * g.h)
+    probes = partition.sample_shifts(ea.real.min(), 40, 2, box)
+    samples = [eigen.window_from_spectrum(ea, Ua, s, 8)[0] for s in probes]
+    ref = partition.sampled_windows(ea.real.min(), samples, partition.equal_counts(40, 2))
+    assert [n for _, n in wins] == [20, 20]
+    np.testing.assert_allclose([s for s, _ in wins], ref, rtol=0, atol=1e-6)
     oper.close()

@@ -249,3 +249,17 @@ def test_gradient_full_spectrum_equals_direct_adjoint():
     G = np.linalg.inv(E[0] * np.eye(len(ea)) - A)
     direct = 2 * np.real(np.diag(G @ np.diag(gR) @ G.conj().T @ np.diag(gL) @ G))
     np.testing.assert_allclose(gr["V"], direct, rtol=1e-8, atol=1e-12)
+
+
+def test_sampled_windows_uniform_spectrum_closed_form():
+    # An evenly spaced spectrum e_min + d k: every sample of 8 consecutive
+    # eigenvalues measures density 1/d, the counting function is (E - e_min)/d
+    # + const, and windows of n eigenvalues sit at e_min + d (n/2 + n j) up to
+    # the half-spacing offset of the first sample's mean.
+    d, e_min = 0.01, -1.0
+    spectrum = e_min + d * np.arange(400)
+    samples = [spectrum[i:i + 8] for i in range(0, 392, 40)]
+    shifts = partition.sampled_windows(e_min, samples, [50, 50, 50])
+    np.testing.assert_allclose(shifts, [e_min + d * (25 + 50 * j) for j in range(3)], atol=1e-12)
+    # monotone and separated by n d for equal counts
+    np.testing.assert_allclose(np.diff(shifts), 50 * d, atol=1e-12)
