@@ -57,7 +57,7 @@ def stencil_roofline(w, ncols, dtype, reps=50):
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
     N = g.n
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
-    X = torch.randn(N, ncols, dtype=tdt, device="cuda")
+    X = torch.randn(ncols, N, dtype=tdt, device="cuda")
     Y = torch.empty_like(X)
     for _ in range(5):
         oper.apply(X, Y)

@@ -17,7 +17,8 @@
  *   - "host" arrays are in CPU memory; "device" arrays are in the GPU memory
  *     of the device that is current when the context is built.
  *   - Grid vectors are indexed n = x + nx (y + ny z) (x fastest); a block of
- *     B vectors is stored point-major: element (n, c) at ptr[n * ld + c].
+ *     B vectors stores each vector contiguously: element (n, c) at
+ *     ptr[c * ld + n] with ld >= N.
  *   - Complex numbers are pairs (re, im) of the stated real type.
  *   - Units are Hartree and bohr.
  *   - A context is used by one host thread at a time; distinct contexts are
@@ -84,6 +85,8 @@ typedef struct {
   int32_t keep_lowest;  /* combine keeps only the n lowest by real part (0: keep all) */
   int32_t select;       /* TSG_SELECT_NEAREST ('SM' on the shifted operator), or an exterior selection */
   double bulk_tol;      /* TSG_FP32_BULK: backward error the complex64 phase stops at (default 1e-5) */
+  int32_t graphs;       /* 1 (default): each restart cycle after the first is captured once as a
+                           hipGraph and replayed; 0: every kernel is launched directly */
 } tsg_opts;
 
 /* Per-window solver statistics of the last solve. */
@@ -147,6 +150,22 @@ tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opt
 tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int32_t p, const tsg_opts* opts,
                                     int32_t* n_unique, uint8_t* hole_flags);
 
+/* The windows of n_sys independent systems (one context each, same device
+ * and fd_radius) in one batched iteration: every kernel launch covers all
+ * windows of all systems, each window on its own grid (the partitions of
+ * Section 2 are independent, so windows of different systems share the
+ * device like windows of one system).  System s's partitions replace those
+ * of ctx[s], which is then combined as by tsg_combine.
+ *   ctx:      host, n_sys context pointers;
+ *   windows:  host, n_sys pointers, windows[s] has p[s] entries;
+ *   p:        host, n_sys counts (>= 1);
+ *   n_unique: host, n_sys outputs (count after combine), or NULL.
+ * The work runs on ctx[0]'s device; every context's stream is drained first.
+ * Errors: TSG_EINVAL, TSG_ENOCONV (some window of some system did not
+ * converge; converged subsets kept), TSG_ENOMEM, TSG_EDEVICE. */
+tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window* const* windows, const int32_t* p,
+                           const tsg_opts* opts, int32_t* n_unique);
+
 /* Algorithm 2 (Section 2.2) over the stored partitions in order: pairs
  * whose eigenvalues agree within 1e-6 ||A||_G are Gram-Schmidt
  * bi-orthogonalised under the unconjugated product; a pair whose vector
@@ -162,9 +181,10 @@ tsg_status tsg_combine(tsg_ctx* ctx, int32_t keep_lowest, int32_t* n_unique, uin
  * Errors: TSG_ESTATE (no combined set), TSG_ECAPACITY. */
 tsg_status tsg_get_eigenvalues(tsg_ctx* ctx, double* re_im, int32_t cap, int32_t* n);
 
-/* Combined eigenvectors: borrowed device view, complex128, point-major
- * N x n with leading dimension *ld; valid until the next solve, combine or
- * tsg_destroy.  Each column satisfies u^T u = 1.
+/* Combined eigenvectors: borrowed device view, complex128, N x n with each
+ * vector contiguous (element (n, c) at ptr[c * ld + n], *ld = N); valid
+ * until the next solve, combine or tsg_destroy.  Each column satisfies
+ * u^T u = 1.
  * Errors: TSG_ESTATE. */
 tsg_status tsg_get_eigenvectors(tsg_ctx* ctx, void** dev_ptr, int64_t* ld, int32_t* n);
 
@@ -186,10 +206,10 @@ tsg_status tsg_get_stats(tsg_ctx* ctx, int32_t j, tsg_window_stats* stats);
 tsg_status tsg_transmission(tsg_ctx* ctx, const double* E, int32_t nE, double* T);
 
 /* Y = A X for a block of ncols vectors (the stencil matrix-vector product of
- * Section 1, used by every iteration).  X, Y: device, point-major N x ncols
- * with leading dimension ld >= ncols, element type dtype (TSG_C128 or
- * TSG_C64); X and Y must not overlap.  Runs on the context stream; returns
- * without synchronising.  Errors: TSG_EINVAL. */
+ * Section 1, used by every iteration).  X, Y: device, ncols vectors of N
+ * elements, vector c at ptr + c * ld (ld >= N), element type dtype
+ * (TSG_C128 or TSG_C64); X and Y must not overlap.  Runs on the context
+ * stream; returns without synchronising.  Errors: TSG_EINVAL. */
 tsg_status tsg_apply_operator(tsg_ctx* ctx, const void* X, void* Y, int32_t ncols, int64_t ld, int32_t dtype);
 
 /* Dense eigen-decomposition of `batch` general complex m x m matrices (the

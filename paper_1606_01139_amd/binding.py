@@ -27,7 +27,7 @@ C128, C64 = 0, 1
 # Every symbol include/transec_gpu.h declares.
 EXPORTS = [
     "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
-    "tsg_solve_all_partitions", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
+    "tsg_solve_all_partitions", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
     "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_apply_operator", "tsg_dense_eig",
     "tsg_last_error", "tsg_destroy",
 ]
@@ -50,7 +50,8 @@ class TsgWindow(C.Structure):
 class TsgOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("basis", C.c_int32),
                 ("keep", C.c_int32), ("max_restarts", C.c_int32), ("seed", C.c_uint64),
-                ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double)]
+                ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double),
+                ("graphs", C.c_int32)]
 
 
 class TsgWindowStats(C.Structure):
@@ -85,6 +86,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_solve_partition.argtypes = [vp, TsgWindow, C.POINTER(TsgOpts), C.POINTER(i32)]
     lib.tsg_solve_all_partitions.argtypes = [vp, C.POINTER(TsgWindow), i32, C.POINTER(TsgOpts), C.POINTER(i32),
                                              C.POINTER(C.c_uint8)]
+    lib.tsg_solve_batch.argtypes = [C.POINTER(vp), i32, C.POINTER(C.POINTER(TsgWindow)), C.POINTER(i32),
+                                    C.POINTER(TsgOpts), C.POINTER(i32)]
     lib.tsg_combine.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_uint8)]
     lib.tsg_get_eigenvalues.argtypes = [vp, dp, i32, C.POINTER(i32)]
     lib.tsg_get_eigenvectors.argtypes = [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i32)]
@@ -141,10 +144,11 @@ class _DevView:
 
 
 def _complex_view(ptr: int, rows: int, cols: int, ld: int):
+    """rows x cols complex128 view of `cols` contiguous vectors at stride ld."""
     import torch
     if rows * cols == 0 or not ptr:
         return torch.zeros((rows, cols), dtype=torch.complex128, device="cuda")
-    v = _DevView(ptr, (rows, cols), "<c16", (ld * 16, 16))
+    v = _DevView(ptr, (rows, cols), "<c16", (16, ld * 16))
     return torch.as_tensor(v, device="cuda")
 
 
@@ -189,14 +193,15 @@ class Operator:
             pass
 
     # -- K1
-    def apply(self, X, Y, ld: Optional[int] = None):
+    def apply(self, X, Y):
+        """Y = A X for X, Y of shape (ncols, N): one grid vector per row."""
         import torch
-        assert X.is_cuda and Y.is_cuda and X.dim() == 2 and X.shape[0] == self.N and Y.shape == X.shape
-        assert X.is_contiguous() and Y.is_contiguous()
+        assert X.is_cuda and Y.is_cuda and X.dim() == 2 and X.shape[1] == self.N and Y.shape == X.shape
+        assert X.stride(1) == 1 and Y.stride(1) == 1 and X.stride(0) == Y.stride(0)
         dt = {torch.complex128: C128, torch.complex64: C64}[X.dtype]
         assert Y.dtype == X.dtype
         s = self.lib.tsg_apply_operator(self.ctx, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
-                                        X.shape[1], ld or X.shape[1], dt)
+                                        X.shape[0], X.stride(0), dt)
         _check(self.lib, self.ctx, s)
 
     # -- Algorithm 1 planning
@@ -279,6 +284,22 @@ class Operator:
                                       T.ctypes.data_as(C.POINTER(C.c_double)))
         _check(self.lib, self.ctx, s)
         return T
+
+
+def solve_batch(operators: Sequence["Operator"], windows: Sequence[Sequence[Tuple[float, int]]],
+                opts: Optional[TsgOpts] = None, allow_noconv=False):
+    """All windows of several systems in one batched iteration
+    (tsg_solve_batch).  Returns the unique count per system and the status."""
+    lib = load()
+    ns = len(operators)
+    ctxs = (C.c_void_p * ns)(*[op.ctx for op in operators])
+    arrs = [(TsgWindow * len(w))(*[TsgWindow(float(s), int(n)) for s, n in w]) for w in windows]
+    ptrs = (C.POINTER(TsgWindow) * ns)(*[C.cast(a, C.POINTER(TsgWindow)) for a in arrs])
+    p = (C.c_int32 * ns)(*[len(w) for w in windows])
+    nu = (C.c_int32 * ns)()
+    s = lib.tsg_solve_batch(ctxs, ns, ptrs, p, C.byref(opts) if opts else None, nu)
+    status = _check(lib, operators[0].ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
+    return [nu[i] for i in range(ns)], status
 
 
 def dense_eig(H, stream=None):

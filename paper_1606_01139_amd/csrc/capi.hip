@@ -79,6 +79,7 @@ void tsg_default_opts(tsg_opts* o) {
   o->keep_lowest = 0;
   o->select = TSG_SELECT_NEAREST;
   o->bulk_tol = 1e-5;
+  o->graphs = 1;
 }
 
 tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab, void* hip_stream,
@@ -175,6 +176,37 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
   });
 }
 
+tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window* const* windows, const int32_t* p,
+                           const tsg_opts* opts, int32_t* n_unique) {
+  if (!ctx || !windows || !p) return fail(nullptr, TSG_EINVAL, "null argument");
+  if (n_sys < 1) return fail(nullptr, TSG_EINVAL, "n_sys must be >= 1");
+  for (int s = 0; s < n_sys; ++s) {
+    if (!ctx[s]) return fail(nullptr, TSG_EINVAL, "null context in batch");
+    if (p[s] < 1 || !windows[s]) return fail(ctx[s], TSG_EINVAL, "every system needs p >= 1 windows");
+  }
+  return guarded(ctx[0], [&]() {
+    tsg_opts o;
+    if (opts) o = *opts; else tsg_default_opts(&o);
+    std::vector<tsg_ctx*> cs(ctx, ctx + n_sys);
+    std::vector<std::vector<tsg::WindowSpec>> w(n_sys);
+    for (int s = 0; s < n_sys; ++s)
+      for (int j = 0; j < p[s]; ++j) w[s].push_back(tsg::WindowSpec{windows[s][j].shift, windows[s][j].nev});
+    std::vector<bool> ok;
+    tsg::solve_batch(cs, w, o, ok);
+    bool all = true;
+    for (int s = 0; s < n_sys; ++s) {
+      if (n_unique) n_unique[s] = cs[s]->nc;
+      all = all && ok[s];
+    }
+    if (!all) {
+      ctx[0]->err = "a window did not converge within max_restarts";
+      g_last_error = ctx[0]->err;
+      return TSG_ENOCONV;
+    }
+    return TSG_OK;
+  });
+}
+
 tsg_status tsg_get_eigenvalues(tsg_ctx* ctx, double* re_im, int32_t cap, int32_t* n) {
   if (!ctx || !n) return fail(ctx, TSG_EINVAL, "null argument");
   if (!ctx->have_combined) return fail(ctx, TSG_ESTATE, "no combined eigenpairs");
@@ -192,7 +224,7 @@ tsg_status tsg_get_eigenvectors(tsg_ctx* ctx, void** dev_ptr, int64_t* ld, int32
   if (!ctx || !dev_ptr || !ld || !n) return fail(ctx, TSG_EINVAL, "null argument");
   if (!ctx->have_combined) return fail(ctx, TSG_ESTATE, "no combined eigenpairs");
   *dev_ptr = ctx->Uc.p;
-  *ld = ctx->nc;
+  *ld = ctx->N;
   *n = ctx->nc;
   return TSG_OK;
 }
@@ -209,7 +241,7 @@ tsg_status tsg_get_partition(tsg_ctx* ctx, int32_t j, double* re_im, int32_t cap
     for (int i = 0; i < cnt; ++i) { re_im[2 * i] = P.eps[i].re; re_im[2 * i + 1] = P.eps[i].im; }
   }
   if (dev_ptr) *dev_ptr = P.U.p;
-  if (ld) *ld = cnt;
+  if (ld) *ld = ctx->N;
   return TSG_OK;
 }
 

@@ -1,10 +1,13 @@
 // Batched tall-skinny dense kernels for the window solver:
 //   gram        C = X^H Y        (block orthogonalisation, Rayleigh-Ritz)
-//   gemm_rows   Y = b Y + X B    (orthogonalisation update, restart rotation)
+//   gemm_cols   Y = b Y + a X B  (orthogonalisation update, restart rotation)
 //   residuals, c-products, start vectors, copies, small Cholesky.
 // Section 1 of Feldman & Zhou: the orthogonalisation of the growing subspace
 // and the Rayleigh-Ritz rotations are the O(N n^2) part of the eigensolve.
 //
+// Layout: every grid vector is contiguous (vector-major).  Column j of the
+// block of window w starts at base + w * ws + j * ld; a window's row count
+// is rows.of(w), so windows of systems of different size share one launch.
 // All reductions over the grid index go through per-chunk partial sums and a
 // second fixed-order pass, so results are bitwise reproducible run to run.
 #include <algorithm>
@@ -16,30 +19,38 @@ namespace tsg {
 namespace {
 
 constexpr int kGT = 32;   // gram tile (rows and columns of C)
-constexpr int kGK = 16;   // rows of X, Y staged per step
+constexpr int kGK = 32;   // grid rows of X, Y staged per step
 
 inline int gram_chunks(int64_t N, int r, int s, int nwin) {
   const int64_t tiles = int64_t((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT) * nwin;
   int64_t want = (4096 + tiles - 1) / tiles;
-  int64_t maxc = (N + 255) / 256;
+  int64_t maxc = (N + 511) / 512;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   return int(want);
 }
 
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
                                                            const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
-                                                           int64_t N, int r, int s, int nchunk,
+                                                           Rows rows, int r, int s, int nchunk,
                                                            c128* __restrict__ P, const int* __restrict__ wmap) {
-  __shared__ c128 Xs[kGK][kGT];
-  __shared__ c128 Ys[kGK][kGT];
+  __shared__ c128 Xs[kGK][kGT + 1];
+  __shared__ c128 Ys[kGK][kGT + 1];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int64_t N = rows.of(w);
   const int tilesJ = (s + kGT - 1) / kGT;
   const int ti = blockIdx.y / tilesJ, tj = blockIdx.y % tilesJ;
   const int chunk = blockIdx.x;
-  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  const int64_t rows_per = ((rows.N + nchunk - 1) / nchunk + kGK - 1) / kGK * kGK;
   const int64_t n0 = chunk * rows_per;
   const int64_t n1 = min(N, n0 + rows_per);
   const int t = threadIdx.x;
@@ -51,20 +62,21 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __res
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = c128{0.0, 0.0};
   for (int64_t nb = n0; nb < n1; nb += kGK) {
-    // stage kGK rows x 32 columns of X and Y (512 each, 2 per thread)
+    // stage kGK rows of 32 columns of X and Y; consecutive threads read
+    // consecutive rows of one column
     for (int e = t; e < kGK * kGT; e += 256) {
-      const int rr = e / kGT, cc = e % kGT;
+      const int cc = e / kGK, rr = e % kGK;
       const int64_t n = nb + rr;
       c128 xv{0.0, 0.0}, yv{0.0, 0.0};
       if (n < n1) {
-        if (i0 + cc < r) { cplx<TX> v = X[n * ldx + i0 + cc]; xv = c128{double(v.re), double(v.im)}; }
-        if (j0 + cc < s) { cplx<TY> v = Y[n * ldy + j0 + cc]; yv = c128{double(v.re), double(v.im)}; }
+        if (i0 + cc < r) { cplx<TX> v = X[int64_t(i0 + cc) * ldx + n]; xv = c128{double(v.re), double(v.im)}; }
+        if (j0 + cc < s) { cplx<TY> v = Y[int64_t(j0 + cc) * ldy + n]; yv = c128{double(v.re), double(v.im)}; }
       }
       Xs[rr][cc] = xv;
       Ys[rr][cc] = yv;
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < kGK; ++k) {
       c128 x0 = Xs[k][2 * ty], x1 = Xs[k][2 * ty + 1];
       c128 y0 = Ys[k][2 * tx], y1 = Ys[k][2 * tx + 1];
@@ -87,6 +99,7 @@ __global__ void gram_reduce_kernel(const c128* __restrict__ P, int nchunk, int r
                                    int64_t ldc, int64_t wsc, const int* __restrict__ wmap) {
   const int wz = blockIdx.y;
   const int w = wmap ? wmap[wz] : wz;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t rs = int64_t(r) * s;
   if (e >= rs) return;
@@ -97,111 +110,129 @@ __global__ void gram_reduce_kernel(const c128* __restrict__ P, int nchunk, int r
   C[int64_t(w) * wsc + int64_t(i) * ldc + j] = acc;
 }
 
-// ------------------------------------------------------------- gemm_rows
-template <typename T, int TS>
-__global__ __launch_bounds__(256) void gemm_rows_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx,
+// ------------------------------------------------------------- gemm_cols
+// Tile of 64 grid rows x 32 output columns per workgroup; each thread owns
+// rows tr + 16 q (q < 4) and columns 2 tc, 2 tc + 1, so that a wavefront
+// reads and writes runs of 16 consecutive grid rows.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_cols_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx,
                                                         const c128* __restrict__ B, int64_t ldb, int64_t wsb,
-                                                        cplx<T>* __restrict__ Y, int64_t ldy, int64_t wsy,
-                                                        int64_t N, int r, int s, T beta, T alpha,
+                                                        cplx<T>* __restrict__ Y, int64_t ldy, int64_t wsy, Rows rows,
+                                                        int r, int s, T beta, T alpha,
                                                         const int* __restrict__ wmap) {
-  constexpr int TR = 64, KC = 16;
-  constexpr int RPT = TR * TS / 256;  // rows per thread
-  __shared__ cplx<T> Xs[TR][KC + 1];
-  __shared__ cplx<T> Bs[KC][TS];
+  constexpr int TM = 64, TN = 32, KC = 16;
+  __shared__ cplx<T> Xs[KC][TM];
+  __shared__ cplx<T> Bs[KC][TN];
   const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
-  const int64_t r0 = int64_t(blockIdx.x) * TR;
-  const int j0 = blockIdx.y * TS;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int64_t N = rows.of(w);
+  const int64_t r0 = int64_t(blockIdx.x) * TM;
+  if (r0 >= N) return;  // whole workgroup, before any barrier
+  const int j0 = blockIdx.y * TN;
   const int t = threadIdx.x;
-  const int j = t % TS, rg = t / TS;
+  const int tr = t % 16, tc = t / 16;
   X += int64_t(w) * wsx;
   Y += int64_t(w) * wsy;
   B += int64_t(w) * wsb;
-  cplx<T> acc[RPT];
+  cplx<T> acc[4][2];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) acc[q] = cplx<T>{T(0), T(0)};
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = cplx<T>{T(0), T(0)};
   for (int k0 = 0; k0 < r; k0 += KC) {
-    for (int e = t; e < TR * KC; e += 256) {
-      const int rr = e / KC, kk = e % KC;
+    for (int e = t; e < TM * KC; e += 256) {
+      const int kk = e / TM, rr = e % TM;
       const int64_t n = r0 + rr;
-      Xs[rr][kk] = (n < N && k0 + kk < r) ? X[n * ldx + k0 + kk] : cplx<T>{T(0), T(0)};
+      Xs[kk][rr] = (n < N && k0 + kk < r) ? X[int64_t(k0 + kk) * ldx + n] : cplx<T>{T(0), T(0)};
     }
-    for (int e = t; e < KC * TS; e += 256) {
-      const int kk = e / TS, jj = e % TS;
+    for (int e = t; e < KC * TN; e += 256) {
+      const int kk = e / TN, jj = e % TN;
       c128 v = (k0 + kk < r && j0 + jj < s) ? B[int64_t(k0 + kk) * ldb + j0 + jj] : c128{0.0, 0.0};
       Bs[kk][jj] = cplx<T>{T(v.re), T(v.im)};
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (int kk = 0; kk < KC; ++kk) {
-      const cplx<T> b = Bs[kk][j];
+      const cplx<T> b0 = Bs[kk][2 * tc], b1 = Bs[kk][2 * tc + 1];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) fma_acc(acc[q], Xs[rg * RPT + q][kk], b);
+      for (int q = 0; q < 4; ++q) {
+        const cplx<T> x = Xs[kk][tr + 16 * q];
+        fma_acc(acc[q][0], x, b0);
+        fma_acc(acc[q][1], x, b1);
+      }
     }
     __syncthreads();
   }
-  if (j0 + j < s) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int64_t n = r0 + rg * RPT + q;
-      if (n < N) {
-        cplx<T>* y = Y + n * ldy + j0 + j;
-        cplx<T> v = alpha * acc[q];
-        if (beta != T(0)) v = v + beta * (*y);
-        *y = v;
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int64_t n = r0 + tr + 16 * q;
+    if (n >= N) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = j0 + 2 * tc + c;
+      if (j >= s) continue;
+      cplx<T>* y = Y + int64_t(j) * ldy + n;
+      cplx<T> v = alpha * acc[q][c];
+      if (beta != T(0)) v = v + beta * (*y);
+      *y = v;
     }
   }
 }
 
-// ------------------------------------------------------------- residuals
-constexpr int kRC = 64;  // columns per workgroup in column-sum kernels
-
+// ------------------------------------------------------------- column sums
+// One workgroup per (row chunk, column, window); per-chunk partials are
+// summed in a fixed order by colsum_reduce_kernel.
 inline int colsum_chunks(int64_t N, int s, int nwin) {
-  const int64_t groups = int64_t((s + kRC - 1) / kRC) * nwin;
+  const int64_t groups = int64_t(s) * nwin;
   int64_t want = (2048 + groups - 1) / groups;
-  int64_t maxc = (N + 1023) / 1024;
+  int64_t maxc = (N + 2047) / 2048;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   return int(want);
 }
 
+template <int NV>
+__device__ inline void block_sums(double (&v)[NV], double (*red)[4]) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = wave_sum(v[q]);
+    if (lane == 0) red[q][wv] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void residual_partial_kernel(const cplx<T>* __restrict__ U, int64_t ldu, int64_t wsu,
                                                                const cplx<T>* __restrict__ AU, int64_t lda, int64_t wsa,
-                                                               const c128* __restrict__ theta, int64_t wst, int64_t N,
+                                                               const c128* __restrict__ theta, int64_t wst, Rows rows,
                                                                int s, int nchunk, double* __restrict__ P,
                                                                const int* __restrict__ wmap) {
-  __shared__ double red[2][4][kRC];
+  __shared__ double red[2][4];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
-  const int chunk = blockIdx.x;
-  const int jj = threadIdx.x % kRC, lane = threadIdx.x / kRC;
-  const int j = blockIdx.y * kRC + jj;
-  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int chunk = blockIdx.x, j = blockIdx.y;
+  const int64_t N = rows.of(w);
+  const int64_t rows_per = (rows.N + nchunk - 1) / nchunk;
   const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
-  double r2 = 0.0, u2 = 0.0;
-  if (j < s) {
-    U += int64_t(w) * wsu + j;
-    AU += int64_t(w) * wsa + j;
-    const c128 th = theta[int64_t(w) * wst + j];
-    for (int64_t n = n0 + lane; n < n1; n += 4) {
-      cplx<T> u = U[n * ldu], au = AU[n * lda];
-      double ur = u.re, ui = u.im;
-      double rr = double(au.re) - (th.re * ur - th.im * ui);
-      double ri = double(au.im) - (th.re * ui + th.im * ur);
-      r2 += rr * rr + ri * ri;
-      u2 += ur * ur + ui * ui;
-    }
+  U += int64_t(w) * wsu + int64_t(j) * ldu;
+  AU += int64_t(w) * wsa + int64_t(j) * lda;
+  const c128 th = theta[int64_t(w) * wst + j];
+  double v[2] = {0.0, 0.0};
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += 256) {
+    cplx<T> u = U[n], au = AU[n];
+    double ur = u.re, ui = u.im;
+    double rr = double(au.re) - (th.re * ur - th.im * ui);
+    double ri = double(au.im) - (th.re * ui + th.im * ur);
+    v[0] += rr * rr + ri * ri;
+    v[1] += ur * ur + ui * ui;
   }
-  red[0][lane][jj] = r2;
-  red[1][lane][jj] = u2;
-  __syncthreads();
-  if (lane == 0 && j < s) {
-    double a = red[0][0][jj] + red[0][1][jj] + red[0][2][jj] + red[0][3][jj];
-    double b = red[1][0][jj] + red[1][1][jj] + red[1][2][jj] + red[1][3][jj];
+  block_sums<2>(v, red);
+  if (threadIdx.x == 0) {
     double* Pw = P + ((int64_t(wz) * nchunk + chunk) * s + j) * 2;
-    Pw[0] = a;
-    Pw[1] = b;
+    Pw[0] = v[0];
+    Pw[1] = v[1];
   }
 }
 
@@ -209,6 +240,7 @@ __global__ void colsum_reduce_kernel(const double* __restrict__ P, int nchunk, i
                                      const int* __restrict__ wmap) {
   const int wz = blockIdx.y;
   const int w = wmap ? wmap[wz] : wz;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= s * width) return;
   double acc = 0.0;
@@ -219,35 +251,30 @@ __global__ void colsum_reduce_kernel(const double* __restrict__ P, int nchunk, i
 template <typename T>
 __global__ __launch_bounds__(256) void cdot_partial_kernel(const cplx<T>* __restrict__ U, int64_t ldu, int64_t wsu,
                                                            const cplx<T>* __restrict__ AU, int64_t lda, int64_t wsa,
-                                                           int64_t N, int s, int nchunk, double* __restrict__ P,
+                                                           Rows rows, int s, int nchunk, double* __restrict__ P,
                                                            const int* __restrict__ wmap) {
-  __shared__ double red[4][4][kRC];
+  __shared__ double red[4][4];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
-  const int chunk = blockIdx.x;
-  const int jj = threadIdx.x % kRC, lane = threadIdx.x / kRC;
-  const int j = blockIdx.y * kRC + jj;
-  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int chunk = blockIdx.x, j = blockIdx.y;
+  const int64_t N = rows.of(w);
+  const int64_t rows_per = (rows.N + nchunk - 1) / nchunk;
   const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
+  U += int64_t(w) * wsu + int64_t(j) * ldu;
+  AU += int64_t(w) * wsa + int64_t(j) * lda;
   c128 ua{0.0, 0.0}, uu{0.0, 0.0};
-  if (j < s) {
-    U += int64_t(w) * wsu + j;
-    AU += int64_t(w) * wsa + j;
-    for (int64_t n = n0 + lane; n < n1; n += 4) {
-      cplx<T> u = U[n * ldu], au = AU[n * lda];
-      c128 ud{double(u.re), double(u.im)}, ad{double(au.re), double(au.im)};
-      fma_acc(ua, ud, ad);
-      fma_acc(uu, ud, ud);
-    }
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += 256) {
+    cplx<T> u = U[n], au = AU[n];
+    c128 ud{double(u.re), double(u.im)}, ad{double(au.re), double(au.im)};
+    fma_acc(ua, ud, ad);
+    fma_acc(uu, ud, ud);
   }
-  red[0][lane][jj] = ua.re;
-  red[1][lane][jj] = ua.im;
-  red[2][lane][jj] = uu.re;
-  red[3][lane][jj] = uu.im;
-  __syncthreads();
-  if (lane == 0 && j < s) {
+  double v[4] = {ua.re, ua.im, uu.re, uu.im};
+  block_sums<4>(v, red);
+  if (threadIdx.x == 0) {
     double* Pw = P + ((int64_t(wz) * nchunk + chunk) * s + j) * 4;
-    for (int q = 0; q < 4; ++q) Pw[q] = red[q][0][jj] + red[q][1][jj] + red[q][2][jj] + red[q][3][jj];
+    for (int q = 0; q < 4; ++q) Pw[q] = v[q];
   }
 }
 
@@ -256,20 +283,21 @@ __global__ __launch_bounds__(256) void cdot_partial_kernel(const cplx<T>* __rest
 template <typename T>
 __global__ void resblock_kernel(const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ AU, int64_t ld, int64_t ws,
                                 const c128* __restrict__ theta, int64_t wst, const int* __restrict__ sel, int b,
-                                cplx<T>* __restrict__ F, int64_t ldf, int64_t wsf, int64_t N,
+                                cplx<T>* __restrict__ F, int64_t ldf, int64_t wsf, Rows rows,
                                 const int* __restrict__ wmap) {
-  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= N * b) return;
-  const int64_t n = e / b;
-  const int q = int(e % b);
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int q = blockIdx.y;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= rows.of(w)) return;
   const int col = sel[w * b + q];
   if (col < 0) return;
   const c128 th = theta[int64_t(w) * wst + col];
-  const cplx<T> u = U[int64_t(w) * ws + n * ld + col], au = AU[int64_t(w) * ws + n * ld + col];
+  const int64_t off = int64_t(w) * ws + int64_t(col) * ld + n;
+  const cplx<T> u = U[off], au = AU[off];
   const double rr = double(au.re) - (th.re * double(u.re) - th.im * double(u.im));
   const double ri = double(au.im) - (th.re * double(u.im) + th.im * double(u.re));
-  F[int64_t(w) * wsf + n * ldf + q] = cplx<T>{T(rr), T(ri)};
+  F[int64_t(w) * wsf + int64_t(q) * ldf + n] = cplx<T>{T(rr), T(ri)};
 }
 
 // ------------------------------------------------------------- misc
@@ -281,40 +309,40 @@ __device__ inline uint64_t mix64(uint64_t z) {
 }
 
 template <typename T>
-__global__ void random_kernel(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, uint64_t seed,
+__global__ void random_kernel(cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, uint64_t seed,
                               const int* __restrict__ wmap) {
-  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= N * s) return;
-  const int64_t n = e / s;
-  const int j = int(e % s);
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int j = blockIdx.y;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= rows.of(w)) return;
   uint64_t h = mix64(seed ^ mix64(uint64_t(w) * 0x100000001B3ull + uint64_t(j)) ^ mix64(uint64_t(n) + 0x5851F42Dull));
   double u = double(h >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
-  X[int64_t(w) * wsx + n * ldx + j] = cplx<T>{T(2.0 * u - 1.0), T(0)};
+  X[int64_t(w) * wsx + int64_t(j) * ldx + n] = cplx<T>{T(2.0 * u - 1.0), T(0)};
 }
 
 template <typename TX, typename TY>
 __global__ void copy_kernel(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy,
-                            int64_t N, int s, const int* __restrict__ wmap) {
-  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= N * s) return;
-  const int64_t n = e / s;
-  const int j = int(e % s);
-  cplx<TX> v = X[int64_t(w) * wsx + n * ldx + j];
-  Y[int64_t(w) * wsy + n * ldy + j] = cplx<TY>{TY(v.re), TY(v.im)};
+                            Rows rows, const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int j = blockIdx.y;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= rows.of(w)) return;
+  cplx<TX> v = X[int64_t(w) * wsx + int64_t(j) * ldx + n];
+  Y[int64_t(w) * wsy + int64_t(j) * ldy + n] = cplx<TY>{TY(v.re), TY(v.im)};
 }
 
 template <typename T>
-__global__ void scale_kernel(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s,
+__global__ void scale_kernel(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int s, Rows rows,
                              const int* __restrict__ wmap) {
-  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= N * s) return;
-  const int64_t n = e / s;
-  const int j = int(e % s);
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int j = blockIdx.y;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= rows.of(w)) return;
   c128 f = scale[int64_t(w) * s + j];
-  cplx<T>* y = Y + int64_t(w) * wsy + n * ldy + j;
+  cplx<T>* y = Y + int64_t(w) * wsy + int64_t(j) * ldy + n;
   cplx<T> v = *y;
   *y = cplx<T>{T(f.re * v.re - f.im * v.im), T(f.re * v.im + f.im * v.re)};
 }
@@ -326,6 +354,7 @@ __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rin
                                     const int* __restrict__ wmap) {
   extern __shared__ c128 L[];  // b*b: R (upper), row-major
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const c128* Gw = G + int64_t(w) * wsg;
   c128* Ri = Rinv + int64_t(w) * wsr;
   const int t = threadIdx.x;
@@ -363,6 +392,8 @@ __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rin
   }
 }
 
+inline dim3 col_grid(int64_t N, int s, int nwin) { return dim3(unsigned((N + 255) / 256), unsigned(s), unsigned(nwin)); }
+
 }  // namespace
 
 // Sized for every active-window count 1..nwin (the chunk count depends on it).
@@ -373,48 +404,42 @@ int64_t gram_workspace(int64_t N, int r, int s, int nwin) {
 }
 
 template <typename TX, typename TY>
-void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy, int64_t N,
+void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy, Rows rows,
           int r, int s, c128* C, int64_t ldc, int64_t wsc, int nwin, c128* partials, int64_t cap, hipStream_t st,
           const int* wmap) {
   if (nwin <= 0 || r <= 0 || s <= 0) return;
   const int64_t per = int64_t(nwin) * r * s;
   if (cap < per) throw DeviceError("gram: partial workspace too small");
-  const int nchunk = int(std::min<int64_t>(gram_chunks(N, r, s, nwin), cap / per));
+  const int nchunk = int(std::min<int64_t>(gram_chunks(rows.N, r, s, nwin), cap / per));
   const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
   hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
-                     ldy, wsy, N, r, s, nchunk, partials, wmap);
+                     ldy, wsy, rows, r, s, nchunk, partials, wmap);
   const int64_t rs = int64_t(r) * s;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(unsigned((rs + 255) / 256), nwin), dim3(256), 0, st, partials, nchunk,
                      r, s, C, ldc, wsc, wmap);
 }
 
 template <typename T>
-void gemm_rows(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb, cplx<T>* Y,
-               int64_t ldy, int64_t wsy, int64_t N, int r, int s, double beta, int nwin, hipStream_t st,
+void gemm_cols(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb, cplx<T>* Y,
+               int64_t ldy, int64_t wsy, Rows rows, int r, int s, double beta, int nwin, hipStream_t st,
                const int* wmap, double alpha) {
   if (nwin <= 0 || s <= 0) return;
-  const unsigned rt = unsigned((N + 63) / 64);
-  if (s <= 16) {
-    hipLaunchKernelGGL((gemm_rows_kernel<T, 16>), dim3(rt, 1, nwin), dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y,
-                       ldy, wsy, N, r, s, T(beta), T(alpha), wmap);
-  } else {
-    hipLaunchKernelGGL((gemm_rows_kernel<T, 32>), dim3(rt, unsigned((s + 31) / 32), nwin), dim3(256), 0, st, X, ldx,
-                       wsx, B, ldb, wsb, Y, ldy, wsy, N, r, s, T(beta), T(alpha), wmap);
-  }
+  hipLaunchKernelGGL((gemm_cols_kernel<T>), dim3(unsigned((rows.N + 63) / 64), unsigned((s + 31) / 32), nwin),
+                     dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy, wsy, rows, r, s, T(beta), T(alpha), wmap);
 }
 
 template <typename T>
 void residual_block(const cplx<T>* U, const cplx<T>* AU, int64_t ld, int64_t ws, const c128* theta, int64_t wst,
-                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, int64_t N, int nwin, hipStream_t st,
+                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, Rows rows, int nwin, hipStream_t st,
                     const int* wmap) {
   if (nwin <= 0 || b <= 0) return;
-  hipLaunchKernelGGL((resblock_kernel<T>), dim3(unsigned((N * b + 255) / 256), nwin), dim3(256), 0, st, U, AU, ld,
-                     ws, theta, wst, sel, b, F, ldf, wsf, N, wmap);
+  hipLaunchKernelGGL((resblock_kernel<T>), col_grid(rows.N, b, nwin), dim3(256), 0, st, U, AU, ld, ws, theta, wst,
+                     sel, b, F, ldf, wsf, rows, wmap);
 }
 template void residual_block<double>(const c128*, const c128*, int64_t, int64_t, const c128*, int64_t, const int*,
-                                     int, c128*, int64_t, int64_t, int64_t, int, hipStream_t, const int*);
+                                     int, c128*, int64_t, int64_t, Rows, int, hipStream_t, const int*);
 template void residual_block<float>(const c64*, const c64*, int64_t, int64_t, const c128*, int64_t, const int*, int,
-                                    c64*, int64_t, int64_t, int64_t, int, hipStream_t, const int*);
+                                    c64*, int64_t, int64_t, Rows, int, hipStream_t, const int*);
 
 int64_t residual_workspace(int64_t N, int s, int nwin) {
   int64_t best = 0;
@@ -424,54 +449,52 @@ int64_t residual_workspace(int64_t N, int s, int nwin) {
 
 template <typename T>
 void residual_norms(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
-                    const c128* theta, int64_t wst, int64_t N, int s, int nwin, double* out, double* partials,
+                    const c128* theta, int64_t wst, Rows rows, int s, int nwin, double* out, double* partials,
                     int64_t cap, hipStream_t st, const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
   const int64_t per = int64_t(nwin) * s * 2;
   if (cap < per) throw DeviceError("residual_norms: partial workspace too small");
-  const int nchunk = int(std::min<int64_t>(colsum_chunks(N, s, nwin), cap / per));
-  hipLaunchKernelGGL((residual_partial_kernel<T>), dim3(nchunk, (s + kRC - 1) / kRC, nwin), dim3(256), 0, st, U, ldu,
-                     wsu, AU, lda, wsa, theta, wst, N, s, nchunk, partials, wmap);
+  const int nchunk = int(std::min<int64_t>(colsum_chunks(rows.N, s, nwin), cap / per));
+  hipLaunchKernelGGL((residual_partial_kernel<T>), dim3(nchunk, s, nwin), dim3(256), 0, st, U, ldu, wsu, AU, lda,
+                     wsa, theta, wst, rows, s, nchunk, partials, wmap);
   hipLaunchKernelGGL(colsum_reduce_kernel, dim3((2 * s + 255) / 256, nwin), dim3(256), 0, st, partials, nchunk, s, 2,
                      out, wmap);
 }
 
 template <typename T>
-void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa, int64_t N, int s,
+void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa, Rows rows, int s,
            int nwin, c128* out, double* partials, int64_t cap, hipStream_t st, const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
   const int64_t per = int64_t(nwin) * s * 4;
   if (cap < per) throw DeviceError("cdots: partial workspace too small");
-  const int nchunk = int(std::min<int64_t>(colsum_chunks(N, s, nwin), cap / per));
-  double* P = partials;
-  hipLaunchKernelGGL((cdot_partial_kernel<T>), dim3(nchunk, (s + kRC - 1) / kRC, nwin), dim3(256), 0, st, U, ldu, wsu,
-                     AU, lda, wsa, N, s, nchunk, P, wmap);
-  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((4 * s + 255) / 256, nwin), dim3(256), 0, st, P, nchunk, s, 4,
+  const int nchunk = int(std::min<int64_t>(colsum_chunks(rows.N, s, nwin), cap / per));
+  hipLaunchKernelGGL((cdot_partial_kernel<T>), dim3(nchunk, s, nwin), dim3(256), 0, st, U, ldu, wsu, AU, lda, wsa,
+                     rows, s, nchunk, partials, wmap);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((4 * s + 255) / 256, nwin), dim3(256), 0, st, partials, nchunk, s, 4,
                      reinterpret_cast<double*>(out), wmap);
 }
 
 template <typename T>
-void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, int nwin, uint64_t seed, hipStream_t st,
+void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, uint64_t seed, hipStream_t st,
                   const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
-  hipLaunchKernelGGL((random_kernel<T>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, X, ldx, wsx, N,
-                     s, seed, wmap);
+  hipLaunchKernelGGL((random_kernel<T>), col_grid(rows.N, s, nwin), dim3(256), 0, st, X, ldx, wsx, rows, seed, wmap);
 }
 
 template <typename TX, typename TY>
-void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy, int64_t N, int s,
+void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy, Rows rows, int s,
                 int nwin, hipStream_t st, const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
-  hipLaunchKernelGGL((copy_kernel<TX, TY>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, X, ldx, wsx,
-                     Y, ldy, wsy, N, s, wmap);
+  hipLaunchKernelGGL((copy_kernel<TX, TY>), col_grid(rows.N, s, nwin), dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy,
+                     rows, wmap);
 }
 
 template <typename T>
-void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s, int nwin, hipStream_t st,
+void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, Rows rows, int s, int nwin, hipStream_t st,
                 const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
-  hipLaunchKernelGGL((scale_kernel<T>), dim3(unsigned((N * s + 255) / 256), nwin), dim3(256), 0, st, Y, ldy, wsy,
-                     scale, N, s, wmap);
+  hipLaunchKernelGGL((scale_kernel<T>), col_grid(rows.N, s, nwin), dim3(256), 0, st, Y, ldy, wsy, scale, s, rows,
+                     wmap);
 }
 
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
@@ -482,22 +505,22 @@ void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, in
 }
 
 #define TSG_INST_T(T)                                                                                              \
-  template void gemm_rows<T>(const cplx<T>*, int64_t, int64_t, const c128*, int64_t, int64_t, cplx<T>*, int64_t,  \
-                             int64_t, int64_t, int, int, double, int, hipStream_t, const int*, double);                               \
+  template void gemm_cols<T>(const cplx<T>*, int64_t, int64_t, const c128*, int64_t, int64_t, cplx<T>*, int64_t,  \
+                             int64_t, Rows, int, int, double, int, hipStream_t, const int*, double);               \
   template void residual_norms<T>(const cplx<T>*, int64_t, int64_t, const cplx<T>*, int64_t, int64_t, const c128*, \
-                                  int64_t, int64_t, int, int, double*, double*, int64_t, hipStream_t, const int*);                     \
-  template void cdots<T>(const cplx<T>*, int64_t, int64_t, const cplx<T>*, int64_t, int64_t, int64_t, int, int,    \
-                         c128*, double*, int64_t, hipStream_t, const int*);                                                               \
-  template void random_block<T>(cplx<T>*, int64_t, int64_t, int64_t, int, int, uint64_t, hipStream_t, const int*); \
-  template void scale_cols<T>(cplx<T>*, int64_t, int64_t, const c128*, int64_t, int, int, hipStream_t, const int*);
+                                  int64_t, Rows, int, int, double*, double*, int64_t, hipStream_t, const int*);    \
+  template void cdots<T>(const cplx<T>*, int64_t, int64_t, const cplx<T>*, int64_t, int64_t, Rows, int, int,       \
+                         c128*, double*, int64_t, hipStream_t, const int*);                                         \
+  template void random_block<T>(cplx<T>*, int64_t, int64_t, Rows, int, int, uint64_t, hipStream_t, const int*);   \
+  template void scale_cols<T>(cplx<T>*, int64_t, int64_t, const c128*, Rows, int, int, hipStream_t, const int*);
 TSG_INST_T(double)
 TSG_INST_T(float)
 
 #define TSG_INST_2(TX, TY)                                                                                           \
-  template void gram<TX, TY>(const cplx<TX>*, int64_t, int64_t, const cplx<TY>*, int64_t, int64_t, int64_t, int, \
-                             int, c128*, int64_t, int64_t, int, c128*, int64_t, hipStream_t, const int*);         \
-  template void copy_block<TX, TY>(const cplx<TX>*, int64_t, int64_t, cplx<TY>*, int64_t, int64_t, int64_t, int,  \
-                                   int, hipStream_t, const int*);
+  template void gram<TX, TY>(const cplx<TX>*, int64_t, int64_t, const cplx<TY>*, int64_t, int64_t, Rows, int, int, \
+                             c128*, int64_t, int64_t, int, c128*, int64_t, hipStream_t, const int*);                 \
+  template void copy_block<TX, TY>(const cplx<TX>*, int64_t, int64_t, cplx<TY>*, int64_t, int64_t, Rows, int, int, \
+                                   hipStream_t, const int*);
 TSG_INST_2(double, double)
 TSG_INST_2(float, float)
 TSG_INST_2(float, double)

@@ -61,7 +61,7 @@ struct Partition {
   double shift = 0.0;
   int nev = 0;
   std::vector<c128> eps;   // ascending real part
-  DevArr<c128> U;          // N x n (ld = n), c-normalised
+  DevArr<c128> U;          // N x n, contiguous columns (ld = N), c-normalised
   tsg_window_stats stats{};
 };
 
@@ -84,6 +84,8 @@ struct tsg_ctx {
   double vmin = 0.0, vmax = 0.0, gmax = 0.0;
   tsg::DevArr<double> V, gam, gL, gR;      // FP64 operator data (gam, gL, gR per z plane)
   tsg::DevArr<float> Vf, gamf;             // complex64 path
+  tsg::SysDesc sys{};                      // this system for the stencil
+  tsg::DevArr<tsg::SysDesc> sysd;          // the same, on the device
   std::vector<tsg::Partition> parts;
   // combined set
   bool have_combined = false;
@@ -106,6 +108,11 @@ void apply_operator(tsg_ctx* c, const void* X, void* Y, int ncols, int64_t ld, i
 // Solves the windows together and stores them as new partitions (appended).
 // Returns true when every window converged.
 bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_opts& o);
+// Windows of several systems in one batched iteration; system s's
+// partitions replace those of ctx[s] and are combined.  ok[s] reports
+// convergence of every window of system s.
+void solve_batch(const std::vector<tsg_ctx*>& ctx, const std::vector<std::vector<WindowSpec>>& wins,
+                 const tsg_opts& o, std::vector<bool>& ok);
 void combine(tsg_ctx* c, int keep_lowest);
 void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
                   double* e_range);

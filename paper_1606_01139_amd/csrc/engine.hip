@@ -40,63 +40,134 @@ double fd_coef(int R, int m) {
   return (m % 2 == 1) ? v : -v;
 }
 
-template <typename T> const T* opV(const tsg_ctx* c);
-template <> const double* opV<double>(const tsg_ctx* c) { return c->V.p; }
-template <> const float* opV<float>(const tsg_ctx* c) { return c->Vf.p; }
-template <typename T> const T* opG(const tsg_ctx* c);
-template <> const double* opG<double>(const tsg_ctx* c) { return c->gam.p; }
-template <> const float* opG<float>(const tsg_ctx* c) { return c->gamf.p; }
-
-template <typename T>
-void stencil(const tsg_ctx* c, const cplx<T>* X, int64_t ldx, int64_t wsx, cplx<T>* Y, int64_t ldy, int64_t wsy,
-             int ncols, int nwin, const int* wmap) {
-  StencilArgs<T> a;
-  a.X = X; a.ldx = ldx; a.wsx = wsx;
-  a.Y = Y; a.ldy = ldy; a.wsy = wsy;
-  a.ncols = ncols;
-  a.nx = c->nx; a.ny = c->ny; a.nz = c->nz; a.radius = c->R;
-  a.V = opV<T>(c);
-  a.gamma = opG<T>(c);
-  a.diag0 = T(c->diag0);
-  for (int m = 0; m < 7; ++m) a.coef[m] = T(c->coef[m]);
-  a.shifts = nullptr;
-  a.wmap = wmap;
-  const int64_t base = ((int64_t(c->nx) * c->ny * ncols + 255) / 256) * std::max(nwin, 1);
-  int64_t nzc = (2048 + base - 1) / base;
-  nzc = std::max<int64_t>(1, std::min<int64_t>(nzc, std::max(1, c->nz / 4)));
-  a.zchunk = int((c->nz + nzc - 1) / nzc);
-  launch_stencil<T>(a, nwin, c->st);
-}
-
 void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw DeviceError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
 int round_up(int x, int b) { return ((x + b - 1) / b) * b; }
+int64_t round_up64(int64_t x, int64_t b) { return ((x + b - 1) / b) * b; }
 
 // TSG_TRACE=1 in the environment prints one line per restart and window.
 bool trace_on() {
   static const bool on = [] { const char* v = std::getenv("TSG_TRACE"); return v && v[0] == '1'; }();
   return on;
 }
+// Restart cycles are replayed from a captured hipGraph unless the options or
+// TSG_NO_GRAPH=1 (or the K4 phase profiler) turn it off.
+bool graphs_allowed() {
+  static const bool ok = [] {
+    const char* a = std::getenv("TSG_NO_GRAPH");
+    const char* b = std::getenv("TSG_K4PROF");
+    return !(a && a[0] == '1') && !(b && b[0] == '1');
+  }();
+  return ok;
+}
+
+// ------------------------------------------------------------------ systems
+// The grid systems of one batched solve and the window -> system map.  A
+// single system needs no device tables beyond its own descriptor.
+struct Systems {
+  std::vector<tsg_ctx*> ctx;
+  std::vector<int> wsys_h;                 // per window
+  DevArr<SysDesc> table_own;
+  DevArr<int> wsys_own, rows_own;
+  const SysDesc* table = nullptr;
+  const int* wsys = nullptr;               // null: every window on system 0
+  const int* rows = nullptr;               // null: every window has Nmax rows
+  int64_t Nmax = 0, Nmin = 0, ldN = 0;
+  int nx = 0, ny = 0, nz = 0, R = 6;
+  hipStream_t st = nullptr;
+  Rows rows_arg() const { return Rows{Nmax, rows}; }
+  tsg_ctx* of(int w) const { return ctx[wsys_h.empty() ? 0 : wsys_h[w]]; }
+};
+
+void one_system(Systems& S, tsg_ctx* c, hipStream_t st) {
+  S.ctx = {c};
+  S.table = c->sysd.p;
+  S.Nmax = S.Nmin = c->N;
+  S.ldN = round_up64(c->N, 64);
+  S.nx = c->nx; S.ny = c->ny; S.nz = c->nz; S.R = c->R;
+  S.st = st;
+}
+
+void many_systems(Systems& S, const std::vector<tsg_ctx*>& ctx, const std::vector<int>& wsys, hipStream_t st) {
+  S.ctx = ctx;
+  S.wsys_h = wsys;
+  S.st = st;
+  std::vector<SysDesc> tab(ctx.size());
+  S.Nmax = 0;
+  S.Nmin = ctx[0]->N;
+  S.R = ctx[0]->R;
+  for (size_t s = 0; s < ctx.size(); ++s) {
+    tab[s] = ctx[s]->sys;
+    S.Nmax = std::max(S.Nmax, ctx[s]->N);
+    S.Nmin = std::min(S.Nmin, ctx[s]->N);
+    S.nx = std::max(S.nx, ctx[s]->nx); S.ny = std::max(S.ny, ctx[s]->ny); S.nz = std::max(S.nz, ctx[s]->nz);
+    if (ctx[s]->R != S.R) throw InvalidArg("all systems of a batch must use the same fd_radius");
+  }
+  S.ldN = round_up64(S.Nmax, 64);
+  std::vector<int> rows(wsys.size());
+  for (size_t w = 0; w < wsys.size(); ++w) rows[w] = int(ctx[wsys[w]]->N);
+  S.table_own.alloc(tab.size());
+  S.wsys_own.alloc(wsys.size());
+  S.rows_own.alloc(rows.size());
+  check(hipMemcpyAsync(S.table_own.p, tab.data(), sizeof(SysDesc) * tab.size(), hipMemcpyHostToDevice, st), "sys");
+  check(hipMemcpyAsync(S.wsys_own.p, wsys.data(), sizeof(int) * wsys.size(), hipMemcpyHostToDevice, st), "wsys");
+  check(hipMemcpyAsync(S.rows_own.p, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, st), "rows");
+  check(hipStreamSynchronize(st), "sync");
+  S.table = S.table_own.p;
+  S.wsys = S.wsys_own.p;
+  S.rows = S.rows_own.p;
+}
+
+template <typename T>
+void stencil(const Systems& S, const cplx<T>* X, int64_t ldx, int64_t wsx, cplx<T>* Y, int64_t ldy, int64_t wsy,
+             int ncols, int nwin, const int* wmap) {
+  StencilArgs<T> a;
+  a.X = X; a.ldx = ldx; a.wsx = wsx;
+  a.Y = Y; a.ldy = ldy; a.wsy = wsy;
+  a.ncols = ncols;
+  a.radius = S.R;
+  a.sys = S.table;
+  a.wsys = S.wsys;
+  a.wmap = wmap;
+  stencil_geometry<T>(a, S.nx, S.ny, S.nz, nwin);
+  launch_stencil<T>(a, nwin, S.nz, S.st);
+}
+
+// Private non-blocking stream of one solve (graph capture needs a stream
+// other than the null stream); the caller's stream is drained first.
+struct SolveStream {
+  hipStream_t s = nullptr;
+  explicit SolveStream(hipStream_t user) {
+    check(hipStreamSynchronize(user), "sync");
+    check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  }
+  ~SolveStream() {
+    if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+  }
+};
 
 // ------------------------------------------------------------------ batch
 // Device state of one batched solve in storage precision T.  Window w's
-// basis V (N x m, point-major, ld m) starts at V + w * N * m; likewise AV and
-// the rotation targets Vr, AVr.  F holds each window's continuation block.
+// basis V (ldN x m, contiguous columns) starts at V + w * ldN * m; likewise
+// AV and the rotation targets Vr, AVr.  F holds each window's continuation
+// block (ldN x b).
 template <typename T> struct Batch {
   int nw = 0, m = 0, k = 0, b = 0, nv = 0;
-  int64_t N = 0;
+  int64_t ldN = 0;
+  Rows rows;
   DevArr<cplx<T>> V, AV, Vr, AVr, F, Ft;
   DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, part;
   DevArr<double> res, sig;
   DevArr<int> flags, info, wmap, sel;
 
-  void alloc(int nw_, int64_t N_, int m_, int k_, int b_, int nv_) {
-    nw = nw_; N = N_; m = m_; k = k_; b = b_; nv = nv_;
-    const size_t nm = size_t(N) * m * nw;
+  void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
+    nw = nw_; ldN = S.ldN; rows = S.rows_arg(); m = m_; k = k_; b = b_; nv = nv_;
+    const int64_t N = S.Nmax;
+    const size_t nm = size_t(ldN) * m * nw;
     V.alloc(nm); AV.alloc(nm); Vr.alloc(nm); AVr.alloc(nm);
-    F.alloc(size_t(N) * b * nw); Ft.alloc(size_t(N) * b * nw);
+    F.alloc(size_t(ldN) * b * nw); Ft.alloc(size_t(ldN) * b * nw);
     H.alloc(size_t(m) * m * nw); Ys.alloc(size_t(m) * m * nw);
     work.alloc(size_t(smalleig_workspace(m)) * nw);
     theta.alloc(size_t(m) * nw);
@@ -114,30 +185,33 @@ template <typename T> struct Batch {
     sig.alloc(size_t(nw));
     flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
   }
-  int64_t ws() const { return N * m; }
+  int64_t ws() const { return ldN * m; }
 };
 
-// dest (N x b per window, row stride ldd, window stride wsd) is made
+// dest (ldN x b per window, column stride ldd, window stride wsd) is made
 // orthonormal against the first J basis columns (CGS2) and within itself
 // (Cholesky-QR, twice).
 template <typename T>
-void orthonormalize(tsg_ctx* c, Batch<T>& B, cplx<T>* dest, int64_t ldd, int64_t wsd, int J, int na) {
-  const int b = B.b;
+void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, int64_t wsd, int J) {
+  const int b = B.b, nw = B.nw;
   const int* wm = B.wmap.p;
+  hipStream_t st = S.st;
+  const int64_t ldN = B.ldN;
   for (int pass = 0; pass < 2 && J > 0; ++pass) {
-    gram<T, T>(B.V.p, B.m, B.ws(), dest, ldd, wsd, B.N, J, b, B.C.p, b, int64_t(B.m) * b, na, B.part.p,
-               int64_t(B.part.n), c->st, wm);
-    gemm_rows<T>(B.V.p, B.m, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.N, J, b, 1.0, na, c->st, wm, -1.0);
+    gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, int64_t(B.m) * b, nw, B.part.p,
+               int64_t(B.part.n), st, wm);
+    gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wm,
+                 -1.0);
   }
   for (int pass = 0; pass < 2; ++pass) {
     cplx<T>* src = pass == 0 ? dest : B.Ft.p;
-    int64_t lds = pass == 0 ? ldd : b, wss = pass == 0 ? wsd : B.N * b;
+    int64_t lds = pass == 0 ? ldd : ldN, wss = pass == 0 ? wsd : ldN * b;
     cplx<T>* dst = pass == 0 ? B.Ft.p : dest;
-    int64_t ldo = pass == 0 ? b : ldd, wso = pass == 0 ? B.N * b : wsd;
-    gram<T, T>(src, lds, wss, src, lds, wss, B.N, b, b, B.G.p, b, int64_t(b) * b, na, B.part.p,
-               int64_t(B.part.n), c->st, wm);
-    cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, na, c->st, wm);
-    gemm_rows<T>(src, lds, wss, B.Rinv.p, b, int64_t(b) * b, dst, ldo, wso, B.N, b, b, 0.0, na, c->st, wm, 1.0);
+    int64_t ldo = pass == 0 ? ldN : ldd, wso = pass == 0 ? ldN * b : wsd;
+    gram<T, T>(src, lds, wss, src, lds, wss, B.rows, b, b, B.G.p, b, int64_t(b) * b, nw, B.part.p,
+               int64_t(B.part.n), st, wm);
+    cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, nw, st, wm);
+    gemm_cols<T>(src, lds, wss, B.Rinv.p, b, int64_t(b) * b, dst, ldo, wso, B.rows, b, b, 0.0, nw, st, wm, 1.0);
   }
 }
 
@@ -150,38 +224,92 @@ struct WinOut {
   std::vector<double> rho;
 };
 
-// Runs the batched iteration on windows of one precision.  init_from:
-// nullptr = random start; otherwise per-window [V_k | F] blocks (N x (k+b),
-// complex64, ld k+b) from a complex64 phase.  On convergence of window w,
-// `save` receives the current device state.
+// A captured restart cycle, one per assignment of the two basis buffers.
+struct CycleGraphs {
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  ~CycleGraphs() {
+    for (auto& e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
+};
+
+// Runs the batched iteration on windows of one precision.  Every launch
+// covers all nw window slots; slots of finished windows hold -1 in wmap and
+// their workgroups exit at once, so one captured cycle stays valid as
+// windows converge.  init_from: nullptr = random start; otherwise
+// per-window [V_k | F] blocks (ldN x (k+b), complex64) from a complex64
+// phase.  On convergence of window w, `save` receives the current device
+// state.
 template <typename T, typename Save>
-void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int mode, double tol, int max_restarts,
-             uint64_t seed, const cplx<float>* init_from, std::vector<WinOut>& out, Save&& save,
-             double stall_floor = 0.0, bool davidson = false) {
+void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins, const std::vector<double>& normA,
+             int mode, double tol, int max_restarts, uint64_t seed, const cplx<float>* init_from,
+             std::vector<WinOut>& out, Save&& save, bool use_graphs, double stall_floor = 0.0,
+             bool davidson = false) {
   const int nw = B.nw, m = B.m, k = B.k, b = B.b, nv = B.nv;
-  const int64_t N = B.N, wsV = B.ws();
-  hipStream_t st = c->st;
+  const int64_t ldN = B.ldN, wsV = B.ws();
+  hipStream_t st = S.st;
   std::vector<int> active(nw);
   std::iota(active.begin(), active.end(), 0);
-  check(hipMemcpyAsync(B.wmap.p, active.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st), "wmap");
+  std::vector<int> slots(nw);
+  auto upload_slots = [&]() {
+    for (int q = 0; q < nw; ++q) slots[q] = q < int(active.size()) ? active[q] : -1;
+    check(hipMemcpyAsync(B.wmap.p, slots.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st), "wmap");
+  };
+  upload_slots();
   std::vector<double> shifts(nw);
   for (int w = 0; w < nw; ++w) shifts[w] = wins[w].shift;
   check(hipMemcpyAsync(B.sig.p, shifts.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st), "shifts");
   out.assign(nw, WinOut{});
-  int na = nw;
+  const int* wm = B.wmap.p;
+  const Rows rows = B.rows;
   int j0 = 0;
   if (!init_from) {
-    random_block<T>(B.V.p, m, wsV, N, b, na, seed, st, B.wmap.p);
-    orthonormalize<T>(c, B, B.V.p, m, wsV, 0, na);
+    random_block<T>(B.V.p, ldN, wsV, rows, b, nw, seed, st, wm);
+    orthonormalize<T>(S, B, B.V.p, ldN, wsV, 0);
   } else {
     // promote the complex64 kept basis and continuation block, re-orthonormalise
     // block by block in this precision and recompute A V for the kept part
-    copy_block<float, T>(init_from, k + b, int64_t(N) * (k + b), B.V.p, m, wsV, N, k + b, na, st, B.wmap.p);
-    for (int j = 0; j <= k; j += b) orthonormalize<T>(c, B, B.V.p + j, m, wsV, j, na);
-    stencil<T>(c, B.V.p, m, wsV, B.AV.p, m, wsV, k, na, B.wmap.p);
+    copy_block<float, T>(init_from, ldN, ldN * (k + b), B.V.p, ldN, wsV, rows, k + b, nw, st, wm);
+    for (int j = 0; j <= k; j += b) orthonormalize<T>(S, B, B.V.p + j * ldN, ldN, wsV, j);
+    stencil<T>(S, B.V.p, ldN, wsV, B.AV.p, ldN, wsV, k, nw, wm);
     for (int w = 0; w < nw; ++w) out[w].matvecs += k;
     j0 = k;
   }
+  // expansion from column j0, projection, small eigenproblem, selection,
+  // rotation and residual norms; with `cont`, first the continuation block
+  // (and in Davidson mode the residual block that feeds it)
+  auto body = [&](int jstart, bool cont) {
+    if (cont) {
+      if (davidson)
+        residual_block<T>(B.V.p + k * ldN, B.AV.p + k * ldN, ldN, wsV, B.thsel.p, nv, B.sel.p, b, B.F.p, ldN,
+                          ldN * b, rows, nw, st, wm);
+      copy_block<T, T>(B.F.p, ldN, ldN * b, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
+      orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
+    }
+    for (int j = jstart; j < m; j += b) {
+      stencil<T>(S, B.V.p + j * ldN, ldN, wsV, B.AV.p + j * ldN, ldN, wsV, b, nw, wm);
+      const bool last = j + b >= m;
+      cplx<T>* dest = last ? B.F.p : B.V.p + (j + b) * ldN;
+      const int64_t wsd = last ? ldN * b : wsV;
+      copy_block<T, T>(B.AV.p + j * ldN, ldN, wsV, dest, ldN, wsd, rows, b, nw, st, wm);
+      orthonormalize<T>(S, B, dest, ldN, wsd, j + b);
+    }
+    gram<T, T>(B.V.p, ldN, wsV, B.AV.p, ldN, wsV, rows, m, m, B.H.p, m, int64_t(m) * m, nw, B.part.p,
+               int64_t(B.part.n), st, wm);
+    smalleig(B.H.p, int64_t(m) * m, m, B.theta.p, m, B.Ys.p, int64_t(m) * m, B.work.p, smalleig_workspace(m),
+             B.info.p, nw, st, wm);
+    select_restart(B.theta.p, m, B.Ys.p, int64_t(m) * m, m, B.sig.p, mode, k, nv, B.Ysel.p, int64_t(m) * (k + nv),
+                   B.thsel.p, nv, nw, st, wm);
+    // rotation: [V Q_k | V Y_nev] and the same for A V
+    gemm_cols<T>(B.V.p, ldN, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.Vr.p, ldN, wsV, rows, m, k + nv, 0.0,
+                 nw, st, wm);
+    gemm_cols<T>(B.AV.p, ldN, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.AVr.p, ldN, wsV, rows, m, k + nv, 0.0,
+                 nw, st, wm);
+    residual_norms<T>(B.Vr.p + k * ldN, ldN, wsV, B.AVr.p + k * ldN, ldN, wsV, B.thsel.p, nv, rows, nv, nw, B.res.p,
+                      reinterpret_cast<double*>(B.part.p), 2 * int64_t(B.part.n), st, wm);
+  };
+  CycleGraphs graphs;
+  cplx<T>* const buf0 = B.V.p;
   // complex64 phase: a window whose worst wanted backward error stops
   // improving (no 5% gain in 8 restarts) below stall_floor is handed on, as
   // complex64 storage bounds the attainable residual
@@ -190,31 +318,24 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
   std::vector<double> hres(size_t(2) * nv * nw);
   std::vector<c128> hth(size_t(nv) * nw);
   std::vector<int> hinfo(nw);
-  for (int cyc = 0; cyc < max_restarts && na > 0; ++cyc) {
-    const int* wm = B.wmap.p;
-    for (int j = j0; j < m; j += b) {
-      stencil<T>(c, B.V.p + j, m, wsV, B.AV.p + j, m, wsV, b, na, wm);
-      for (int q = 0; q < na; ++q) out[active[q]].matvecs += b;
-      const bool last = j + b >= m;
-      cplx<T>* dest = last ? B.F.p : B.V.p + j + b;
-      const int64_t ldd = last ? b : m, wsd = last ? N * b : wsV;
-      copy_block<T, T>(B.AV.p + j, m, wsV, dest, ldd, wsd, N, b, na, st, wm);
-      orthonormalize<T>(c, B, dest, ldd, wsd, j + b, na);
+  for (int cyc = 0; cyc < max_restarts && !active.empty(); ++cyc) {
+    const bool steady = cyc > 0;
+    if (steady && use_graphs) {
+      const int par = B.V.p == buf0 ? 0 : 1;
+      if (!graphs.exec[par]) {
+        hipGraph_t g = nullptr;
+        check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture");
+        body(k, true);
+        check(hipStreamEndCapture(st, &g), "capture");
+        const hipError_t e = hipGraphInstantiate(&graphs.exec[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        check(e, "hipGraphInstantiate");
+      }
+      check(hipGraphLaunch(graphs.exec[par], st), "hipGraphLaunch");
+    } else {
+      body(steady ? k : j0, steady);
     }
-    // Rayleigh-Ritz projection and small eigenproblem
-    gram<T, T>(B.V.p, m, wsV, B.AV.p, m, wsV, N, m, m, B.H.p, m, int64_t(m) * m, na, B.part.p,
-               int64_t(B.part.n), st, wm);
-    smalleig(B.H.p, int64_t(m) * m, m, B.theta.p, m, B.Ys.p, int64_t(m) * m, B.work.p, smalleig_workspace(m),
-             B.info.p, na, st, wm);
-    select_restart(B.theta.p, m, B.Ys.p, int64_t(m) * m, m, B.sig.p, mode, k, nv, B.Ysel.p, int64_t(m) * (k + nv),
-                   B.thsel.p, nv, na, st, wm);
-    // rotation: [V Q_k | V Y_nev] and the same for A V
-    gemm_rows<T>(B.V.p, m, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.Vr.p, m, wsV, N, m, k + nv, 0.0, na, st,
-                 wm);
-    gemm_rows<T>(B.AV.p, m, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.AVr.p, m, wsV, N, m, k + nv, 0.0, na,
-                 st, wm);
-    residual_norms<T>(B.Vr.p + k, m, wsV, B.AVr.p + k, m, wsV, B.thsel.p, nv, N, nv, na, B.res.p,
-                      reinterpret_cast<double*>(B.part.p), 2 * int64_t(B.part.n), st, wm);
+    for (int w : active) out[w].matvecs += (m - (steady ? k : j0));
     check(hipMemcpyAsync(hres.data(), B.res.p, sizeof(double) * 2 * nv * nw, hipMemcpyDeviceToHost, st), "res");
     check(hipMemcpyAsync(hth.data(), B.thsel.p, sizeof(c128) * nv * nw, hipMemcpyDeviceToHost, st), "theta");
     check(hipMemcpyAsync(hinfo.data(), B.info.p, sizeof(int) * nw, hipMemcpyDeviceToHost, st), "info");
@@ -222,8 +343,7 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
     std::swap(B.V, B.Vr);
     std::swap(B.AV, B.AVr);
     std::vector<int> still;
-    for (int q = 0; q < na; ++q) {
-      const int w = active[q];
+    for (int w : active) {
       WinOut& o = out[w];
       o.restarts = cyc + 1;
       const int nev = wins[w].nev;
@@ -232,7 +352,7 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
       int nconv = 0;
       for (int i = 0; i < nev; ++i) {
         const double r2 = hres[(size_t(w) * nv + i) * 2], u2 = hres[(size_t(w) * nv + i) * 2 + 1];
-        const double rho = std::sqrt(std::max(r2, 0.0)) / (c->normA * std::sqrt(std::max(u2, 1e-300)));
+        const double rho = std::sqrt(std::max(r2, 0.0)) / (normA[w] * std::sqrt(std::max(u2, 1e-300)));
         o.rho[i] = std::isfinite(rho) ? rho : 1e300;
         nconv += (o.rho[i] <= tol) ? 1 : 0;
       }
@@ -254,10 +374,11 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
         still.push_back(w);
       }
     }
-    active = still;
-    na = int(active.size());
-    if (na == 0) break;
-    check(hipMemcpyAsync(B.wmap.p, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, st), "wmap");
+    if (still.size() != active.size()) {
+      active = still;
+      upload_slots();
+    }
+    if (active.empty()) break;
     if (davidson) {
       // after a precision change the kept basis has a residual of full rank,
       // so the next block is built from the explicit residuals of the b
@@ -270,14 +391,8 @@ void iterate(tsg_ctx* c, Batch<T>& B, const std::vector<WindowSpec>& wins, int m
         for (int q = 0; q < b && q < int(ord.size()); ++q) hsel[size_t(w) * b + q] = ord[q];
       }
       check(hipMemcpyAsync(B.sel.p, hsel.data(), sizeof(int) * hsel.size(), hipMemcpyHostToDevice, st), "sel");
-      residual_block<T>(B.V.p + k, B.AV.p + k, m, wsV, B.thsel.p, nv, B.sel.p, b, B.F.p, b, N * b, N, na, st,
-                        B.wmap.p);
       check(hipStreamSynchronize(st), "sync");  // hsel is a host temporary
     }
-    // next block: the continuation F, re-orthogonalised against the kept basis
-    copy_block<T, T>(B.F.p, b, N * b, B.V.p + k, m, wsV, N, b, na, st, B.wmap.p);
-    orthonormalize<T>(c, B, B.V.p + k, m, wsV, k, na);
-    j0 = k;
   }
 }
 
@@ -292,21 +407,23 @@ void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& 
   if (k + nvmax > m) throw InvalidArg("basis too small: keep + nev must not exceed basis");
 }
 
-// FP64 finish of one window's nev vectors (device c128, ld nev): fresh
-// A u, c-Rayleigh quotient, backward error, c-normalisation, sort by real
-// part.  Returns the partition.
-Partition finish_window(tsg_ctx* c, const WindowSpec& ws, DevArr<c128>&& U, int nev, const WinOut& o,
-                        int restarts_bulk) {
+// FP64 finish of one window's nev vectors (device c128, N x nev, ld N):
+// fresh A u, c-Rayleigh quotient, backward error, c-normalisation, sort by
+// real part.  Returns the partition.
+Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr<c128>&& U, int nev,
+                        const WinOut& o, int restarts_bulk) {
   const int64_t N = c->N;
-  hipStream_t st = c->st;
-  DevArr<c128> AU, dots, part, scale, Us;
+  Systems S;
+  one_system(S, c, st);
+  DevArr<c128> AU, dots, part;
   DevArr<double> res;
   AU.alloc(size_t(N) * nev);
-  stencil<double>(c, U.p, nev, 0, AU.p, nev, 0, nev, 1, nullptr);
+  stencil<double>(S, U.p, N, 0, AU.p, N, 0, nev, 1, nullptr);
   dots.alloc(size_t(nev) * 2);
   part.alloc(size_t(std::max(residual_workspace(N, nev, 1), int64_t(1))) * 2);
-  cdots<double>(U.p, nev, 0, AU.p, nev, 0, N, nev, 1, dots.p, reinterpret_cast<double*>(part.p),
-                2 * int64_t(part.n), st);
+  const Rows rows{N, nullptr};
+  cdots<double>(U.p, N, 0, AU.p, N, 0, rows, nev, 1, dots.p, reinterpret_cast<double*>(part.p), 2 * int64_t(part.n),
+                st);
   std::vector<c128> hd(size_t(nev) * 2);
   check(hipMemcpyAsync(hd.data(), dots.p, sizeof(c128) * 2 * nev, hipMemcpyDeviceToHost, st), "dots");
   check(hipStreamSynchronize(st), "sync");
@@ -321,7 +438,7 @@ Partition finish_window(tsg_ctx* c, const WindowSpec& ws, DevArr<c128>&& U, int 
   thd.alloc(nev);
   check(hipMemcpyAsync(thd.p, thc.data(), sizeof(c128) * nev, hipMemcpyHostToDevice, st), "thc");
   res.alloc(size_t(2) * nev);
-  residual_norms<double>(U.p, nev, 0, AU.p, nev, 0, thd.p, 0, N, nev, 1, res.p, reinterpret_cast<double*>(part.p),
+  residual_norms<double>(U.p, N, 0, AU.p, N, 0, thd.p, 0, rows, nev, 1, res.p, reinterpret_cast<double*>(part.p),
                          2 * int64_t(part.n), st);
   std::vector<double> hr(size_t(2) * nev);
   check(hipMemcpyAsync(hr.data(), res.p, sizeof(double) * 2 * nev, hipMemcpyDeviceToHost, st), "res");
@@ -343,23 +460,20 @@ Partition finish_window(tsg_ctx* c, const WindowSpec& ws, DevArr<c128>&& U, int 
   }
   // gather sorted, c-normalised columns
   std::vector<const c128*> srcs(nev);
-  std::vector<int64_t> lds(nev, nev);
   std::vector<c128> scs(nev);
   P.eps.resize(nev);
   for (int i = 0; i < nev; ++i) {
-    srcs[i] = U.p + ord[i];
+    srcs[i] = U.p + int64_t(ord[i]) * N;
     scs[i] = sc[ord[i]];
     P.eps[i] = thc[ord[i]];
   }
   DevArr<const c128*> dsrc;
-  DevArr<int64_t> dld;
   DevArr<c128> dsc;
-  dsrc.alloc(nev); dld.alloc(nev); dsc.alloc(nev);
+  dsrc.alloc(nev); dsc.alloc(nev);
   check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nev, hipMemcpyHostToDevice, st), "srcs");
-  check(hipMemcpyAsync(dld.p, lds.data(), sizeof(int64_t) * nev, hipMemcpyHostToDevice, st), "lds");
   check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nev, hipMemcpyHostToDevice, st), "sc");
   P.U.alloc(size_t(N) * nev);
-  gather_columns(P.U.p, nev, dsrc.p, dld.p, dsc.p, nev, N, st);
+  gather_columns(P.U.p, N, dsrc.p, dsc.p, nev, N, st);
   check(hipStreamSynchronize(st), "sync");
   P.stats.shift = ws.shift;
   P.stats.nev = ws.nev;
@@ -369,6 +483,86 @@ Partition finish_window(tsg_ctx* c, const WindowSpec& ws, DevArr<c128>&& U, int 
   P.stats.max_backward_error = maxrho;
   P.stats.restarts_bulk = restarts_bulk;
   return P;
+}
+
+// Solves the windows (window w on system S.of(w)); returns the partitions in
+// window order and per-window convergence.
+void solve_core(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts& o, std::vector<Partition>& parts,
+                std::vector<bool>& conv) {
+  const int nw = int(wins.size());
+  if (nw < 1) throw InvalidArg("need at least one window");
+  int nvmax = 0;
+  for (const auto& w : wins) {
+    if (w.nev < 1) throw InvalidArg("nev must be >= 1");
+    if (!std::isfinite(w.shift)) throw InvalidArg("shift must be finite");
+    nvmax = std::max(nvmax, w.nev);
+  }
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) throw InvalidArg("tol must be positive");
+  if (o.max_restarts < 1) throw InvalidArg("max_restarts must be >= 1");
+  if (o.precision != TSG_FP64 && o.precision != TSG_FP32_BULK) throw InvalidArg("unknown precision");
+  if (o.select < 0 || o.select > 2) throw InvalidArg("unknown selection");
+  int m, k, b;
+  choose_sizes(S.Nmin, nvmax, o, m, k, b);
+  if (int64_t(m) >= S.Nmin) throw InvalidArg("grid too small for the basis size");
+  const int64_t ldN = S.ldN;
+  hipStream_t st = S.st;
+  const bool use_graphs = o.graphs != 0 && graphs_allowed();
+  std::vector<double> normA(nw);
+  for (int w = 0; w < nw; ++w) normA[w] = S.of(w)->normA;
+  std::vector<DevArr<c128>> results(nw);
+  std::vector<WinOut> outs;
+  std::vector<int> bulk_restarts(nw, 0);
+  std::vector<int64_t> bulk_mv(nw, 0);
+  auto save_fp64 = [&](Batch<double>& Bd) {
+    return [&](int w) {
+      const int64_t Nw = S.of(w)->N;
+      results[w].alloc(size_t(Nw) * wins[w].nev);
+      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * Nw, Bd.V.p + size_t(w) * ldN * m + size_t(k) * ldN,
+                             sizeof(c128) * ldN, sizeof(c128) * Nw, wins[w].nev, hipMemcpyDeviceToDevice, st),
+            "save");
+    };
+  };
+  if (o.precision == TSG_FP32_BULK) {
+    // complex64 phase to bulk_tol; keep [V_k | F] of each window for the FP64 phase
+    DevArr<c64> hand;
+    hand.alloc(size_t(ldN) * (k + b) * nw);
+    {
+      Batch<float> Bf;
+      Bf.alloc(nw, S, m, k, b, nvmax);
+      std::vector<WinOut> fo;
+      const double btol = std::max(o.bulk_tol > 0 ? o.bulk_tol : 1e-5, o.tol);
+      iterate<float>(S, Bf, wins, normA, o.select, btol, o.max_restarts, o.seed, nullptr, fo, [&](int w) {
+        // V (already swapped) holds the kept basis in columns [0, k); F the continuation
+        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b), Bf.V.p + size_t(w) * ldN * m,
+                             sizeof(c64) * ldN * k, hipMemcpyDeviceToDevice, st), "handoff");
+        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b) + size_t(k) * ldN, Bf.F.p + size_t(w) * ldN * b,
+                             sizeof(c64) * ldN * b, hipMemcpyDeviceToDevice, st), "handoff");
+      }, use_graphs, 100.0 * btol);
+      for (int w = 0; w < nw; ++w) { bulk_restarts[w] = fo[w].restarts; bulk_mv[w] = fo[w].matvecs; }
+    }
+    Batch<double> Bd;
+    Bd.alloc(nw, S, m, k, b, nvmax);
+    iterate<double>(S, Bd, wins, normA, o.select, o.tol, o.max_restarts, o.seed + 1, hand.p, outs, save_fp64(Bd),
+                    use_graphs, 0.0, true);
+  } else {
+    Batch<double> Bd;
+    Bd.alloc(nw, S, m, k, b, nvmax);
+    iterate<double>(S, Bd, wins, normA, o.select, o.tol, o.max_restarts, o.seed, nullptr, outs, save_fp64(Bd),
+                    use_graphs);
+  }
+  check(hipStreamSynchronize(st), "sync");
+  parts.clear();
+  conv.assign(nw, true);
+  for (int w = 0; w < nw; ++w) {
+    outs[w].matvecs += bulk_mv[w];
+    Partition P = finish_window(S.of(w), st, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w]);
+    if (!outs[w].converged || P.stats.max_backward_error > o.tol) {
+      conv[w] = false;
+      P.stats.n_conv = 0;
+      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= o.tol;
+    }
+    parts.push_back(std::move(P));
+  }
 }
 
 }  // namespace
@@ -436,15 +630,24 @@ void build_context(tsg_ctx* c, const tsg_grid* g, const double* V, const tsg_abs
   check(hipMemcpy(c->gamf.p, gamf.data(), sizeof(float) * g->nz, hipMemcpyHostToDevice), "upload gamma");
   check(hipMemcpy(c->gL.p, gL.data(), sizeof(double) * g->nz, hipMemcpyHostToDevice), "upload gamma");
   check(hipMemcpy(c->gR.p, gR.data(), sizeof(double) * g->nz, hipMemcpyHostToDevice), "upload gamma");
+  SysDesc& d = c->sys;
+  d.nx = g->nx; d.ny = g->ny; d.nz = g->nz; d.pad = 0;
+  d.Vd = c->V.p; d.Vf = c->Vf.p; d.Gd = c->gam.p; d.Gf = c->gamf.p;
+  d.diag0 = c->diag0;
+  for (int m = 0; m < 7; ++m) d.coef[m] = c->coef[m];
+  c->sysd.alloc(1);
+  check(hipMemcpy(c->sysd.p, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "upload system");
 }
 
 void apply_operator(tsg_ctx* c, const void* X, void* Y, int ncols, int64_t ld, int dtype) {
   if (!X || !Y) throw InvalidArg("null device pointer");
-  if (ncols < 1 || ld < ncols) throw InvalidArg("need 1 <= ncols <= ld");
+  if (ncols < 1 || ld < c->N) throw InvalidArg("need ncols >= 1 and ld >= N");
+  Systems S;
+  one_system(S, c, c->st);
   if (dtype == TSG_C128) {
-    stencil<double>(c, static_cast<const c128*>(X), ld, 0, static_cast<c128*>(Y), ld, 0, ncols, 1, nullptr);
+    stencil<double>(S, static_cast<const c128*>(X), ld, 0, static_cast<c128*>(Y), ld, 0, ncols, 1, nullptr);
   } else if (dtype == TSG_C64) {
-    stencil<float>(c, static_cast<const c64*>(X), ld, 0, static_cast<c64*>(Y), ld, 0, ncols, 1, nullptr);
+    stencil<float>(S, static_cast<const c64*>(X), ld, 0, static_cast<c64*>(Y), ld, 0, ncols, 1, nullptr);
   } else {
     throw InvalidArg("dtype must be TSG_C128 or TSG_C64");
   }
@@ -452,83 +655,52 @@ void apply_operator(tsg_ctx* c, const void* X, void* Y, int ncols, int64_t ld, i
 }
 
 bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_opts& o) {
-  const int nw = int(wins.size());
-  if (nw < 1) throw InvalidArg("need at least one window");
-  int nvmax = 0;
-  for (const auto& w : wins) {
-    if (w.nev < 1) throw InvalidArg("nev must be >= 1");
-    if (!std::isfinite(w.shift)) throw InvalidArg("shift must be finite");
-    nvmax = std::max(nvmax, w.nev);
-  }
-  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) throw InvalidArg("tol must be positive");
-  if (o.max_restarts < 1) throw InvalidArg("max_restarts must be >= 1");
-  if (o.precision != TSG_FP64 && o.precision != TSG_FP32_BULK) throw InvalidArg("unknown precision");
-  if (o.select < 0 || o.select > 2) throw InvalidArg("unknown selection");
-  int m, k, b;
-  choose_sizes(c->N, nvmax, o, m, k, b);
-  if (int64_t(m) >= c->N) throw InvalidArg("grid too small for the basis size");
-  const int64_t N = c->N;
-  hipStream_t st = c->st;
+  SolveStream ss(c->st);
+  Systems S;
+  one_system(S, c, ss.s);
   c->have_combined = false;
   c->have_grams = false;
-  std::vector<DevArr<c128>> results(nw);
-  std::vector<WinOut> outs;
-  std::vector<int> bulk_restarts(nw, 0);
-  std::vector<int64_t> bulk_mv(nw, 0);
-
-  if (o.precision == TSG_FP32_BULK) {
-    // complex64 phase to bulk_tol; keep [V_k | F] of each window for the FP64 phase
-    DevArr<c64> hand;
-    hand.alloc(size_t(N) * (k + b) * nw);
-    {
-      Batch<float> Bf;
-      Bf.alloc(nw, N, m, k, b, nvmax);
-      std::vector<WinOut> fo;
-      const double btol = std::max(o.bulk_tol > 0 ? o.bulk_tol : 1e-5, o.tol);
-      iterate<float>(c, Bf, wins, o.select, btol, o.max_restarts, o.seed, nullptr, fo, [&](int w) {
-        int one = w;
-        (void)one;
-        // V (already swapped) holds the kept basis in columns [0, k); F the continuation
-        check(hipMemcpy2DAsync(hand.p + size_t(w) * N * (k + b), sizeof(c64) * (k + b),
-                               Bf.V.p + size_t(w) * N * m, sizeof(c64) * m, sizeof(c64) * k, N,
-                               hipMemcpyDeviceToDevice, st), "handoff");
-        check(hipMemcpy2DAsync(hand.p + size_t(w) * N * (k + b) + k, sizeof(c64) * (k + b),
-                               Bf.F.p + size_t(w) * N * b, sizeof(c64) * b, sizeof(c64) * b, N,
-                               hipMemcpyDeviceToDevice, st), "handoff");
-      }, 100.0 * btol);
-      for (int w = 0; w < nw; ++w) { bulk_restarts[w] = fo[w].restarts; bulk_mv[w] = fo[w].matvecs; }
-    }
-    Batch<double> Bd;
-    Bd.alloc(nw, N, m, k, b, nvmax);
-    iterate<double>(c, Bd, wins, o.select, o.tol, o.max_restarts, o.seed + 1, hand.p, outs, [&](int w) {
-      results[w].alloc(size_t(N) * wins[w].nev);
-      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * wins[w].nev, Bd.V.p + size_t(w) * N * m + k,
-                             sizeof(c128) * m, sizeof(c128) * wins[w].nev, N, hipMemcpyDeviceToDevice, st),
-            "save");
-    }, 0.0, true);
-  } else {
-    Batch<double> Bd;
-    Bd.alloc(nw, N, m, k, b, nvmax);
-    iterate<double>(c, Bd, wins, o.select, o.tol, o.max_restarts, o.seed, nullptr, outs, [&](int w) {
-      results[w].alloc(size_t(N) * wins[w].nev);
-      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * wins[w].nev, Bd.V.p + size_t(w) * N * m + k,
-                             sizeof(c128) * m, sizeof(c128) * wins[w].nev, N, hipMemcpyDeviceToDevice, st),
-            "save");
-    });
-  }
-  check(hipStreamSynchronize(st), "sync");
+  std::vector<Partition> parts;
+  std::vector<bool> conv;
+  solve_core(S, wins, o, parts, conv);
   bool all = true;
-  for (int w = 0; w < nw; ++w) {
-    outs[w].matvecs += bulk_mv[w];
-    Partition P = finish_window(c, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w]);
-    if (!outs[w].converged || P.stats.max_backward_error > o.tol) {
-      all = false;
-      P.stats.n_conv = 0;
-      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= o.tol;
-    }
-    c->parts.push_back(std::move(P));
+  for (size_t w = 0; w < parts.size(); ++w) {
+    all = all && conv[w];
+    c->parts.push_back(std::move(parts[w]));
   }
   return all;
+}
+
+void solve_batch(const std::vector<tsg_ctx*>& ctx, const std::vector<std::vector<WindowSpec>>& wins,
+                 const tsg_opts& o, std::vector<bool>& ok) {
+  const int ns = int(ctx.size());
+  if (ns < 1) throw InvalidArg("need at least one system");
+  std::vector<WindowSpec> all;
+  std::vector<int> wsys;
+  for (int s = 0; s < ns; ++s) {
+    if (!ctx[s]) throw InvalidArg("null context in batch");
+    if (wins[s].empty()) throw InvalidArg("every system needs at least one window");
+    for (const auto& w : wins[s]) { all.push_back(w); wsys.push_back(s); }
+  }
+  for (int s = 1; s < ns; ++s) check(hipStreamSynchronize(ctx[s]->st), "sync");
+  SolveStream ss(ctx[0]->st);
+  Systems S;
+  many_systems(S, ctx, wsys, ss.s);
+  std::vector<Partition> parts;
+  std::vector<bool> conv;
+  solve_core(S, all, o, parts, conv);
+  ok.assign(ns, true);
+  for (int s = 0; s < ns; ++s) {
+    ctx[s]->parts.clear();
+    ctx[s]->have_combined = false;
+    ctx[s]->have_grams = false;
+  }
+  for (size_t w = 0; w < parts.size(); ++w) {
+    const int s = wsys[w];
+    ok[s] = ok[s] && conv[w];
+    ctx[s]->parts.push_back(std::move(parts[w]));
+  }
+  for (int s = 0; s < ns; ++s) combine(ctx[s], o.keep_lowest);
 }
 
 void combine(tsg_ctx* c, int keep_lowest) {
@@ -551,23 +723,20 @@ void combine(tsg_ctx* c, int keep_lowest) {
   std::vector<uint8_t> holes(std::max(p - 1, 0), 1);
   // pending plain copies into Ucomb
   std::vector<const c128*> psrc;
-  std::vector<int64_t> pld;
   std::vector<c128> psc;
   int pend_start = 0;
   DevArr<const c128*> dsrc;
-  DevArr<int64_t> dld;
   DevArr<c128> dsc;
-  dsrc.alloc(size_t(std::max(total, 1))); dld.alloc(size_t(std::max(total, 1))); dsc.alloc(size_t(std::max(total, 1)));
+  dsrc.alloc(size_t(std::max(total, 1))); dsc.alloc(size_t(std::max(total, 1)));
   auto flush = [&]() {
     const int n = int(psrc.size());
     if (n == 0) return;
     check(hipMemcpyAsync(dsrc.p, psrc.data(), sizeof(void*) * n, hipMemcpyHostToDevice, st), "srcs");
-    check(hipMemcpyAsync(dld.p, pld.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st), "lds");
     check(hipMemcpyAsync(dsc.p, psc.data(), sizeof(c128) * n, hipMemcpyHostToDevice, st), "sc");
-    gather_columns(Ucomb.p + pend_start, total, dsrc.p, dld.p, dsc.p, n, N, st);
+    gather_columns(Ucomb.p + int64_t(pend_start) * N, N, dsrc.p, dsc.p, n, N, st);
     check(hipStreamSynchronize(st), "sync");
     pend_start += n;
-    psrc.clear(); pld.clear(); psc.clear();
+    psrc.clear(); psc.clear();
   };
   for (int j = 0; j < p; ++j) {
     Partition& P = c->parts[j];
@@ -578,18 +747,16 @@ void combine(tsg_ctx* c, int keep_lowest) {
       for (int q = 0; q < int(keps.size()); ++q)
         if (cabs(keps[q] - lam) <= tau) pt.push_back(q);
       if (pt.empty()) {
-        psrc.push_back(P.U.p + i);
-        pld.push_back(n);
+        psrc.push_back(P.U.p + int64_t(i) * N);
         psc.push_back(c128{1.0, 0.0});
         keps.push_back(lam);
         kown.push_back(j);
         continue;
       }
       flush();
-      check(hipMemcpy2DAsync(v.p, sizeof(c128), P.U.p + i, sizeof(c128) * n, sizeof(c128), N,
-                             hipMemcpyDeviceToDevice, st), "copy v");
+      check(hipMemcpyAsync(v.p, P.U.p + int64_t(i) * N, sizeof(c128) * N, hipMemcpyDeviceToDevice, st), "copy v");
       check(hipMemcpyAsync(partners.p, pt.data(), sizeof(int) * pt.size(), hipMemcpyHostToDevice, st), "partners");
-      project_out(v.p, Ucomb.p, total, partners.p, int(pt.size()), N, out.p, st);
+      project_out(v.p, Ucomb.p, N, partners.p, int(pt.size()), N, out.p, st);
       double h[4];
       check(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st), "norms");
       check(hipStreamSynchronize(st), "sync");
@@ -602,7 +769,6 @@ void combine(tsg_ctx* c, int keep_lowest) {
       }
       const c128 sc = cdiv(c128{1.0, 0.0}, csqrt(c128{h[2], h[3]}));
       psrc.push_back(v.p);
-      pld.push_back(1);
       psc.push_back(sc);
       keps.push_back(lam);
       kown.push_back(j);
@@ -621,20 +787,18 @@ void combine(tsg_ctx* c, int keep_lowest) {
   if (keep_lowest > 0 && keep_lowest < nk) nout = keep_lowest;
   c->Uc.alloc(size_t(N) * std::max(nout, 1));
   std::vector<const c128*> srcs(nout);
-  std::vector<int64_t> lds(nout, total);
   std::vector<c128> scs(nout, c128{1.0, 0.0});
   c->epsc.resize(nout);
   c->ownerc.resize(nout);
   for (int i = 0; i < nout; ++i) {
-    srcs[i] = Ucomb.p + ord[i];
+    srcs[i] = Ucomb.p + int64_t(ord[i]) * N;
     c->epsc[i] = keps[ord[i]];
     c->ownerc[i] = kown[ord[i]];
   }
   if (nout > 0) {
     check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nout, hipMemcpyHostToDevice, st), "srcs");
-    check(hipMemcpyAsync(dld.p, lds.data(), sizeof(int64_t) * nout, hipMemcpyHostToDevice, st), "lds");
     check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nout, hipMemcpyHostToDevice, st), "sc");
-    gather_columns(c->Uc.p, nout, dsrc.p, dld.p, dsc.p, nout, N, st);
+    gather_columns(c->Uc.p, N, dsrc.p, dsc.p, nout, N, st);
   }
   check(hipStreamSynchronize(st), "sync");
   c->nc = nout;
@@ -792,7 +956,7 @@ void transmission(tsg_ctx* c, const double* E, int nE, double* T) {
     c->MR.alloc(nn); c->ML.alloc(nn); c->Wt.alloc(nn); c->epsd.alloc(n);
     DevArr<c128> part;
     part.alloc(size_t(gamma_gram_workspace(c->N, n)));
-    gamma_grams<double>(c->Uc.p, n, c->N, n, c->gL.p, c->gR.p, c->nx * c->ny, c->MR.p, c->ML.p, c->Wt.p, part.p, st);
+    gamma_grams<double>(c->Uc.p, c->N, c->N, n, c->gL.p, c->gR.p, c->nx * c->ny, c->MR.p, c->ML.p, c->Wt.p, part.p, st);
     check(hipMemcpyAsync(c->epsd.p, c->epsc.data(), sizeof(c128) * n, hipMemcpyHostToDevice, st), "eps");
     check(hipStreamSynchronize(st), "sync");
     c->have_grams = true;

@@ -4,45 +4,68 @@
 
 namespace tsg {
 
-// ---------------------------------------------------------------- K1
-template <typename T> struct StencilArgs {
-  const cplx<T>* X; int64_t ldx, wsx;      // input block, row stride, window stride
-  cplx<T>* Y; int64_t ldy, wsy;            // output block
-  int ncols;                               // columns per window
-  int nx, ny, nz, radius, zchunk;
-  const T* V;                              // N, potential (precision T)
-  const T* gamma;                          // nz, Gamma_L + Gamma_R per plane
-  T diag0;                                 // 3 * (-c0 / (2 h^2))
-  T coef[7];                               // coef[m] = -c_m / (2 h^2)
-  const T* shifts;                         // per-window real shift, or null
-  const int* wmap;                         // launch slot -> window index, or null
+// Row count of each window's vectors: `per` (indexed by window) when the
+// windows of one launch belong to systems of different size, else N.
+struct Rows {
+  int64_t N = 0;             // largest row count (sizes the launch)
+  const int* per = nullptr;  // device, per window, or null
+  __host__ __device__ int64_t of(int w) const { return per ? int64_t(per[w]) : N; }
 };
-template <typename T> void launch_stencil(const StencilArgs<T>& a, int nwin, hipStream_t s);
+
+// ---------------------------------------------------------------- K1
+// One grid system: dimensions, its potential V (N values) and absorber
+// profile Gamma_L + Gamma_R (nz values, one per z plane) in both
+// precisions, and its finite-difference weights: diag0 = -3 c_0 / (2 h^2)
+// and coef[m] = -c_m / (2 h^2).
+struct SysDesc {
+  int32_t nx, ny, nz, pad;
+  const double* Vd;
+  const float* Vf;
+  const double* Gd;
+  const float* Gf;
+  double diag0;
+  double coef[7];
+};
+
+template <typename T> struct StencilArgs {
+  const cplx<T>* X; int64_t ldx, wsx;      // input: column j of window w at X + w*wsx + j*ldx
+  cplx<T>* Y; int64_t ldy, wsy;            // output, same form
+  int ncols;                               // columns per window
+  int radius;
+  const SysDesc* sys;                      // device table
+  const int* wsys;                         // window -> system index, or null (system 0)
+  const int* wmap;                         // launch slot -> window index (< 0: idle), or null
+  int tx, ty, zchunk, tiles;               // launch geometry (tiles = largest tile count)
+};
+template <typename T> void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s);
+// Tile geometry for the largest system of a launch.
+template <typename T> void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin);
 
 // ---------------------------------------------------------------- dense
-// Batched tall-skinny products over the row index n < N.  Window w uses
-// X + w*wsx, etc.  All small matrices are FP64 complex, row-major.
+// Batched tall-skinny products over the grid index n < rows.of(w).  Grid
+// vectors are contiguous: column j of window w's block is X + w*wsx + j*ldx.
+// All small matrices are FP64 complex, row-major.
 
-// C[w] (r x s, ldc) = X[w]^H Y[w] (rows 0..N-1), reduced deterministically.
+// C[w] (r x s, ldc) = X[w]^H Y[w], reduced deterministically.
 // `partials` holds `cap` c128 entries (at least nwin * r * s); the number of
 // row chunks is capped to fit.  gram_workspace() is a good size.
 template <typename TX, typename TY>
-void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy,
-          int64_t N, int r, int s, c128* C, int64_t ldc, int64_t wsc, int nwin, c128* partials, int64_t cap,
-          hipStream_t st, const int* wmap = nullptr);
+void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_t ldy, int64_t wsy, Rows rows,
+          int r, int s, c128* C, int64_t ldc, int64_t wsc, int nwin, c128* partials, int64_t cap, hipStream_t st,
+          const int* wmap = nullptr);
 int64_t gram_workspace(int64_t N, int r, int s, int nwin);
 
 // Y[w] (N x s) = beta * Y[w] + alpha * X[w] (N x r) * B[w] (r x s, ldb).  Y must not alias X.
 template <typename T>
-void gemm_rows(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb,
-               cplx<T>* Y, int64_t ldy, int64_t wsy, int64_t N, int r, int s, double beta, int nwin,
-               hipStream_t st, const int* wmap = nullptr, double alpha = 1.0);
+void gemm_cols(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_t ldb, int64_t wsb, cplx<T>* Y,
+               int64_t ldy, int64_t wsy, Rows rows, int r, int s, double beta, int nwin, hipStream_t st,
+               const int* wmap = nullptr, double alpha = 1.0);
 
 // Per-column sums over rows of |AU - theta U|^2 and |U|^2 (FP64 partials,
 // reduced); out[w*s + j] = {res2, unorm2}.
 template <typename T>
 void residual_norms(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
-                    const c128* theta, int64_t wst, int64_t N, int s, int nwin, double* out, double* partials,
+                    const c128* theta, int64_t wst, Rows rows, int s, int nwin, double* out, double* partials,
                     int64_t cap, hipStream_t st, const int* wmap = nullptr);
 int64_t residual_workspace(int64_t N, int s, int nwin);
 
@@ -50,29 +73,28 @@ int64_t residual_workspace(int64_t N, int s, int nwin);
 // negative selection are left unchanged).
 template <typename T>
 void residual_block(const cplx<T>* U, const cplx<T>* AU, int64_t ld, int64_t ws, const c128* theta, int64_t wst,
-                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, int64_t N, int nwin, hipStream_t st,
+                    const int* sel, int b, cplx<T>* F, int64_t ldf, int64_t wsf, Rows rows, int nwin, hipStream_t st,
                     const int* wmap = nullptr);
 
 // c-products u^T A u and u^T u of each column (unconjugated), FP64.
 template <typename T>
-void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa,
-           int64_t N, int s, int nwin, c128* out, double* partials, int64_t cap, hipStream_t st,
-           const int* wmap = nullptr);
+void cdots(const cplx<T>* U, int64_t ldu, int64_t wsu, const cplx<T>* AU, int64_t lda, int64_t wsa, Rows rows, int s,
+           int nwin, c128* out, double* partials, int64_t cap, hipStream_t st, const int* wmap = nullptr);
 
 // Counter-based start vectors: real values uniform in [-1, 1) from a
 // 64-bit mix of (seed, window, row, column).
 template <typename T>
-void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, int64_t N, int s, int nwin, uint64_t seed, hipStream_t st,
+void random_block(cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, uint64_t seed, hipStream_t st,
                   const int* wmap = nullptr);
 
 // Y = X (columns), with precision conversion.
 template <typename TX, typename TY>
-void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy,
-                int64_t N, int s, int nwin, hipStream_t st, const int* wmap = nullptr);
+void copy_block(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy, Rows rows, int s,
+                int nwin, hipStream_t st, const int* wmap = nullptr);
 
 // Column scaling Y[:, j] *= scale[w*s + j] (complex FP64 factors).
 template <typename T>
-void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, int64_t N, int s, int nwin, hipStream_t st,
+void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, Rows rows, int s, int nwin, hipStream_t st,
                 const int* wmap = nullptr);
 
 // Small per-window kernels on b x b Gram matrices (one workgroup per window):
@@ -107,6 +129,7 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
 void transmission_sweep(const c128* W, int n, const c128* eps, const double* E, int nE, double* T,
                         hipStream_t st);
 // M^X = U^T diag(gamma_X) conj(U) for X = L, R and W = M^R o M^L (Hadamard).
+// U is N x n with contiguous columns (ld >= N).
 template <typename T>
 void gamma_grams(const cplx<T>* U, int64_t ldu, int64_t N, int n, const double* gL, const double* gR,
                  int plane, c128* MR, c128* ML, c128* W, c128* partials, hipStream_t st);
@@ -116,8 +139,8 @@ int64_t gamma_gram_workspace(int64_t N, int n);
 // order; out = {||v|| before, ||v|| after, Re v^T v, Im v^T v}.
 void project_out(c128* v, const c128* U, int64_t ldu, const int* partners, int np, int64_t N, double* out,
                  hipStream_t st);
-// dst[:, j] = scale[j] * (column pointed to by srcs[j], row stride srcld[j]).
-void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const int64_t* srcld, const c128* scale, int n,
-                    int64_t N, hipStream_t st);
+// dst[:, j] = scale[j] * (contiguous vector srcs[j]); dst column j at dst + j*ldd.
+void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const c128* scale, int n, int64_t N,
+                    hipStream_t st);
 
 }  // namespace tsg

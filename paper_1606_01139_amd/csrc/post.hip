@@ -34,13 +34,13 @@ __global__ __launch_bounds__(kPT) void project_kernel(c128* v, const c128* U, in
     const int m = partners[q];
     double dr = 0.0, di = 0.0;
     for (int64_t n = t; n < N; n += kPT) {
-      const c128 a = U[n * ldu + m], b = v[n];
+      const c128 a = U[int64_t(m) * ldu + n], b = v[n];
       dr += a.re * b.re - a.im * b.im;
       di += a.re * b.im + a.im * b.re;
     }
     const double cr = wg_sum(dr, red), ci = wg_sum(di, red);
     const c128 c{cr, ci};
-    for (int64_t n = t; n < N; n += kPT) v[n] = v[n] - U[n * ldu + m] * c;
+    for (int64_t n = t; n < N; n += kPT) v[n] = v[n] - U[int64_t(m) * ldu + n] * c;
     __syncthreads();
   }
   double a2 = 0.0, sr = 0.0, si = 0.0;
@@ -61,14 +61,11 @@ __global__ __launch_bounds__(kPT) void project_kernel(c128* v, const c128* U, in
 }
 
 // dst[:, j] = f_j * src_j  (columns gathered from arbitrary device vectors)
-__global__ void gather_kernel(c128* dst, int64_t ldd, const c128* const* srcs, const int64_t* srcld,
-                              const c128* scale, int n, int64_t N) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= N * n) return;
-  const int64_t row = e / n;
-  const int j = int(e % n);
-  const c128 v = srcs[j][row * srcld[j]];
-  dst[row * ldd + j] = scale[j] * v;
+__global__ void gather_kernel(c128* dst, int64_t ldd, const c128* const* srcs, const c128* scale, int64_t N) {
+  const int j = blockIdx.y;
+  const int64_t row = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= N) return;
+  dst[int64_t(j) * ldd + row] = scale[j] * srcs[j][row];
 }
 
 // Weighted Grams over the grid: MR = U^T diag(gR) conj U, ML likewise,
@@ -90,8 +87,11 @@ __global__ __launch_bounds__(256) void gamma_gram_partial(const c128* __restrict
   for (int64_t nb = n0; nb < n1; nb += kWT) {
     const int64_t row = nb + ty;
     const bool ok = row < n1;
-    As[ty][tx] = (ok && ti * kWT + tx < n) ? U[row * ldu + ti * kWT + tx] : c128{0.0, 0.0};
-    Bs[ty][tx] = (ok && tj * kWT + tx < n) ? U[row * ldu + tj * kWT + tx] : c128{0.0, 0.0};
+    // As[r][k]: row nb + r of column ti*16 + k (consecutive threads walk rows)
+    const int64_t rowc = nb + tx;
+    const bool okc = rowc < n1;
+    As[tx][ty] = (okc && ti * kWT + ty < n) ? U[int64_t(ti * kWT + ty) * ldu + rowc] : c128{0.0, 0.0};
+    Bs[tx][ty] = (okc && tj * kWT + ty < n) ? U[int64_t(tj * kWT + ty) * ldu + rowc] : c128{0.0, 0.0};
     if (tx == 0) {
       wl[ty] = ok ? gL[row / plane] : 0.0;
       wr[ty] = ok ? gR[row / plane] : 0.0;
@@ -188,11 +188,11 @@ void project_out(c128* v, const c128* U, int64_t ldu, const int* partners, int n
   hipLaunchKernelGGL(project_kernel, dim3(1), dim3(kPT), 0, st, v, U, ldu, partners, np, N, out);
 }
 
-void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const int64_t* srcld, const c128* scale, int n,
-                    int64_t N, hipStream_t st) {
+void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const c128* scale, int n, int64_t N,
+                    hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(gather_kernel, dim3(unsigned((N * n + 255) / 256)), dim3(256), 0, st, dst, ldd, srcs, srcld,
-                     scale, n, N);
+  hipLaunchKernelGGL(gather_kernel, dim3(unsigned((N + 255) / 256), unsigned(n)), dim3(256), 0, st, dst, ldd, srcs,
+                     scale, N);
 }
 
 }  // namespace tsg

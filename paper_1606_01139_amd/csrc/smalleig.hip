@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
   __shared__ double red[kEigThreads / 64];
   c128* v = sm;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
 __global__ void trevc_kernel(const c128* Tall, int64_t wst, int m, c128* Xall, int64_t wsx,
                              const int* __restrict__ wmap) {
   const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const c128* T = Tall + int64_t(w) * wst;
@@ -148,6 +150,7 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(const c128* Zall, int64
   __shared__ c128 As[16][17];
   __shared__ c128 Bs[16][17];
   const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const c128* Z = Zall + int64_t(w) * wsz;
   const c128* X = Xall + int64_t(w) * wsx;
   c128* Y = Yall + int64_t(w) * wsy;
@@ -167,6 +170,7 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(const c128* Zall, int64
 
 __global__ void colnorm_kernel(c128* Yall, int64_t wsy, int m, const int* __restrict__ wmap) {
   const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   c128* Y = Yall + int64_t(w) * wsy;
@@ -193,6 +197,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
   c128* coef = vec + m;                                              // k
   __shared__ double red[256];
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
   const c128* th = thall + int64_t(w) * wst;
   const c128* Y = Yall + int64_t(w) * wsy;
   c128* out = outall + int64_t(w) * wso;

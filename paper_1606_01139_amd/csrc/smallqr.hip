@@ -239,6 +239,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
   __shared__ QRShared S;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   c128* th = theta + int64_t(w) * wst;

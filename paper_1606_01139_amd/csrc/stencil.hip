@@ -5,89 +5,157 @@
 // difference star (2R+1 taps per axis, 6R+1 in all) with zero values outside
 // the box.
 //
-// Layout: a block of B vectors is stored point-major, X[n * ld + c] for grid
-// point n = x + nx (y + ny z) and column c < B, so one point's B values are
-// contiguous.  Batched over windows: blockIdx.z selects a window whose block
-// sits at a fixed element stride from the previous one.
+// Layout: each vector is one contiguous grid function, X[n] with
+// n = x + nx (y + ny z).  A launch covers every column of every active window
+// (blockIdx.z = slot * ncols + column); windows may belong to different
+// systems, each described by a SysDesc.
 //
-// Mapping: one thread owns one (x, y, column) and walks a chunk of z planes;
-// the 2R+1 z-neighbours live in a register queue (each input value is loaded
-// once per z-walk), x- and y-neighbours are read through L1/L2.
+// Mapping (2.5-D blocking): a workgroup owns a tx x ty tile of one xy plane
+// and walks a chunk of z planes.  Each thread keeps its point's 2R+1 z
+// neighbours in a register queue, so every interior value is read from HBM
+// once per walk; the x and y neighbours come from an LDS copy of the plane
+// with an R-wide halo (double-buffered: one barrier per plane).  Halo cells
+// outside the box hold zeros, which is the Dirichlet condition, so the tap
+// loop has no branches.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace tsg {
 
+namespace {
+
+constexpr int kST = 512;  // threads per workgroup
+
 template <typename T, int R>
-__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs<T> a) {
-  const int w = a.wmap ? a.wmap[blockIdx.z] : blockIdx.z;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int nc = a.ncols;
-  const int64_t plane = int64_t(a.nx) * a.ny;
-  if (gid >= plane * nc) return;
-  const int c = int(gid % nc);
-  const int64_t xy = gid / nc;
-  const int x = int(xy % a.nx);
-  const int y = int(xy / a.nx);
-  const int z0 = blockIdx.y * a.zchunk;
-  const int z1 = min(a.nz, z0 + a.zchunk);
-  if (z0 >= z1) return;
+__global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int slot = int(blockIdx.z) / a.ncols, col = int(blockIdx.z) % a.ncols;
+  const int w = a.wmap ? a.wmap[slot] : slot;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const SysDesc& S = a.sys[a.wsys ? a.wsys[w] : 0];
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int tx = a.tx, ty = a.ty;
+  const int tilesx = (nx + tx - 1) / tx, tilesy = (ny + ty - 1) / ty;
+  if (int(blockIdx.x) >= tilesx * tilesy) return;  // whole workgroup: smaller system
+  const int z0 = int(blockIdx.y) * a.zchunk;
+  if (z0 >= nz) return;
+  const int z1 = min(nz, z0 + a.zchunk);
+  const int bx = int(blockIdx.x) % tilesx, by = int(blockIdx.x) / tilesx;
+  const int lx = int(threadIdx.x) % tx, ly = int(threadIdx.x) / tx;
+  const bool active = ly < ty;
+  const int x = bx * tx + lx, y = by * ty + ly;
+  const bool inside = active && x < nx && y < ny;
+  const int64_t plane = int64_t(nx) * ny;
+  const int64_t xy = inside ? int64_t(y) * nx + x : 0;
 
-  const cplx<T>* __restrict__ X = a.X + int64_t(w) * a.wsx + c;
-  cplx<T>* __restrict__ Y = a.Y + int64_t(w) * a.wsy + c;
-  const int64_t ldx = a.ldx;
-  const T shift = a.shifts ? a.shifts[w] : T(0);
+  const cplx<T>* __restrict__ X = a.X + int64_t(w) * a.wsx + int64_t(col) * a.ldx;
+  cplx<T>* __restrict__ Y = a.Y + int64_t(w) * a.wsy + int64_t(col) * a.ldy;
+  const T* __restrict__ V;
+  const T* __restrict__ G;
+  if constexpr (sizeof(T) == 8) { V = reinterpret_cast<const T*>(S.Vd); G = reinterpret_cast<const T*>(S.Gd); }
+  else { V = reinterpret_cast<const T*>(S.Vf); G = reinterpret_cast<const T*>(S.Gf); }
+  const T diag0 = T(S.diag0);
+  T cf[R + 1];
+#pragma unroll
+  for (int m = 1; m <= R; ++m) cf[m] = T(S.coef[m]);
 
-  // z register queue: q[j] holds the value at plane z - R + j
+  const int LW = tx + 2 * R, LH = ty + 2 * R;
+  const int nhalo = 2 * R * LW + 2 * R * ty;
+  const cplx<T> zero{T(0), T(0)};
+
+  // q[j] holds the value at plane z - R + j
   cplx<T> q[2 * R + 1];
 #pragma unroll
   for (int j = 0; j < 2 * R + 1; ++j) {
-    int zz = z0 - R + j;
-    q[j] = (zz >= 0 && zz < a.nz) ? X[(zz * plane + xy) * ldx] : cplx<T>{T(0), T(0)};
+    const int zz = z0 - R + j;
+    q[j] = (inside && zz >= 0 && zz < nz) ? X[zz * plane + xy] : zero;
   }
   for (int z = z0; z < z1; ++z) {
-    const int64_t n = z * plane + xy;
-    const cplx<T>* __restrict__ Xp = X + n * ldx;
-    cplx<T> acc = q[R];
-    const T d = a.diag0 + a.V[n] - shift;
-    const T gi = -a.gamma[z];
-    acc = cplx<T>{d * acc.re - gi * acc.im, d * acc.im + gi * acc.re};
-#pragma unroll
-    for (int m = 1; m <= R; ++m) {
-      const T cm = a.coef[m];
-      cplx<T> s = q[R - m] + q[R + m];
-      if (x - m >= 0) s = s + Xp[-int64_t(m) * ldx];
-      if (x + m < a.nx) s = s + Xp[int64_t(m) * ldx];
-      if (y - m >= 0) s = s + Xp[-int64_t(m) * a.nx * ldx];
-      if (y + m < a.ny) s = s + Xp[int64_t(m) * a.nx * ldx];
-      acc.re = fma(cm, s.re, acc.re);
-      acc.im = fma(cm, s.im, acc.im);
+    cplx<T>* L = smem + ((z - z0) & 1) * (LW * LH);
+    // the next plane's value is fetched early to overlap its latency
+    const int zn = z + R + 1;
+    const cplx<T> nxt = (inside && zn < nz) ? X[zn * plane + xy] : zero;
+    if (active) L[(ly + R) * LW + lx + R] = inside ? q[R] : zero;
+    const cplx<T>* __restrict__ Xz = X + z * plane;
+    for (int e = int(threadIdx.x); e < nhalo; e += kST) {
+      int hx, hy;
+      if (e < 2 * R * LW) {  // bands above and below the tile
+        hy = e / LW;
+        hx = e % LW;
+        if (hy >= R) hy += ty;
+      } else {               // bands left and right of the tile
+        const int f = e - 2 * R * LW;
+        hy = R + f / (2 * R);
+        const int k = f % (2 * R);
+        hx = k < R ? k : tx + k;
+      }
+      const int gx = bx * tx + hx - R, gy = by * ty + hy - R;
+      L[hy * LW + hx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? Xz[int64_t(gy) * nx + gx] : zero;
     }
-    Y[n * a.ldy] = acc;
-    // advance the queue
+    __syncthreads();
+    if (inside) {
+      const int64_t n = z * plane + xy;
+      const cplx<T> c0 = q[R];
+      const T d = diag0 + V[n];
+      const T g = G[z];
+      cplx<T> acc{d * c0.re + g * c0.im, d * c0.im - g * c0.re};
+      const cplx<T>* Lc = L + (ly + R) * LW + lx + R;
+#pragma unroll
+      for (int m = 1; m <= R; ++m) {
+        cplx<T> s = q[R - m] + q[R + m];
+        s = s + Lc[-m];
+        s = s + Lc[m];
+        s = s + Lc[-m * LW];
+        s = s + Lc[m * LW];
+        acc.re = fma(cf[m], s.re, acc.re);
+        acc.im = fma(cf[m], s.im, acc.im);
+      }
+      Y[n] = acc;
+    }
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) q[j] = q[j + 1];
-    const int zn = z + R + 1;
-    q[2 * R] = (zn < a.nz) ? X[(zn * plane + xy) * ldx] : cplx<T>{T(0), T(0)};
+    q[2 * R] = nxt;
   }
+}
+
+}  // namespace
+
+template <typename T>
+void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin) {
+  int tx = 64;
+  while (tx > 16 && tx / 2 >= nx) tx /= 2;
+  a.tx = tx;
+  a.ty = kST / tx;
+  a.tiles = ((nx + tx - 1) / tx) * ((ny + a.ty - 1) / a.ty);
+  // enough workgroups to fill the chip; a chunk re-reads 2R planes
+  const int64_t base = int64_t(a.tiles) * a.ncols * std::max(nwin, 1);
+  int64_t nch = (2048 + base - 1) / base;
+  const int minchunk = std::max(8, 2 * a.radius);
+  nch = std::max<int64_t>(1, std::min<int64_t>(nch, (nz + minchunk - 1) / minchunk));
+  a.zchunk = int((nz + nch - 1) / nch);
 }
 
 template <typename T>
-void launch_stencil(const StencilArgs<T>& a, int nwin, hipStream_t s) {
+void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s) {
   if (nwin <= 0 || a.ncols <= 0) return;
-  const int64_t threads = int64_t(a.nx) * a.ny * a.ncols;
-  dim3 block(256);
-  dim3 grid(unsigned((threads + 255) / 256), unsigned((a.nz + a.zchunk - 1) / a.zchunk), unsigned(nwin));
+  dim3 block(kST);
+  dim3 grid(unsigned(a.tiles), unsigned((max_nz + a.zchunk - 1) / a.zchunk), unsigned(nwin * a.ncols));
+  const size_t lds = size_t(2) * (a.tx + 2 * a.radius) * (a.ty + 2 * a.radius) * sizeof(cplx<T>);
   switch (a.radius) {
-    case 1: hipLaunchKernelGGL((stencil_kernel<T, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stencil_kernel<T, 2>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stencil_kernel<T, 3>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((stencil_kernel<T, 4>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((stencil_kernel<T, 5>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((stencil_kernel<T, 6>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((stencil_kernel<T, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((stencil_kernel<T, 2>), grid, block, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((stencil_kernel<T, 3>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((stencil_kernel<T, 4>), grid, block, lds, s, a); break;
+    case 5: hipLaunchKernelGGL((stencil_kernel<T, 5>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((stencil_kernel<T, 6>), grid, block, lds, s, a); break;
   }
 }
 
-template void launch_stencil<double>(const StencilArgs<double>&, int, hipStream_t);
-template void launch_stencil<float>(const StencilArgs<float>&, int, hipStream_t);
+template void launch_stencil<double>(StencilArgs<double>, int, int, hipStream_t);
+template void launch_stencil<float>(StencilArgs<float>, int, int, hipStream_t);
+template void stencil_geometry<double>(StencilArgs<double>&, int, int, int, int);
+template void stencil_geometry<float>(StencilArgs<float>&, int, int, int, int);
 
 }  // namespace tsg

@@ -26,30 +26,42 @@ def _fields(nx, ny, nz, seed, h=0.5):
     return V, ab, gL, gR
 
 
-@pytest.mark.parametrize("shape,B,R", [((10, 10, 20), 16, 6), ((13, 11, 17), 5, 6), ((7, 9, 30), 3, 6),
-                                       ((12, 12, 12), 8, 3), ((5, 6, 7), 1, 1), ((32, 32, 64), 16, 6)])
-def test_stencil_c128_matches_oracle(torch_cuda, shape, B, R):
+def _to_dev(torch, X, pad):
+    """(N, B) host block -> (B, N) device view whose rows sit `pad` elements apart beyond N."""
+    N, B = X.shape
+    buf = torch.zeros((B, N + pad), dtype={np.complex128: torch.complex128,
+                                            np.complex64: torch.complex64}[X.dtype.type], device="cuda")
+    buf[:, :N] = torch.tensor(np.ascontiguousarray(X.T), device="cuda")
+    return buf[:, :N]
+
+
+# shapes cover a tile of the x extent (16, 32 and 64 wide), ragged tiles in
+# x and y, z shorter than the finite-difference reach, and padded columns
+@pytest.mark.parametrize("shape,B,R,pad", [((10, 10, 20), 16, 6, 0), ((13, 11, 17), 5, 6, 3), ((7, 9, 30), 3, 6, 0),
+                                           ((12, 12, 12), 8, 3, 0), ((5, 6, 7), 1, 1, 0), ((32, 32, 64), 16, 6, 64),
+                                           ((70, 19, 9), 2, 6, 0), ((64, 40, 33), 3, 6, 0), ((33, 17, 5), 2, 4, 1)])
+def test_stencil_c128_matches_oracle(torch_cuda, shape, B, R, pad):
     torch = torch_cuda
     from oracle import operator as op
     from paper_1606_01139_amd import Operator
     nx, ny, nz = shape
-    print(f"stencil c128 shape={shape} B={B} R={R}", flush=True)
+    print(f"stencil c128 shape={shape} B={B} R={R} pad={pad}", flush=True)
     V, ab, gL, gR = _fields(nx, ny, nz, 3)
     N = nx * ny * nz
     rng = np.random.default_rng(4)
     X = rng.standard_normal((N, B)) + 1j * rng.standard_normal((N, B))
     ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X, R)
     oper = Operator(nx, ny, nz, 0.5, V, ab, fd_radius=R)
-    Xd = torch.tensor(X, device="cuda")
-    Yd = torch.empty_like(Xd)
+    Xd = _to_dev(torch, X, pad)
+    Yd = _to_dev(torch, np.zeros_like(X), pad)
     oper.apply(Xd, Yd)
     torch.cuda.synchronize()
-    Y = Yd.cpu().numpy()
+    Y = Yd.cpu().numpy().T
     scale = np.abs(ref).max()
     assert np.abs(Y - ref).max() <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("shape,B", [((10, 10, 20), 16), ((13, 11, 17), 5), ((32, 32, 64), 16)])
+@pytest.mark.parametrize("shape,B", [((10, 10, 20), 16), ((13, 11, 17), 5), ((32, 32, 64), 16), ((64, 64, 40), 2)])
 def test_stencil_c64_matches_oracle(torch_cuda, shape, B):
     torch = torch_cuda
     from oracle import operator as op
@@ -62,11 +74,11 @@ def test_stencil_c64_matches_oracle(torch_cuda, shape, B):
     X = (rng.standard_normal((N, B)) + 1j * rng.standard_normal((N, B))).astype(np.complex64)
     ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X.astype(np.complex128), 6)
     oper = Operator(nx, ny, nz, 0.5, V, ab)
-    Xd = torch.tensor(X, device="cuda")
-    Yd = torch.empty_like(Xd)
+    Xd = _to_dev(torch, X, 0)
+    Yd = _to_dev(torch, np.zeros_like(X), 0)
     oper.apply(Xd, Yd)
     torch.cuda.synchronize()
-    Y = Yd.cpu().numpy().astype(np.complex128)
+    Y = Yd.cpu().numpy().T.astype(np.complex128)
     # FP32 accumulation over 37 taps: relative error a few ulp of float32
     assert np.abs(Y - ref).max() <= 1e-6 * np.abs(ref).max()
 

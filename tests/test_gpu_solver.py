@@ -150,3 +150,55 @@ def test_planner_matches_oracle(torch_cuda):
     assert [n for _, n in wins] == [20, 20]
     np.testing.assert_allclose([s for s, _ in wins], ref, rtol=0, atol=1e-6)
     oper.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_direct_launches(torch_cuda, precision):
+    # Each restart cycle after the first is replayed from a captured
+    # hipGraph; with deterministic kernels the replayed run must reproduce
+    # the directly launched one bit for bit (every replay, separated by host
+    # synchronisation and copies, feeds the next cycle).
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import small_workload
+    w = small_workload(10, 9, 14, 3, seed=23)
+    g = w.grid
+    print(f"graph vs direct precision={precision}", flush=True)
+    res = []
+    for graphs in (1, 0):
+        oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+        wins = [(-1.5, 6), (-0.8, 6)]
+        n, holes, _ = oper.solve_all_partitions(wins, default_opts(precision=precision, graphs=graphs))
+        st = [oper.stats(j) for j in range(2)]
+        res.append((oper.eigenvalues(), oper.eigenvectors().cpu().numpy(), [(s.restarts, s.matvecs) for s in st]))
+        oper.close()
+    assert res[0][2] == res[1][2] and res[0][2][0][0] > 2
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ragged_batch_matches_oracle(torch_cuda, precision):
+    # windows of systems of different size in one batched iteration: each
+    # system's combined set equals the oracle's windows of its own spectrum
+    from oracle import eigen, partition
+    from paper_1606_01139_amd import Operator, default_opts, solve_batch
+    from synth.workloads import small_workload
+    print(f"ragged batch precision={precision}", flush=True)
+    shapes = [(8, 8, 12, 2, 31), (11, 9, 13, 3, 32), (9, 12, 10, 4, 33)]
+    ops, refs, wins = [], [], []
+    for nx, ny, nz, nwell, seed in shapes:
+        w = small_workload(nx, ny, nz, nwell, seed=seed)
+        g = w.grid
+        A, gL, gR, ea, Ua, nrm = _setup(w)
+        shifts = [float(ea[3].real), float(ea[12].real)]
+        wins.append([(s, 6) for s in shifts])
+        refs.append((partition.combine([eigen.window_from_spectrum(ea, Ua, s, 6) for s in shifts], nrm), A, nrm, ea))
+        ops.append(Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple()))
+    nu, status = solve_batch(ops, wins, default_opts(precision=precision, basis=48, keep=24))
+    for s, op_ in enumerate(ops):
+        ref, A, nrm, ea = refs[s]
+        assert nu[s] == len(ref.eps)
+        eps = op_.eigenvalues()
+        _match_sets(eps, ref.eps, 1e-10)
+        _check_vectors(op_.eigenvectors().cpu().numpy(), ref.U, A, eps, nrm, ea)
+        op_.close()
