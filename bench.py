@@ -30,12 +30,13 @@ def energy_grid(eps, n):
     return np.linspace(re.min(), re.max(), n) if n > 1 else np.array([re.mean()])
 
 
-def run_step(w, prec_code, n_r, p, opts, max_windows=None, plan="sampled"):
-    from paper_1606_01139_amd import Operator, PLAN_EQUAL, PLAN_SAMPLED
+def run_step(w, prec_code, n_r, p, opts, max_windows=None, plan="semiclassical"):
+    from paper_1606_01139_amd import Operator, PLAN_EQUAL, PLAN_SAMPLED, PLAN_SEMICLASSICAL
     g = w.grid
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
     t0 = time.perf_counter()
-    wins, erange = oper.plan_windows(n_r, p, PLAN_SAMPLED if plan == "sampled" else PLAN_EQUAL, opts)
+    mode = {"semiclassical": PLAN_SEMICLASSICAL, "sampled": PLAN_SAMPLED, "alg1": PLAN_EQUAL}[plan]
+    wins, erange = oper.plan_windows(n_r, p, mode, opts)
     oper.plan_seconds = time.perf_counter() - t0
     if max_windows:
         wins = wins[:max_windows]
@@ -111,7 +112,7 @@ def main():
     ap.add_argument("--precision", default="bulk", choices=["fp64", "bulk"])
     ap.add_argument("--max-restarts", type=int, default=2000)
     ap.add_argument("--max-windows", type=int, default=0)
-    ap.add_argument("--plan", default="sampled", choices=["sampled", "alg1"])
+    ap.add_argument("--plan", default="semiclassical", choices=["semiclassical", "sampled", "alg1"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")

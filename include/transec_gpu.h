@@ -45,7 +45,7 @@ typedef enum {
 } tsg_status;
 
 enum { TSG_FP64 = 0, TSG_FP32_BULK = 1 };                 /* tsg_opts.precision */
-enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1, TSG_PLAN_SAMPLED = 2 }; /* tsg_plan_windows mode */
+enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1, TSG_PLAN_SAMPLED = 2, TSG_PLAN_SEMICLASSICAL = 3 }; /* tsg_plan_windows mode */
 enum { TSG_SELECT_NEAREST = 0, TSG_SELECT_SMALLEST_REAL = 1, TSG_SELECT_LARGEST_REAL = 2 };
 enum { TSG_C128 = 0, TSG_C64 = 1 };                       /* element types of device blocks */
 
@@ -124,7 +124,13 @@ tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_a
  *                     sampled by solving 8 eigenpairs at each of max(2p, 8)
  *                     shifts (Section 2.2's density estimate) and the shifts
  *                     are the midpoints of consecutive intervals of n_{r,j}
- *                     eigenvalues of the integrated density.
+ *                     eigenvalues of the integrated density;
+ *   TSG_PLAN_SEMICLASSICAL: n_{r,j} = n_r/p; the shifts are the midpoints
+ *                     of consecutive intervals of n_{r,j} eigenvalues of the
+ *                     semiclassical counting function (phase-space volume of
+ *                     p^2/2 + V over the box with Weyl's Dirichlet surface
+ *                     term), a density estimate that needs no eigensolve
+ *                     beyond E_min.
  *   out:     host, capacity p windows;
  *   e_range: host, 2 doubles {E_min, E_max}, or NULL.
  * Errors: TSG_EINVAL (n_r < 1, p < 1, mode), TSG_ESTATE (no convergence),

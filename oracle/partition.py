@@ -21,6 +21,14 @@ Readings where the paper is silent or garbled:
   * E_max (Algorithm 1's upper extremal eigenvalue) is taken as the exact
     upper bound on the real parts, max V + 3 max|symbol| / (2 h^2), instead of
     a second exterior solve: Re eps = u^H (K + V) u / u^H u lies below it;
+  * the semiclassical planner estimates the counting function (how many
+    eigenvalues have real part below E) from the phase-space volume of the
+    Hamiltonian H = p^2/2 + V(r) over the box, with the Dirichlet surface
+    correction of Weyl's asymptotics: N(E) = sum_r w k_r^3/(6 pi^2) -
+    S <k_r^2>/(16 pi) with k_r^2 = 2 max(E - V(r), 0), w the volume per grid
+    point, S the box surface and <.> the mean over grid points; windows sit
+    at the midpoints of consecutive intervals of n_{r,j} estimated
+    eigenvalues, as in the density-sampling planner below;
   * density sampling (Section 2.2, "a few eigenpairs at several sample
     points") is read as: 8 eigenpairs nearest each of S = max(2p, 8) shifts
     spread evenly over [E_min, top], each giving a local density
@@ -120,6 +128,46 @@ def sampled_windows(e_min: float, samples: Sequence[np.ndarray], counts: Sequenc
         return xs[-1] + (target - cum[-1]) / max(rho[order[-1]], 1e-12)
 
     shifts, acc = [], 0.0
+    for c in counts:
+        shifts.append(0.5 * (inverse(acc) + inverse(acc + c)))
+        acc += c
+    return shifts
+
+
+def box_lengths(shape, h: float):
+    """Edges of the Dirichlet box: the grid plus one spacing (the zero
+    values sit one step outside the first and last points)."""
+    return tuple((n + 1) * h for n in shape)
+
+
+def semiclassical_count(V: np.ndarray, h: float, shape, E: float) -> float:
+    """Estimated number of eigenvalues with real part below E (module notes)."""
+    lx, ly, lz = box_lengths(shape, h)
+    vol = lx * ly * lz
+    surf = 2.0 * (lx * ly + ly * lz + lx * lz)
+    k2 = np.maximum(2.0 * (E - np.asarray(V, dtype=np.float64)), 0.0)
+    return (vol / k2.size) * float(np.sum(k2 ** 1.5)) / (6.0 * math.pi ** 2) - surf * float(np.mean(k2)) / (16.0 * math.pi)
+
+
+def semiclassical_windows(V: np.ndarray, h: float, shape, e_min: float, counts: Sequence[int]) -> List[float]:
+    """Window shifts at the midpoints of consecutive intervals holding
+    n_{r,j} eigenvalues of the semiclassical counting function."""
+    def inverse(target):
+        if target <= 0:
+            return e_min
+        lo, width = e_min, 1.0
+        while semiclassical_count(V, h, shape, lo + width) < target:
+            width *= 2.0
+        hi = lo + width
+        for _ in range(100):
+            mid = 0.5 * (lo + hi)
+            if semiclassical_count(V, h, shape, mid) < target:
+                lo = mid
+            else:
+                hi = mid
+        return 0.5 * (lo + hi)
+
+    shifts, acc = [], 0
     for c in counts:
         shifts.append(0.5 * (inverse(acc) + inverse(acc + c)))
         acc += c

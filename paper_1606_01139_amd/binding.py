@@ -20,7 +20,7 @@ TSG_OK, TSG_EINVAL, TSG_ENOMEM, TSG_ENOCONV, TSG_EBREAKDOWN, TSG_EDEVICE, TSG_ES
 STATUS_NAMES = ["TSG_OK", "TSG_EINVAL", "TSG_ENOMEM", "TSG_ENOCONV", "TSG_EBREAKDOWN", "TSG_EDEVICE",
                 "TSG_ESTATE", "TSG_ECAPACITY"]
 FP64, FP32_BULK = 0, 1
-PLAN_ALG1, PLAN_EQUAL, PLAN_SAMPLED = 0, 1, 2
+PLAN_ALG1, PLAN_EQUAL, PLAN_SAMPLED, PLAN_SEMICLASSICAL = 0, 1, 2, 3
 SELECT_NEAREST, SELECT_SMALLEST_REAL, SELECT_LARGEST_REAL = 0, 1, 2
 C128, C64 = 0, 1
 

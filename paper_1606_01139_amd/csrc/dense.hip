@@ -23,7 +23,7 @@ constexpr int kGK = 32;   // grid rows of X, Y staged per step
 
 inline int gram_chunks(int64_t N, int r, int s, int nwin) {
   const int64_t tiles = int64_t((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT) * nwin;
-  int64_t want = (4096 + tiles - 1) / tiles;
+  int64_t want = std::min<int64_t>((4096 + tiles - 1) / tiles, 64);
   int64_t maxc = (N + 511) / 512;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
@@ -174,6 +174,117 @@ __global__ __launch_bounds__(256) void gemm_cols_kernel(const cplx<T>* __restric
       if (beta != T(0)) v = v + beta * (*y);
       *y = v;
     }
+  }
+}
+
+// ------------------------------------------------------------- skinny
+// Tall-skinny forms for s <= kSK output columns (the block of new vectors):
+// the gram keeps 64 columns of X per workgroup, each thread one column of X
+// against all s columns of Y over a quarter of the staged rows; the update
+// streams X once with one grid row per thread.
+constexpr int kSK = 8;
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void gram_skinny_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                          const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
+                                                          Rows rows, int r, int s, int nchunk, c128* __restrict__ P,
+                                                          const int* __restrict__ wmap) {
+  constexpr int TI = 64, KR = 32;
+  __shared__ cplx<TX> Xs[KR][TI + 1];
+  __shared__ c128 Ys[KR][kSK];
+  __shared__ c128 red[3][TI][kSK];
+  const int wz = blockIdx.z;
+  const int w = wmap ? wmap[wz] : wz;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int64_t N = rows.of(w);
+  const int i0 = blockIdx.y * TI;
+  const int chunk = blockIdx.x;
+  const int64_t rows_per = ((rows.N + nchunk - 1) / nchunk + KR - 1) / KR * KR;
+  const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
+  const int t = threadIdx.x, il = t % TI, g = t / TI;
+  X += int64_t(w) * wsx;
+  Y += int64_t(w) * wsy;
+  c128 acc[kSK];
+#pragma unroll
+  for (int q = 0; q < kSK; ++q) acc[q] = c128{0.0, 0.0};
+  for (int64_t nb = n0; nb < n1; nb += KR) {
+    for (int e = t; e < KR * TI; e += 256) {
+      const int cc = e / KR, rr = e % KR;
+      const int64_t n = nb + rr;
+      Xs[rr][cc] = (n < n1 && i0 + cc < r) ? X[int64_t(i0 + cc) * ldx + n] : cplx<TX>{TX(0), TX(0)};
+    }
+    for (int e = t; e < KR * kSK; e += 256) {
+      const int q = e / KR, rr = e % KR;
+      const int64_t n = nb + rr;
+      c128 v{0.0, 0.0};
+      if (n < n1 && q < s) { const cplx<TY> y = Y[int64_t(q) * ldy + n]; v = c128{double(y.re), double(y.im)}; }
+      Ys[rr][q] = v;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = g; k < KR; k += 4) {
+      const cplx<TX> xv = Xs[k][il];
+      const c128 x{double(xv.re), double(xv.im)};
+#pragma unroll
+      for (int q = 0; q < kSK; ++q) fma_cacc(acc[q], x, Ys[k][q]);
+    }
+    __syncthreads();
+  }
+  if (g > 0)
+#pragma unroll
+    for (int q = 0; q < kSK; ++q) red[g - 1][il][q] = acc[q];
+  __syncthreads();
+  if (g == 0 && i0 + il < r) {
+    c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
+    for (int q = 0; q < s; ++q)
+      Pw[int64_t(i0 + il) * s + q] = acc[q] + red[0][il][q] + red[1][il][q] + red[2][il][q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_skinny_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                          const c128* __restrict__ B, int64_t ldb, int64_t wsb,
+                                                          cplx<T>* __restrict__ Y, int64_t ldy, int64_t wsy, Rows rows,
+                                                          int r, int s, T beta, T alpha,
+                                                          const int* __restrict__ wmap) {
+  constexpr int KB = 128;
+  __shared__ cplx<T> Bs[KB][kSK];
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int64_t N = rows.of(w);
+  const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (int64_t(blockIdx.x) * 256 >= N) return;  // whole workgroup, before any barrier
+  X += int64_t(w) * wsx;
+  Y += int64_t(w) * wsy;
+  B += int64_t(w) * wsb;
+  const bool ok = n < N;
+  cplx<T> acc[kSK];
+#pragma unroll
+  for (int q = 0; q < kSK; ++q) acc[q] = cplx<T>{T(0), T(0)};
+  for (int k0 = 0; k0 < r; k0 += KB) {
+    const int kn = min(KB, r - k0);
+    for (int e = threadIdx.x; e < KB * kSK; e += 256) {
+      const int kk = e / kSK, q = e % kSK;
+      c128 v = (kk < kn && q < s) ? B[int64_t(k0 + kk) * ldb + q] : c128{0.0, 0.0};
+      Bs[kk][q] = cplx<T>{T(v.re), T(v.im)};
+    }
+    __syncthreads();
+    if (ok) {
+      const cplx<T>* xp = X + int64_t(k0) * ldx + n;
+      for (int kk = 0; kk < kn; ++kk) {
+        const cplx<T> x = xp[int64_t(kk) * ldx];
+#pragma unroll
+        for (int q = 0; q < kSK; ++q) fma_acc(acc[q], x, Bs[kk][q]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok) return;
+  for (int q = 0; q < s; ++q) {
+    cplx<T>* y = Y + int64_t(q) * ldy + n;
+    cplx<T> v = alpha * acc[q];
+    if (beta != T(0)) v = v + beta * (*y);
+    *y = v;
   }
 }
 
@@ -411,9 +522,14 @@ void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_
   const int64_t per = int64_t(nwin) * r * s;
   if (cap < per) throw DeviceError("gram: partial workspace too small");
   const int nchunk = int(std::min<int64_t>(gram_chunks(rows.N, r, s, nwin), cap / per));
-  const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
-  hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
-                     ldy, wsy, rows, r, s, nchunk, partials, wmap);
+  if (s <= kSK) {
+    hipLaunchKernelGGL((gram_skinny_kernel<TX, TY>), dim3(nchunk, (r + 63) / 64, nwin), dim3(256), 0, st, X, ldx,
+                       wsx, Y, ldy, wsy, rows, r, s, nchunk, partials, wmap);
+  } else {
+    const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
+    hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
+                       ldy, wsy, rows, r, s, nchunk, partials, wmap);
+  }
   const int64_t rs = int64_t(r) * s;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(unsigned((rs + 255) / 256), nwin), dim3(256), 0, st, partials, nchunk,
                      r, s, C, ldc, wsc, wmap);
@@ -424,6 +540,11 @@ void gemm_cols(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_
                int64_t ldy, int64_t wsy, Rows rows, int r, int s, double beta, int nwin, hipStream_t st,
                const int* wmap, double alpha) {
   if (nwin <= 0 || s <= 0) return;
+  if (s <= kSK) {
+    hipLaunchKernelGGL((gemm_skinny_kernel<T>), dim3(unsigned((rows.N + 255) / 256), 1, nwin), dim3(256), 0, st, X,
+                       ldx, wsx, B, ldb, wsb, Y, ldy, wsy, rows, r, s, T(beta), T(alpha), wmap);
+    return;
+  }
   hipLaunchKernelGGL((gemm_cols_kernel<T>), dim3(unsigned((rows.N + 63) / 64), unsigned((s + 31) / 32), nwin),
                      dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy, wsy, rows, r, s, T(beta), T(alpha), wmap);
 }

@@ -82,6 +82,7 @@ struct tsg_ctx {
   double diag0 = 0.0;                      // 3 (-c_0 / (2h^2))
   double normA = 0.0;                      // Gershgorin bound ||A||_G
   double vmin = 0.0, vmax = 0.0, gmax = 0.0;
+  std::vector<double> Vh;                  // host copy of V (window planning)
   tsg::DevArr<double> V, gam, gL, gR;      // FP64 operator data (gam, gL, gR per z plane)
   tsg::DevArr<float> Vf, gamf;             // complex64 path
   tsg::SysDesc sys{};                      // this system for the stencil

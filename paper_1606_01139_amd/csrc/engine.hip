@@ -621,6 +621,7 @@ void build_context(tsg_ctx* c, const tsg_grid* g, const double* V, const tsg_abs
   }
   c->normA = 3.0 * (std::fabs(c0) + 2.0 * sabs) / (2.0 * g->h * g->h) + vabs + gmax;
   c->vmin = vmin; c->vmax = vmax; c->gmax = gmax;
+  c->Vh.assign(V, V + N);
   c->V.alloc(N); c->Vf.alloc(N);
   c->gam.alloc(g->nz); c->gamf.alloc(g->nz); c->gL.alloc(g->nz); c->gR.alloc(g->nz);
   std::vector<float> Vf(V, V + N), gamf(gam.begin(), gam.end());
@@ -838,6 +839,7 @@ double smallest_real_part(tsg_ctx* c, const tsg_opts& o) {
   oe.basis = 0;
   oe.keep = 0;
   oe.select = TSG_SELECT_SMALLEST_REAL;
+  oe.max_restarts = std::max(o.max_restarts, 2000);
   const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
   const double e = c->parts.back().eps[0].re;
   c->parts.resize(keep_parts);
@@ -859,13 +861,50 @@ double upper_bound_real(const tsg_ctx* c) {
 void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
                   double* e_range) {
   if (n_r < 1 || p < 1) throw InvalidArg("need n_r >= 1 and p >= 1");
-  if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL && mode != TSG_PLAN_SAMPLED)
+  if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL && mode != TSG_PLAN_SAMPLED && mode != TSG_PLAN_SEMICLASSICAL)
     throw InvalidArg("unknown planning mode");
   const double e_min = smallest_real_part(c, o);
   const double e_max = upper_bound_real(c);
   const std::vector<int> counts = window_counts(n_r, p, mode == TSG_PLAN_ALG1 ? TSG_PLAN_ALG1 : TSG_PLAN_EQUAL);
   out.resize(p);
-  if (mode != TSG_PLAN_SAMPLED) {
+  if (mode == TSG_PLAN_SEMICLASSICAL) {
+    // Counting function from the phase-space volume of p^2/2 + V over the
+    // box, N(E) = w sum_r k_r^3 / (6 pi^2) - S <k_r^2> / (16 pi) with
+    // k_r^2 = 2 max(E - V_r, 0) (Weyl's law with its Dirichlet surface
+    // term); windows at the midpoints of consecutive intervals of n_{r,j}
+    // eigenvalues (the placement of Section 3).
+    const double lx = (c->nx + 1) * c->h, ly = (c->ny + 1) * c->h, lz = (c->nz + 1) * c->h;
+    const double vol = lx * ly * lz, surf = 2.0 * (lx * ly + ly * lz + lx * lz);
+    std::vector<double> vs(c->Vh);
+    std::sort(vs.begin(), vs.end());
+    auto count = [&](double E) {
+      double s3 = 0.0, s2 = 0.0;
+      for (double v : vs) {
+        if (v >= E) break;
+        const double k2 = 2.0 * (E - v);
+        s3 += k2 * std::sqrt(k2);
+        s2 += k2;
+      }
+      const double n = double(vs.size());
+      return (vol / n) * s3 / (6.0 * M_PI * M_PI) - surf * (s2 / n) / (16.0 * M_PI);
+    };
+    auto inverse = [&](double target) {
+      if (target <= 0) return e_min;
+      double lo = e_min, width = 1.0;
+      while (count(lo + width) < target) width *= 2.0;
+      double hi = lo + width;
+      for (int it = 0; it < 100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count(mid) < target) lo = mid; else hi = mid;
+      }
+      return 0.5 * (lo + hi);
+    };
+    int acc = 0;
+    for (int j = 0; j < p; ++j) {
+      out[j] = WindowSpec{0.5 * (inverse(acc) + inverse(acc + counts[j])), counts[j]};
+      acc += counts[j];
+    }
+  } else if (mode != TSG_PLAN_SAMPLED) {
     // E_{S,j} = E_{S,j-1} + ((E_max - E_min)/N)(n_{r,j} + n_{r,j-1})/2
     const double delta = (e_max - e_min) / double(c->N);
     double prev_s = e_min;
@@ -897,6 +936,7 @@ void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::
     op.basis = 0;
     op.keep = 0;
     op.select = TSG_SELECT_NEAREST;
+    op.max_restarts = std::max(o.max_restarts, 2000);
     (void)solve_windows(c, probes, op);
     std::vector<double> pc(S + 1), rho(S + 1);
     for (int i = 0; i < S; ++i) {

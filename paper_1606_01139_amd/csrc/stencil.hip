@@ -27,6 +27,20 @@ namespace {
 
 constexpr int kST = 512;  // threads per workgroup
 
+// Conditional load into registers (a value select, so the load stays a
+// global load rather than a generic one through a selected pointer).
+template <typename T>
+__device__ inline void ld_or_zero(const cplx<T>* p, bool ok, T& re, T& im) {
+  if (ok) {
+    const cplx<T> v = *p;
+    re = v.re;
+    im = v.im;
+  } else {
+    re = T(0);
+    im = T(0);
+  }
+}
+
 template <typename T, int R>
 __global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
@@ -57,27 +71,25 @@ __global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
   if constexpr (sizeof(T) == 8) { V = reinterpret_cast<const T*>(S.Vd); G = reinterpret_cast<const T*>(S.Gd); }
   else { V = reinterpret_cast<const T*>(S.Vf); G = reinterpret_cast<const T*>(S.Gf); }
   const T diag0 = T(S.diag0);
-  T cf[R + 1];
-#pragma unroll
-  for (int m = 1; m <= R; ++m) cf[m] = T(S.coef[m]);
 
   const int LW = tx + 2 * R, LH = ty + 2 * R;
   const int nhalo = 2 * R * LW + 2 * R * ty;
-  const cplx<T> zero{T(0), T(0)};
 
-  // q[j] holds the value at plane z - R + j
-  cplx<T> q[2 * R + 1];
+  // qr[j], qi[j] hold the value at plane z - R + j (separate real arrays keep
+  // the queue in registers)
+  T qr[2 * R + 1], qi[2 * R + 1];
 #pragma unroll
   for (int j = 0; j < 2 * R + 1; ++j) {
     const int zz = z0 - R + j;
-    q[j] = (inside && zz >= 0 && zz < nz) ? X[zz * plane + xy] : zero;
+    ld_or_zero(X + zz * plane + xy, inside && zz >= 0 && zz < nz, qr[j], qi[j]);
   }
   for (int z = z0; z < z1; ++z) {
     cplx<T>* L = smem + ((z - z0) & 1) * (LW * LH);
     // the next plane's value is fetched early to overlap its latency
     const int zn = z + R + 1;
-    const cplx<T> nxt = (inside && zn < nz) ? X[zn * plane + xy] : zero;
-    if (active) L[(ly + R) * LW + lx + R] = inside ? q[R] : zero;
+    T nr, ni;
+    ld_or_zero(X + zn * plane + xy, inside && zn < nz, nr, ni);
+    if (active) L[(ly + R) * LW + lx + R] = cplx<T>{qr[R], qi[R]};
     const cplx<T>* __restrict__ Xz = X + z * plane;
     for (int e = int(threadIdx.x); e < nhalo; e += kST) {
       int hx, hy;
@@ -92,31 +104,32 @@ __global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
         hx = k < R ? k : tx + k;
       }
       const int gx = bx * tx + hx - R, gy = by * ty + hy - R;
-      L[hy * LW + hx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? Xz[int64_t(gy) * nx + gx] : zero;
+      T hr, hi;
+      ld_or_zero(Xz + (int64_t(gy) * nx + gx), gx >= 0 && gx < nx && gy >= 0 && gy < ny, hr, hi);
+      L[hy * LW + hx] = cplx<T>{hr, hi};
     }
     __syncthreads();
     if (inside) {
       const int64_t n = z * plane + xy;
-      const cplx<T> c0 = q[R];
       const T d = diag0 + V[n];
       const T g = G[z];
-      cplx<T> acc{d * c0.re + g * c0.im, d * c0.im - g * c0.re};
+      T ar = d * qr[R] + g * qi[R], ai = d * qi[R] - g * qr[R];
       const cplx<T>* Lc = L + (ly + R) * LW + lx + R;
 #pragma unroll
       for (int m = 1; m <= R; ++m) {
-        cplx<T> s = q[R - m] + q[R + m];
-        s = s + Lc[-m];
-        s = s + Lc[m];
-        s = s + Lc[-m * LW];
-        s = s + Lc[m * LW];
-        acc.re = fma(cf[m], s.re, acc.re);
-        acc.im = fma(cf[m], s.im, acc.im);
+        const cplx<T> a = Lc[-m], b = Lc[m], c = Lc[-m * LW], e = Lc[m * LW];
+        const T sr = (qr[R - m] + qr[R + m]) + ((a.re + b.re) + (c.re + e.re));
+        const T si = (qi[R - m] + qi[R + m]) + ((a.im + b.im) + (c.im + e.im));
+        const T cm = T(S.coef[m]);
+        ar = fma(cm, sr, ar);
+        ai = fma(cm, si, ai);
       }
-      Y[n] = acc;
+      Y[n] = cplx<T>{ar, ai};
     }
 #pragma unroll
-    for (int j = 0; j < 2 * R; ++j) q[j] = q[j + 1];
-    q[2 * R] = nxt;
+    for (int j = 0; j < 2 * R; ++j) { qr[j] = qr[j + 1]; qi[j] = qi[j + 1]; }
+    qr[2 * R] = nr;
+    qi[2 * R] = ni;
   }
 }
 
@@ -129,27 +142,32 @@ void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin) {
   a.tx = tx;
   a.ty = kST / tx;
   a.tiles = ((nx + tx - 1) / tx) * ((ny + a.ty - 1) / a.ty);
-  // enough workgroups to fill the chip; a chunk re-reads 2R planes
+  // enough workgroups to fill the chip (a few per compute unit), but z
+  // chunks long enough that the 2R planes a chunk re-reads stay minor
   const int64_t base = int64_t(a.tiles) * a.ncols * std::max(nwin, 1);
-  int64_t nch = (2048 + base - 1) / base;
-  const int minchunk = std::max(8, 2 * a.radius);
+  int64_t nch = (1024 + base - 1) / base;
+  const int minchunk = std::max(32, 4 * a.radius);
   nch = std::max<int64_t>(1, std::min<int64_t>(nch, (nz + minchunk - 1) / minchunk));
   a.zchunk = int((nz + nch - 1) / nch);
+}
+
+template <typename T, int R>
+void launch_r(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
+  const size_t lds = size_t(2) * (a.tx + 2 * R) * (a.ty + 2 * R) * sizeof(cplx<T>);
+  hipLaunchKernelGGL((stencil_kernel<T, R>), grid, dim3(kST), lds, s, a);
 }
 
 template <typename T>
 void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s) {
   if (nwin <= 0 || a.ncols <= 0) return;
-  dim3 block(kST);
   dim3 grid(unsigned(a.tiles), unsigned((max_nz + a.zchunk - 1) / a.zchunk), unsigned(nwin * a.ncols));
-  const size_t lds = size_t(2) * (a.tx + 2 * a.radius) * (a.ty + 2 * a.radius) * sizeof(cplx<T>);
   switch (a.radius) {
-    case 1: hipLaunchKernelGGL((stencil_kernel<T, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((stencil_kernel<T, 2>), grid, block, lds, s, a); break;
-    case 3: hipLaunchKernelGGL((stencil_kernel<T, 3>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((stencil_kernel<T, 4>), grid, block, lds, s, a); break;
-    case 5: hipLaunchKernelGGL((stencil_kernel<T, 5>), grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL((stencil_kernel<T, 6>), grid, block, lds, s, a); break;
+    case 1: launch_r<T, 1>(a, grid, s); break;
+    case 2: launch_r<T, 2>(a, grid, s); break;
+    case 3: launch_r<T, 3>(a, grid, s); break;
+    case 4: launch_r<T, 4>(a, grid, s); break;
+    case 5: launch_r<T, 5>(a, grid, s); break;
+    default: launch_r<T, 6>(a, grid, s); break;
   }
 }
 

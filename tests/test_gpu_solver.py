@@ -149,6 +149,12 @@ def test_planner_matches_oracle(torch_cuda):
     ref = partition.sampled_windows(ea.real.min(), samples, partition.equal_counts(40, 2))
     assert [n for _, n in wins] == [20, 20]
     np.testing.assert_allclose([s for s, _ in wins], ref, rtol=0, atol=1e-6)
+    # semiclassical counting function
+    from paper_1606_01139_amd import PLAN_SEMICLASSICAL
+    wins, (emin, _) = oper.plan_windows(40, 2, PLAN_SEMICLASSICAL)
+    ref = partition.semiclassical_windows(w.V, g.h, (g.nx, g.ny, g.nz), ea.real.min(), partition.equal_counts(40, 2))
+    assert [n for _, n in wins] == [20, 20]
+    np.testing.assert_allclose([s for s, _ in wins], ref, rtol=0, atol=1e-6)
     oper.close()
 
 

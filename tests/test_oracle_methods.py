@@ -263,3 +263,40 @@ def test_sampled_windows_uniform_spectrum_closed_form():
     np.testing.assert_allclose(shifts, [e_min + d * (25 + 50 * j) for j in range(3)], atol=1e-12)
     # monotone and separated by n d for equal counts
     np.testing.assert_allclose(np.diff(shifts), 50 * d, atol=1e-12)
+
+
+def test_semiclassical_count_tracks_exact_counts():
+    # The phase-space estimate of the counting function against brute-force
+    # counts of the dense spectrum, on two small systems: within 10% once 40
+    # or more eigenvalues lie below E (the surface term matters: without it
+    # the estimate is 40-60% high on these small boxes).
+    from oracle import operator as op, eigen, partition
+    from synth.workloads import workload, small_workload
+    for w in (workload("c1"), small_workload(12, 10, 14, 3, seed=71)):
+        g = w.grid
+        gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
+        ea, _ = eigen.dense_spectrum(op.assemble_dense(g.nx, g.ny, g.nz, g.h, w.V, gL, gR))
+        re = np.sort(ea.real)
+        shape = (g.nx, g.ny, g.nz)
+        for E in np.linspace(re[40], re[min(400, len(re) - 1)], 9):
+            exact = np.sum(re <= E)
+            est = partition.semiclassical_count(w.V, g.h, shape, E)
+            assert abs(est - exact) <= 0.10 * exact, (E, exact, est)
+
+
+def test_semiclassical_windows_are_interval_midpoints():
+    from oracle import partition
+    from synth.workloads import workload
+    w = workload("c1")
+    g = w.grid
+    shape = (g.nx, g.ny, g.nz)
+    e_min = float(w.V.min())
+    counts = [20, 30, 10]
+    sh = partition.semiclassical_windows(w.V, g.h, shape, e_min, counts)
+    assert all(a < b for a, b in zip(sh, sh[1:]))
+    # each shift lies where the estimated count is halfway through its window
+    acc = 0
+    for s, c in zip(sh, counts):
+        n = partition.semiclassical_count(w.V, g.h, shape, s)
+        assert acc - 1e-6 <= n <= acc + c + 1e-6
+        acc += c
