@@ -211,6 +211,26 @@ tsg_status tsg_get_stats(tsg_ctx* ctx, int32_t j, tsg_window_stats* stats);
  * Errors: TSG_EINVAL (nE < 1, null), TSG_ESTATE (no combined set). */
 tsg_status tsg_transmission(tsg_ctx* ctx, const double* E, int32_t nE, double* T);
 
+/* Vector-Jacobian product of the transmission: the gradient of
+ * L = sum_e dL_dT[e] T(E[e]) (energies held fixed, T as in
+ * tsg_transmission over the combined eigenpairs) with respect to the
+ * potential V(r) and the absorber parameters.  The paper does not
+ * differentiate T; this is the derivative of what the pipeline computes.
+ * First-order perturbation of the c-normalised pairs (d eps_k = u_k^T dA u_k
+ * with dA = diag(dV) - i diag(dGamma)) gives the part inside the computed
+ * set from n x n products; the part outside it comes from the projected
+ * solves (eps_k - A) x_k = (I - U U^T) z_k, all k at once by COCR on
+ * P (eps_k - A) P with P = I - U U^T (complex symmetric since P^T = P).
+ *   E, dL_dT: host, nE values;
+ *   dL_dV:    host, N outputs (grid order as V);
+ *   dL_dabs:  host, 4 outputs: d/d amp_L, width_L, amp_R, width_R
+ *             (z_L, z_R held fixed).
+ * Errors: TSG_EINVAL, TSG_ESTATE (no combined set), TSG_ENOCONV (the
+ * projected solves missed their 1e-11 relative residual; outputs still
+ * written), TSG_EDEVICE. */
+tsg_status tsg_transmission_vjp(tsg_ctx* ctx, const double* E, int32_t nE, const double* dL_dT, double* dL_dV,
+                                double* dL_dabs);
+
 /* Y = A X for a block of ncols vectors (the stencil matrix-vector product of
  * Section 1, used by every iteration).  X, Y: device, ncols vectors of N
  * elements, vector c at ptr + c * ld (ld >= N), element type dtype

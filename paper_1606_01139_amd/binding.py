@@ -28,7 +28,8 @@ C128, C64 = 0, 1
 EXPORTS = [
     "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
     "tsg_solve_all_partitions", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
-    "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_apply_operator", "tsg_dense_eig",
+    "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_transmission_vjp", "tsg_apply_operator",
+    "tsg_dense_eig",
     "tsg_last_error", "tsg_destroy",
 ]
 
@@ -94,6 +95,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_get_partition.argtypes = [vp, i32, dp, i32, C.POINTER(i32), C.POINTER(vp), C.POINTER(i64)]
     lib.tsg_get_stats.argtypes = [vp, i32, C.POINTER(TsgWindowStats)]
     lib.tsg_transmission.argtypes = [vp, dp, i32, dp]
+    lib.tsg_transmission_vjp.argtypes = [vp, dp, i32, dp, dp, dp]
     lib.tsg_apply_operator.argtypes = [vp, vp, vp, i32, i64, i32]
     lib.tsg_dense_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.tsg_last_error.argtypes = [vp]
@@ -284,6 +286,21 @@ class Operator:
                                       T.ctypes.data_as(C.POINTER(C.c_double)))
         _check(self.lib, self.ctx, s)
         return T
+
+
+    def transmission_vjp(self, energies: Sequence[float], dL_dT: Sequence[float]):
+        """Gradient of sum_e dL_dT[e] T(E[e]) w.r.t. V (N,) and
+        (amp_L, width_L, amp_R, width_R) (4,)."""
+        E = np.ascontiguousarray(energies, dtype=np.float64)
+        w = np.ascontiguousarray(dL_dT, dtype=np.float64)
+        assert w.shape == E.shape
+        dV = np.zeros(self.N)
+        dab = np.zeros(4)
+        dp = C.POINTER(C.c_double)
+        s = self.lib.tsg_transmission_vjp(self.ctx, E.ctypes.data_as(dp), len(E), w.ctypes.data_as(dp),
+                                          dV.ctypes.data_as(dp), dab.ctypes.data_as(dp))
+        _check(self.lib, self.ctx, s)
+        return dV, dab
 
 
 def solve_batch(operators: Sequence["Operator"], windows: Sequence[Sequence[Tuple[float, int]]],

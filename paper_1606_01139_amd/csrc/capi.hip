@@ -21,6 +21,8 @@ tsg_status guarded(tsg_ctx* ctx, F&& f) {
     s = TSG_EINVAL; msg = e.what;
   } catch (const tsg::StateError& e) {
     s = TSG_ESTATE; msg = e.what;
+  } catch (const tsg::NotConverged& e) {
+    s = TSG_ENOCONV; msg = e.what;
   } catch (const tsg::OutOfMemory& e) {
     s = TSG_ENOMEM; msg = e.what;
   } catch (const tsg::DeviceError& e) {
@@ -256,6 +258,15 @@ tsg_status tsg_transmission(tsg_ctx* ctx, const double* E, int32_t nE, double* T
   if (!ctx) return fail(ctx, TSG_EINVAL, "ctx is NULL");
   return guarded(ctx, [&]() {
     tsg::transmission(ctx, E, nE, T);
+    return TSG_OK;
+  });
+}
+
+tsg_status tsg_transmission_vjp(tsg_ctx* ctx, const double* E, int32_t nE, const double* dL_dT, double* dL_dV,
+                                double* dL_dabs) {
+  if (!ctx) return fail(ctx, TSG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() {
+    tsg::transmission_vjp(ctx, E, nE, dL_dT, dL_dV, dL_dabs);
     return TSG_OK;
   });
 }

@@ -20,6 +20,10 @@ struct StateError {
   std::string what;
   explicit StateError(std::string w) : what(std::move(w)) {}
 };
+struct NotConverged {
+  std::string what;
+  explicit NotConverged(std::string w) : what(std::move(w)) {}
+};
 struct OutOfMemory {
   std::string what;
   explicit OutOfMemory(std::string w) : what(std::move(w)) {}
@@ -118,6 +122,10 @@ void combine(tsg_ctx* c, int keep_lowest);
 void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
                   double* e_range);
 void transmission(tsg_ctx* c, const double* E, int nE, double* T);
+// Gradient of sum_e w[e] T(E[e]) with respect to V (N values) and
+// (amp_L, width_L, amp_R, width_R); returns the COCR iterations used, or
+// throws NotConverged.
+int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, double* dV, double* dabs);
 void dense_eig(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st);
 
 }  // namespace tsg

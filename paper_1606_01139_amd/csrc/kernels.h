@@ -143,4 +143,29 @@ void project_out(c128* v, const c128* U, int64_t ldu, const int* partners, int n
 void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const c128* scale, int n, int64_t N,
                     hipStream_t st);
 
+// ---------------------------------------------------------------- adjoint
+// Building blocks of the transmission adjoint (adjoint.hip).  U, Y, Z are
+// N x n with contiguous columns (ld N); n x n matrices are row-major.
+void adj_gmat(const c128* eps, int n, const double* E, int nE, c128* G, hipStream_t st);
+void adj_kmats(const c128* G, int n, int nE, const double* w, const c128* MR, const c128* ML, c128* KRt, c128* KLt,
+               hipStream_t st);
+void adj_avec(const c128* G, int n, int nE, const double* w, const c128* W, c128* a, hipStream_t st);
+void adj_bmat(const c128* C, const c128* a, const c128* eps, int n, c128* B, hipStream_t st);
+void adj_conj(const c128* X, c128* Y, int64_t total, hipStream_t st);
+void adj_zcombine(const c128* YR, const c128* YL, const double* gR, const double* gL, int64_t N, int n,
+                  int64_t plane, c128* Z, hipStream_t st);
+void adj_rowdot(const c128* U, const c128* Y, int64_t N, int n, double scale, bool use_im, double* out,
+                hipStream_t st);
+int64_t adj_cocr_workspace(int64_t N, int n);
+void adj_cocr_sums(const c128* R, const c128* S, const c128* P, int64_t N, int n, double* part, double* out,
+                   hipStream_t st);
+void adj_shift(const c128* R, c128* AR, const c128* eps, int64_t N, int n, hipStream_t st);
+void adj_scalars(const double* sums, int n, int mode, c128* rho, c128* alpha, c128* beta, int* done,
+                 hipStream_t st);
+void adj_xr(c128* X, c128* R, const c128* P, const c128* MP, const c128* alpha, int64_t N, int n, hipStream_t st);
+void adj_p(c128* P, c128* MP, const c128* R, const c128* MR, const c128* beta, int64_t N, int n, hipStream_t st);
+void adj_add(c128* Y, const c128* X, int64_t total, hipStream_t st);
+void adj_absorber(const double* dGL, const double* dGR, const double* prof, int64_t N, int nz, int64_t plane,
+                  double* out, hipStream_t st);
+
 }  // namespace tsg
