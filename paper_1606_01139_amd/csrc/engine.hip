@@ -52,6 +52,11 @@ bool trace_on() {
   static const bool on = [] { const char* v = std::getenv("TSG_TRACE"); return v && v[0] == '1'; }();
   return on;
 }
+// TSG_PROGRESS=1 prints one summary line per restart cycle.
+bool progress_on() {
+  static const bool on = [] { const char* v = std::getenv("TSG_PROGRESS"); return v && v[0] == '1'; }();
+  return on;
+}
 // Restart cycles are replayed from a captured hipGraph unless the options or
 // TSG_NO_GRAPH=1 (or the K4 phase profiler) turn it off.
 bool graphs_allowed() {
@@ -374,6 +379,13 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
         still.push_back(w);
       }
     }
+    if (progress_on()) {
+      double worst_all = 0.0;
+      for (int w : active) worst_all = std::max(worst_all, out[w].rho.empty() ? 0.0 : *std::max_element(
+                                                                out[w].rho.begin(), out[w].rho.end()));
+      std::fprintf(stderr, "[tsg] %s cycle %d active %zu of %d, worst backward error %.2e\n",
+                   sizeof(T) == 4 ? "c64" : "c128", cyc, still.size(), nw, worst_all);
+    }
     if (still.size() != active.size()) {
       active = still;
       upload_slots();
@@ -562,7 +574,7 @@ void solve_core(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts&
     if (!outs[w].converged || P.stats.max_backward_error > o.tol) {
       conv[w] = false;
       P.stats.n_conv = 0;
-      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= itol;
+      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= o.tol;
     }
     parts.push_back(std::move(P));
   }
