@@ -65,6 +65,8 @@ def run_batch(args):
     ws = batch_workloads(args.n_sys)
     prec = FP64 if args.precision == "fp64" else FP32_BULK
     opts = default_opts(precision=prec, tol=1e-8, max_restarts=args.max_restarts)
+    if args.groups:
+        opts.groups = args.groups
     t0 = time.perf_counter()
     ops, wins = [], []
     for w in ws:
@@ -242,6 +244,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--basis", type=int, default=0)
     ap.add_argument("--keep", type=int, default=0)
+    ap.add_argument("--groups", type=int, default=0, help="window groups iterating concurrently (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-sys", type=int, default=64, help="systems of the ragged batch (config c3)")
     args = ap.parse_args()
@@ -268,6 +271,8 @@ def main():
             o.basis = args.basis
         if args.keep:
             o.keep = args.keep
+        if args.groups:
+            o.groups = args.groups
         return o
 
     opts = make_opts(prec)
@@ -301,7 +306,7 @@ def main():
                    "precision": args.precision, "unique_converged_eigenpairs": n, "holes": holes,
                    "status": int(status), "e_range": [round(x, 6) for x in erange],
                    "planner": args.plan, "plan_seconds_last_step": round(oper.plan_seconds, 3),
-                   "block": b, "basis": m},
+                   "block": b, "basis": m, "groups": opts.groups},
         "roofline": roof,
         "stencil": stencil,
         "windows": [{"shift": round(s.shift, 6), "nev": s.nev, "n_conv": s.n_conv, "restarts": s.restarts,

@@ -22,7 +22,9 @@
  *   - Complex numbers are pairs (re, im) of the stated real type.
  *   - Units are Hartree and bohr.
  *   - A context is used by one host thread at a time; distinct contexts are
- *     independent.  All GPU work of a context runs on its stream.
+ *     independent.  GPU work of a context runs on its stream, except that a
+ *     solve drains that stream, runs on internal streams (one per window
+ *     group) and has finished when it returns.
  */
 #ifndef TRANSEC_GPU_H
 #define TRANSEC_GPU_H
@@ -87,6 +89,10 @@ typedef struct {
   double bulk_tol;      /* TSG_FP32_BULK: backward error the complex64 phase stops at (default 1e-5) */
   int32_t graphs;       /* 1 (default): each restart cycle after the first is captured once as a
                            hipGraph and replayed; 0: every kernel is launched directly */
+  int32_t groups;       /* windows are dealt round-robin into this many groups, each a batched
+                           iteration on its own internal stream and host thread, so that the groups'
+                           small eigensolves and expansion steps can overlap (default 1: one batch,
+                           the faster choice measured on MI355X) */
 } tsg_opts;
 
 /* Per-window solver statistics of the last solve. */

@@ -52,7 +52,7 @@ class TsgOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("basis", C.c_int32),
                 ("keep", C.c_int32), ("max_restarts", C.c_int32), ("seed", C.c_uint64),
                 ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("groups", C.c_int32)]
 
 
 class TsgWindowStats(C.Structure):

@@ -82,6 +82,7 @@ void tsg_default_opts(tsg_opts* o) {
   o->select = TSG_SELECT_NEAREST;
   o->bulk_tol = 1e-5;
   o->graphs = 1;
+  o->groups = 1;
 }
 
 tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab, void* hip_stream,

@@ -184,15 +184,15 @@ __global__ __launch_bounds__(256) void gemm_cols_kernel(const cplx<T>* __restric
 // streams X once with one grid row per thread.
 constexpr int kSK = 8;
 
-template <typename TX, typename TY>
+template <typename TX, typename TY, int S>
 __global__ __launch_bounds__(256) void gram_skinny_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
                                                           const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
                                                           Rows rows, int r, int s, int nchunk, c128* __restrict__ P,
                                                           const int* __restrict__ wmap) {
-  constexpr int TI = 64, KR = 32;
+  constexpr int TI = 64, KR = 16;
   __shared__ cplx<TX> Xs[KR][TI + 1];
-  __shared__ c128 Ys[KR][kSK];
-  __shared__ c128 red[3][TI][kSK];
+  __shared__ c128 Ys[KR][S];
+  __shared__ c128 red[3][TI][S];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
   if (w < 0) return;  // idle slot (whole workgroup)
@@ -204,35 +204,35 @@ __global__ __launch_bounds__(256) void gram_skinny_kernel(const cplx<TX>* __rest
   const int t = threadIdx.x, il = t % TI, g = t / TI;
   X += int64_t(w) * wsx;
   Y += int64_t(w) * wsy;
-  c128 acc[kSK];
+  c128 acc[S];
 #pragma unroll
-  for (int q = 0; q < kSK; ++q) acc[q] = c128{0.0, 0.0};
+  for (int q = 0; q < S; ++q) acc[q] = c128{0.0, 0.0};
   for (int64_t nb = n0; nb < n1; nb += KR) {
     for (int e = t; e < KR * TI; e += 256) {
       const int cc = e / KR, rr = e % KR;
       const int64_t n = nb + rr;
       Xs[rr][cc] = (n < n1 && i0 + cc < r) ? X[int64_t(i0 + cc) * ldx + n] : cplx<TX>{TX(0), TX(0)};
     }
-    for (int e = t; e < KR * kSK; e += 256) {
-      const int q = e / KR, rr = e % KR;
+    if (t < KR * S) {
+      const int q = t / KR, rr = t % KR;
       const int64_t n = nb + rr;
       c128 v{0.0, 0.0};
       if (n < n1 && q < s) { const cplx<TY> y = Y[int64_t(q) * ldy + n]; v = c128{double(y.re), double(y.im)}; }
       Ys[rr][q] = v;
     }
     __syncthreads();
-#pragma unroll 2
+#pragma unroll
     for (int k = g; k < KR; k += 4) {
       const cplx<TX> xv = Xs[k][il];
       const c128 x{double(xv.re), double(xv.im)};
 #pragma unroll
-      for (int q = 0; q < kSK; ++q) fma_cacc(acc[q], x, Ys[k][q]);
+      for (int q = 0; q < S; ++q) fma_cacc(acc[q], x, Ys[k][q]);
     }
     __syncthreads();
   }
   if (g > 0)
 #pragma unroll
-    for (int q = 0; q < kSK; ++q) red[g - 1][il][q] = acc[q];
+    for (int q = 0; q < S; ++q) red[g - 1][il][q] = acc[q];
   __syncthreads();
   if (g == 0 && i0 + il < r) {
     c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
@@ -241,14 +241,14 @@ __global__ __launch_bounds__(256) void gram_skinny_kernel(const cplx<TX>* __rest
   }
 }
 
-template <typename T>
+template <typename T, int S>
 __global__ __launch_bounds__(256) void gemm_skinny_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx,
                                                           const c128* __restrict__ B, int64_t ldb, int64_t wsb,
                                                           cplx<T>* __restrict__ Y, int64_t ldy, int64_t wsy, Rows rows,
                                                           int r, int s, T beta, T alpha,
                                                           const int* __restrict__ wmap) {
   constexpr int KB = 128;
-  __shared__ cplx<T> Bs[KB][kSK];
+  __shared__ cplx<T> Bs[KB][S];
   const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
   if (w < 0) return;  // idle slot (whole workgroup)
   const int64_t N = rows.of(w);
@@ -258,13 +258,13 @@ __global__ __launch_bounds__(256) void gemm_skinny_kernel(const cplx<T>* __restr
   Y += int64_t(w) * wsy;
   B += int64_t(w) * wsb;
   const bool ok = n < N;
-  cplx<T> acc[kSK];
+  cplx<T> acc[S];
 #pragma unroll
-  for (int q = 0; q < kSK; ++q) acc[q] = cplx<T>{T(0), T(0)};
+  for (int q = 0; q < S; ++q) acc[q] = cplx<T>{T(0), T(0)};
   for (int k0 = 0; k0 < r; k0 += KB) {
     const int kn = min(KB, r - k0);
-    for (int e = threadIdx.x; e < KB * kSK; e += 256) {
-      const int kk = e / kSK, q = e % kSK;
+    for (int e = threadIdx.x; e < KB * S; e += 256) {
+      const int kk = e / S, q = e % S;
       c128 v = (kk < kn && q < s) ? B[int64_t(k0 + kk) * ldb + q] : c128{0.0, 0.0};
       Bs[kk][q] = cplx<T>{T(v.re), T(v.im)};
     }
@@ -274,13 +274,15 @@ __global__ __launch_bounds__(256) void gemm_skinny_kernel(const cplx<T>* __restr
       for (int kk = 0; kk < kn; ++kk) {
         const cplx<T> x = xp[int64_t(kk) * ldx];
 #pragma unroll
-        for (int q = 0; q < kSK; ++q) fma_acc(acc[q], x, Bs[kk][q]);
+        for (int q = 0; q < S; ++q) fma_acc(acc[q], x, Bs[kk][q]);
       }
     }
     __syncthreads();
   }
   if (!ok) return;
-  for (int q = 0; q < s; ++q) {
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    if (q >= s) break;
     cplx<T>* y = Y + int64_t(q) * ldy + n;
     cplx<T> v = alpha * acc[q];
     if (beta != T(0)) v = v + beta * (*y);
@@ -503,6 +505,39 @@ __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rin
   }
 }
 
+// Squared 2-norm of each column, one workgroup per (column, window); fixed
+// order of summation.
+template <typename T>
+__global__ __launch_bounds__(256) void colsq_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx, Rows rows,
+                                                    int s, double* __restrict__ out, const int* __restrict__ wmap) {
+  __shared__ double red[1][4];
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int j = blockIdx.y;
+  const int64_t N = rows.of(w);
+  const cplx<T>* x = X + int64_t(w) * wsx + int64_t(j) * ldx;
+  double v[1] = {0.0};
+  for (int64_t n = threadIdx.x; n < N; n += 256) {
+    const cplx<T> a = x[n];
+    v[0] += double(a.re) * double(a.re) + double(a.im) * double(a.im);
+  }
+  block_sums<1>(v, red);
+  if (threadIdx.x == 0) out[int64_t(w) * s + j] = v[0];
+}
+
+// Second Gram-Schmidt pass only where the first lost more than half of a
+// column's squared norm (the criterion of Daniel, Gragg, Kaufman and
+// Stewart, eta = 1/sqrt(2)): slot -> window, or -1.
+__global__ void dgks_kernel(const double* before, const double* after, int s, int nslot, const int* wmap, int* wmap2) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslot) return;
+  const int w = wmap ? wmap[slot] : slot;
+  int need = 0;
+  if (w >= 0)
+    for (int j = 0; j < s; ++j) need |= (after[int64_t(w) * s + j] < 0.5 * before[int64_t(w) * s + j]) ? 1 : 0;
+  wmap2[slot] = (w >= 0 && need) ? w : -1;
+}
+
 inline dim3 col_grid(int64_t N, int s, int nwin) { return dim3(unsigned((N + 255) / 256), unsigned(s), unsigned(nwin)); }
 
 }  // namespace
@@ -523,8 +558,19 @@ void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_
   if (cap < per) throw DeviceError("gram: partial workspace too small");
   const int nchunk = int(std::min<int64_t>(gram_chunks(rows.N, r, s, nwin), cap / per));
   if (s <= kSK) {
-    hipLaunchKernelGGL((gram_skinny_kernel<TX, TY>), dim3(nchunk, (r + 63) / 64, nwin), dim3(256), 0, st, X, ldx,
-                       wsx, Y, ldy, wsy, rows, r, s, nchunk, partials, wmap);
+    const dim3 grid(nchunk, (r + 63) / 64, nwin);
+    if (s == 1)
+      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 1>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+                         s, nchunk, partials, wmap);
+    else if (s == 2)
+      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 2>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+                         s, nchunk, partials, wmap);
+    else if (s <= 4)
+      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 4>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+                         s, nchunk, partials, wmap);
+    else
+      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, kSK>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows,
+                         r, s, nchunk, partials, wmap);
   } else {
     const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
     hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
@@ -541,8 +587,19 @@ void gemm_cols(const cplx<T>* X, int64_t ldx, int64_t wsx, const c128* B, int64_
                const int* wmap, double alpha) {
   if (nwin <= 0 || s <= 0) return;
   if (s <= kSK) {
-    hipLaunchKernelGGL((gemm_skinny_kernel<T>), dim3(unsigned((rows.N + 255) / 256), 1, nwin), dim3(256), 0, st, X,
-                       ldx, wsx, B, ldb, wsb, Y, ldy, wsy, rows, r, s, T(beta), T(alpha), wmap);
+    const dim3 grid(unsigned((rows.N + 255) / 256), 1, nwin);
+    if (s == 1)
+      hipLaunchKernelGGL((gemm_skinny_kernel<T, 1>), grid, dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy, wsy,
+                         rows, r, s, T(beta), T(alpha), wmap);
+    else if (s == 2)
+      hipLaunchKernelGGL((gemm_skinny_kernel<T, 2>), grid, dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy, wsy,
+                         rows, r, s, T(beta), T(alpha), wmap);
+    else if (s <= 4)
+      hipLaunchKernelGGL((gemm_skinny_kernel<T, 4>), grid, dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy, wsy,
+                         rows, r, s, T(beta), T(alpha), wmap);
+    else
+      hipLaunchKernelGGL((gemm_skinny_kernel<T, kSK>), grid, dim3(256), 0, st, X, ldx, wsx, B, ldb, wsb, Y, ldy,
+                         wsy, rows, r, s, T(beta), T(alpha), wmap);
     return;
   }
   hipLaunchKernelGGL((gemm_cols_kernel<T>), dim3(unsigned((rows.N + 63) / 64), unsigned((s + 31) / 32), nwin),
@@ -616,6 +673,21 @@ void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, Rows ro
   if (nwin <= 0 || s <= 0) return;
   hipLaunchKernelGGL((scale_kernel<T>), col_grid(rows.N, s, nwin), dim3(256), 0, st, Y, ldy, wsy, scale, s, rows,
                      wmap);
+}
+
+template <typename T>
+void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, double* out, hipStream_t st,
+                 const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  hipLaunchKernelGGL((colsq_kernel<T>), dim3(1, s, nwin), dim3(256), 0, st, X, ldx, wsx, rows, s, out, wmap);
+}
+template void col_sqnorms<double>(const c128*, int64_t, int64_t, Rows, int, int, double*, hipStream_t, const int*);
+template void col_sqnorms<float>(const c64*, int64_t, int64_t, Rows, int, int, double*, hipStream_t, const int*);
+
+void dgks_select(const double* before, const double* after, int s, int nslot, const int* wmap, int* wmap2,
+                 hipStream_t st) {
+  if (nslot <= 0) return;
+  hipLaunchKernelGGL(dgks_kernel, dim3((nslot + 63) / 64), dim3(64), 0, st, before, after, s, nslot, wmap, wmap2);
 }
 
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,

@@ -24,7 +24,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <numeric>
+#include <thread>
 
 #include "engine.h"
 
@@ -164,8 +166,8 @@ template <typename T> struct Batch {
   Rows rows;
   DevArr<cplx<T>> V, AV, Vr, AVr, F, Ft;
   DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, part;
-  DevArr<double> res, sig;
-  DevArr<int> flags, info, wmap, sel;
+  DevArr<double> res, sig, nb, na;
+  DevArr<int> flags, info, wmap, wmap2, sel;
 
   void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
     nw = nw_; ldN = S.ldN; rows = S.rows_arg(); m = m_; k = k_; b = b_; nv = nv_;
@@ -189,6 +191,7 @@ template <typename T> struct Batch {
     res.alloc(size_t(2) * nv * nw);
     sig.alloc(size_t(nw));
     flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
+    wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * b); na.alloc(size_t(nw) * b);
   }
   int64_t ws() const { return ldN * m; }
 };
@@ -202,11 +205,21 @@ void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, i
   const int* wm = B.wmap.p;
   hipStream_t st = S.st;
   const int64_t ldN = B.ldN;
-  for (int pass = 0; pass < 2 && J > 0; ++pass) {
-    gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, int64_t(B.m) * b, nw, B.part.p,
-               int64_t(B.part.n), st, wm);
-    gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wm,
-                 -1.0);
+  // classical Gram-Schmidt; the second pass runs only for windows whose
+  // block lost more than half of a column's squared norm in the first
+  if (J > 0) {
+    col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.nb.p, st, wm);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int* wp = pass == 0 ? wm : B.wmap2.p;
+      gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, int64_t(B.m) * b, nw, B.part.p,
+                 int64_t(B.part.n), st, wp);
+      gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wp,
+                   -1.0);
+      if (pass == 0) {
+        col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.na.p, st, wm);
+        dgks_select(B.nb.p, B.na.p, b, nw, wm, B.wmap2.p, st);
+      }
+    }
   }
   for (int pass = 0; pass < 2; ++pass) {
     cplx<T>* src = pass == 0 ? dest : B.Ft.p;
@@ -499,8 +512,8 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
 
 // Solves the windows (window w on system S.of(w)); returns the partitions in
 // window order and per-window convergence.
-void solve_core(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts& o, std::vector<Partition>& parts,
-                std::vector<bool>& conv) {
+void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts& o, std::vector<Partition>& parts,
+                 std::vector<bool>& conv) {
   const int nw = int(wins.size());
   if (nw < 1) throw InvalidArg("need at least one window");
   int nvmax = 0;
@@ -578,6 +591,64 @@ void solve_core(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts&
     }
     parts.push_back(std::move(P));
   }
+}
+
+// Solves windows of the systems ctx (window w on ctx[wsys[w]]; wsys empty:
+// all on ctx[0]).  The windows are dealt round-robin into o.groups groups;
+// each group is one batched iteration on its own stream and host thread, so
+// one group's small eigensolves (a few compute units) overlap the other
+// groups' bandwidth-bound expansion steps.  Results come back in window
+// order.
+void solve_core(const std::vector<tsg_ctx*>& ctx, const std::vector<int>& wsys, const std::vector<WindowSpec>& wins,
+                const tsg_opts& o, hipStream_t user, std::vector<Partition>& parts, std::vector<bool>& conv) {
+  const int nw = int(wins.size());
+  if (nw < 1) throw InvalidArg("need at least one window");
+  if (o.groups < 0) throw InvalidArg("groups must be >= 0");
+  const int G = std::max(1, std::min(nw, o.groups > 0 ? o.groups : 1));
+  check(hipStreamSynchronize(user), "sync");
+  for (size_t s = 1; s < ctx.size(); ++s) check(hipStreamSynchronize(ctx[s]->st), "sync");
+  std::vector<std::vector<int>> idx(G);
+  for (int w = 0; w < nw; ++w) idx[w % G].push_back(w);
+  std::vector<std::vector<Partition>> gparts(G);
+  std::vector<std::vector<bool>> gconv(G);
+  std::vector<std::exception_ptr> errs(G);
+  int dev = 0;
+  check(hipGetDevice(&dev), "hipGetDevice");
+  auto run = [&](int g) {
+    try {
+      check(hipSetDevice(dev), "hipSetDevice");
+      SolveStream ss(user);
+      Systems S;
+      std::vector<WindowSpec> wg;
+      std::vector<int> sg;
+      for (int w : idx[g]) {
+        wg.push_back(wins[w]);
+        sg.push_back(wsys.empty() ? 0 : wsys[w]);
+      }
+      if (ctx.size() == 1) one_system(S, ctx[0], ss.s);
+      else many_systems(S, ctx, sg, ss.s);
+      solve_group(S, wg, o, gparts[g], gconv[g]);
+    } catch (...) {
+      errs[g] = std::current_exception();
+    }
+  };
+  if (G == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int g = 0; g < G; ++g) th.emplace_back(run, g);
+    for (auto& t : th) t.join();
+  }
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  parts.clear();
+  parts.resize(nw);
+  conv.assign(nw, true);
+  for (int g = 0; g < G; ++g)
+    for (size_t q = 0; q < idx[g].size(); ++q) {
+      parts[idx[g][q]] = std::move(gparts[g][q]);
+      conv[idx[g][q]] = gconv[g][q];
+    }
 }
 
 }  // namespace
@@ -671,14 +742,11 @@ void apply_operator(tsg_ctx* c, const void* X, void* Y, int ncols, int64_t ld, i
 }
 
 bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_opts& o) {
-  SolveStream ss(c->st);
-  Systems S;
-  one_system(S, c, ss.s);
   c->have_combined = false;
   c->have_grams = false;
   std::vector<Partition> parts;
   std::vector<bool> conv;
-  solve_core(S, wins, o, parts, conv);
+  solve_core({c}, {}, wins, o, c->st, parts, conv);
   bool all = true;
   for (size_t w = 0; w < parts.size(); ++w) {
     all = all && conv[w];
@@ -698,13 +766,9 @@ void solve_batch(const std::vector<tsg_ctx*>& ctx, const std::vector<std::vector
     if (wins[s].empty()) throw InvalidArg("every system needs at least one window");
     for (const auto& w : wins[s]) { all.push_back(w); wsys.push_back(s); }
   }
-  for (int s = 1; s < ns; ++s) check(hipStreamSynchronize(ctx[s]->st), "sync");
-  SolveStream ss(ctx[0]->st);
-  Systems S;
-  many_systems(S, ctx, wsys, ss.s);
   std::vector<Partition> parts;
   std::vector<bool> conv;
-  solve_core(S, all, o, parts, conv);
+  solve_core(ctx, wsys, all, o, ctx[0]->st, parts, conv);
   ok.assign(ns, true);
   for (int s = 0; s < ns; ++s) {
     ctx[s]->parts.clear();

@@ -26,6 +26,11 @@ namespace {
 constexpr int kQT = 1024;     // threads per workgroup
 constexpr int kFin = 64;      // largest block finished in LDS
 constexpr int kMaxShift = 64;
+// Shifts per multishift sweep.  Measured on gfx950 (m = 304, 8 matrices):
+// 12-16 shifts are fastest (about 0.7x the time of 48), since the shift
+// computation (an eigenvalue QR of the trailing block in one wavefront)
+// grows with the cube of the count.
+constexpr int kShifts = 16;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -235,7 +240,7 @@ __device__ void apply_left(c128* Y, int64_t ld, int r0, int c0, int c1, const c1
 
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
                                                     c128* theta, int64_t wst, int* info, const int* __restrict__ wmap,
-                                                    int prof) {
+                                                    int prof, int nshift_max) {
   extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
   __shared__ QRShared S;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     }
     if (++sweeps > maxsweeps) { failed = true; break; }
     // shifts: eigenvalues of the trailing ns x ns block (in LDS)
-    const int ns = min(48, max(2, n / 3));
+    const int ns = min(nshift_max, max(2, n / 3));
     {
       c128* B = lds;
       const int b0 = ihi - ns + 1;
@@ -479,7 +484,7 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta
     attr_set = true;
   }
   hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, theta, wst,
-                     info, wmap, prof);
+                     info, wmap, prof, kShifts);
   if (prof) {
     unsigned long long z[8];
     (void)hipMemcpyFromSymbolAsync(z, HIP_SYMBOL(g_k4prof), sizeof(z), 0, hipMemcpyDeviceToHost, st);
