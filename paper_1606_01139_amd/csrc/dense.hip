@@ -179,65 +179,72 @@ __global__ __launch_bounds__(256) void gemm_cols_kernel(const cplx<T>* __restric
 
 // ------------------------------------------------------------- skinny
 // Tall-skinny forms for s <= kSK output columns (the block of new vectors):
-// the gram keeps 64 columns of X per workgroup, each thread one column of X
-// against all s columns of Y over a quarter of the staged rows; the update
-// streams X once with one grid row per thread.
+// the gram runs one wavefront per column of X; the update streams X once
+// with one grid row per thread.
 constexpr int kSK = 8;
 
+// Gram for s <= kSK with one wavefront per column of X: the lanes stride
+// down the column (contiguous, so every load is a full 1 KiB (c128) run),
+// the s columns of Y for the current rows are staged once per workgroup in
+// LDS, and each wavefront reduces its s sums at the end of its row chunk.
 template <typename TX, typename TY, int S>
-__global__ __launch_bounds__(256) void gram_skinny_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
-                                                          const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
-                                                          Rows rows, int r, int s, int nchunk, c128* __restrict__ P,
-                                                          const int* __restrict__ wmap) {
-  constexpr int TI = 64, KR = 16;
-  __shared__ cplx<TX> Xs[KR][TI + 1];
-  __shared__ c128 Ys[KR][S];
-  __shared__ c128 red[3][TI][S];
+__global__ __launch_bounds__(1024) void gram_wave_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                         const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
+                                                         Rows rows, int r, int s, int nchunk, c128* __restrict__ P,
+                                                         const int* __restrict__ wmap) {
+  constexpr int KR = 256;
+  __shared__ c128 Ys[S][KR];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
   if (w < 0) return;  // idle slot (whole workgroup)
   const int64_t N = rows.of(w);
-  const int i0 = blockIdx.y * TI;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int i = blockIdx.y * 16 + wv;
   const int chunk = blockIdx.x;
-  const int64_t rows_per = ((rows.N + nchunk - 1) / nchunk + KR - 1) / KR * KR;
-  const int64_t n0 = chunk * rows_per, n1 = min(N, n0 + rows_per);
-  const int t = threadIdx.x, il = t % TI, g = t / TI;
-  X += int64_t(w) * wsx;
+  const int64_t per = ((rows.N + nchunk - 1) / nchunk + KR - 1) / KR * KR;
+  const int64_t n0 = chunk * per, n1 = min(N, n0 + per);
+  const bool col_ok = i < r;
+  const cplx<TX>* x = X + int64_t(w) * wsx + int64_t(col_ok ? i : 0) * ldx;
   Y += int64_t(w) * wsy;
-  c128 acc[S];
+  double ar[S], ai[S];
 #pragma unroll
-  for (int q = 0; q < S; ++q) acc[q] = c128{0.0, 0.0};
+  for (int q = 0; q < S; ++q) ar[q] = ai[q] = 0.0;
   for (int64_t nb = n0; nb < n1; nb += KR) {
-    for (int e = t; e < KR * TI; e += 256) {
-      const int cc = e / KR, rr = e % KR;
-      const int64_t n = nb + rr;
-      Xs[rr][cc] = (n < n1 && i0 + cc < r) ? X[int64_t(i0 + cc) * ldx + n] : cplx<TX>{TX(0), TX(0)};
-    }
-    if (t < KR * S) {
-      const int q = t / KR, rr = t % KR;
+    for (int e = threadIdx.x; e < S * KR; e += 1024) {
+      const int q = e / KR, rr = e % KR;
       const int64_t n = nb + rr;
       c128 v{0.0, 0.0};
-      if (n < n1 && q < s) { const cplx<TY> y = Y[int64_t(q) * ldy + n]; v = c128{double(y.re), double(y.im)}; }
-      Ys[rr][q] = v;
+      if (q < s && n < n1) { const cplx<TY> yv = Y[int64_t(q) * ldy + n]; v = c128{double(yv.re), double(yv.im)}; }
+      Ys[q][rr] = v;
     }
     __syncthreads();
+    if (col_ok) {
 #pragma unroll
-    for (int k = g; k < KR; k += 4) {
-      const cplx<TX> xv = Xs[k][il];
-      const c128 x{double(xv.re), double(xv.im)};
+      for (int rr = lane; rr < KR; rr += 64) {
+        const int64_t n = nb + rr;
+        if (n < n1) {
+          const cplx<TX> xv = x[n];
+          const double xr = double(xv.re), xi = double(xv.im);
 #pragma unroll
-      for (int q = 0; q < S; ++q) fma_cacc(acc[q], x, Ys[k][q]);
+          for (int q = 0; q < S; ++q) {
+            const c128 y = Ys[q][rr];
+            // conj(x) * y
+            ar[q] = fma(xr, y.re, fma(xi, y.im, ar[q]));
+            ai[q] = fma(xr, y.im, fma(-xi, y.re, ai[q]));
+          }
+        }
+      }
     }
     __syncthreads();
   }
-  if (g > 0)
 #pragma unroll
-    for (int q = 0; q < S; ++q) red[g - 1][il][q] = acc[q];
-  __syncthreads();
-  if (g == 0 && i0 + il < r) {
-    c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
-    for (int q = 0; q < s; ++q)
-      Pw[int64_t(i0 + il) * s + q] = acc[q] + red[0][il][q] + red[1][il][q] + red[2][il][q];
+  for (int q = 0; q < S; ++q) {
+    ar[q] = wave_sum(ar[q]);
+    ai[q] = wave_sum(ai[q]);
+  }
+  if (col_ok && lane == 0) {
+    c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s + int64_t(i) * s;
+    for (int q = 0; q < s; ++q) Pw[q] = c128{ar[q], ai[q]};
   }
 }
 
@@ -505,24 +512,28 @@ __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rin
   }
 }
 
-// Squared 2-norm of each column, one workgroup per (column, window); fixed
-// order of summation.
+// Squared 2-norm of each column: per-chunk partials (one workgroup per
+// (chunk, column, window)), summed in a fixed order by colsum_reduce_kernel.
 template <typename T>
 __global__ __launch_bounds__(256) void colsq_kernel(const cplx<T>* __restrict__ X, int64_t ldx, int64_t wsx, Rows rows,
-                                                    int s, double* __restrict__ out, const int* __restrict__ wmap) {
+                                                    int s, int nchunk, double* __restrict__ P,
+                                                    const int* __restrict__ wmap) {
   __shared__ double red[1][4];
-  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  const int wz = blockIdx.z;
+  const int w = wmap ? wmap[wz] : wz;
   if (w < 0) return;  // idle slot (whole workgroup)
-  const int j = blockIdx.y;
+  const int chunk = blockIdx.x, j = blockIdx.y;
   const int64_t N = rows.of(w);
+  const int64_t per = (rows.N + nchunk - 1) / nchunk;
+  const int64_t n0 = chunk * per, n1 = min(N, n0 + per);
   const cplx<T>* x = X + int64_t(w) * wsx + int64_t(j) * ldx;
   double v[1] = {0.0};
-  for (int64_t n = threadIdx.x; n < N; n += 256) {
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += 256) {
     const cplx<T> a = x[n];
     v[0] += double(a.re) * double(a.re) + double(a.im) * double(a.im);
   }
   block_sums<1>(v, red);
-  if (threadIdx.x == 0) out[int64_t(w) * s + j] = v[0];
+  if (threadIdx.x == 0) P[(int64_t(wz) * nchunk + chunk) * s + j] = v[0];
 }
 
 // Second Gram-Schmidt pass only where the first lost more than half of a
@@ -556,20 +567,24 @@ void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_
   if (nwin <= 0 || r <= 0 || s <= 0) return;
   const int64_t per = int64_t(nwin) * r * s;
   if (cap < per) throw DeviceError("gram: partial workspace too small");
-  const int nchunk = int(std::min<int64_t>(gram_chunks(rows.N, r, s, nwin), cap / per));
+  int nchunk = int(std::min<int64_t>(gram_chunks(rows.N, r, s, nwin), cap / per));
   if (s <= kSK) {
-    const dim3 grid(nchunk, (r + 63) / 64, nwin);
+    // about 2048 workgroups of 16 wavefronts, each wavefront at least 1024 rows
+    const int64_t cb = int64_t((r + 15) / 16) * nwin;
+    int64_t want = std::max<int64_t>(1, std::min<int64_t>((2048 + cb - 1) / cb, (rows.N + 1023) / 1024));
+    nchunk = int(std::min<int64_t>(want, cap / per));
+    const dim3 grid(nchunk, (r + 15) / 16, nwin);
     if (s == 1)
-      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 1>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+      hipLaunchKernelGGL((gram_wave_kernel<TX, TY, 1>), grid, dim3(1024), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
                          s, nchunk, partials, wmap);
     else if (s == 2)
-      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 2>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+      hipLaunchKernelGGL((gram_wave_kernel<TX, TY, 2>), grid, dim3(1024), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
                          s, nchunk, partials, wmap);
     else if (s <= 4)
-      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, 4>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
+      hipLaunchKernelGGL((gram_wave_kernel<TX, TY, 4>), grid, dim3(1024), 0, st, X, ldx, wsx, Y, ldy, wsy, rows, r,
                          s, nchunk, partials, wmap);
     else
-      hipLaunchKernelGGL((gram_skinny_kernel<TX, TY, kSK>), grid, dim3(256), 0, st, X, ldx, wsx, Y, ldy, wsy, rows,
+      hipLaunchKernelGGL((gram_wave_kernel<TX, TY, kSK>), grid, dim3(1024), 0, st, X, ldx, wsx, Y, ldy, wsy, rows,
                          r, s, nchunk, partials, wmap);
   } else {
     const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
@@ -676,13 +691,21 @@ void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, Rows ro
 }
 
 template <typename T>
-void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, double* out, hipStream_t st,
-                 const int* wmap) {
+void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, double* out, double* partials,
+                 int64_t cap, hipStream_t st, const int* wmap) {
   if (nwin <= 0 || s <= 0) return;
-  hipLaunchKernelGGL((colsq_kernel<T>), dim3(1, s, nwin), dim3(256), 0, st, X, ldx, wsx, rows, s, out, wmap);
+  const int64_t per = int64_t(nwin) * s;
+  if (cap < per) throw DeviceError("col_sqnorms: partial workspace too small");
+  const int nchunk = int(std::min<int64_t>(colsum_chunks(rows.N, s, nwin), cap / per));
+  hipLaunchKernelGGL((colsq_kernel<T>), dim3(nchunk, s, nwin), dim3(256), 0, st, X, ldx, wsx, rows, s, nchunk,
+                     partials, wmap);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((s + 255) / 256, nwin), dim3(256), 0, st, partials, nchunk, s, 1, out,
+                     wmap);
 }
-template void col_sqnorms<double>(const c128*, int64_t, int64_t, Rows, int, int, double*, hipStream_t, const int*);
-template void col_sqnorms<float>(const c64*, int64_t, int64_t, Rows, int, int, double*, hipStream_t, const int*);
+template void col_sqnorms<double>(const c128*, int64_t, int64_t, Rows, int, int, double*, double*, int64_t,
+                                  hipStream_t, const int*);
+template void col_sqnorms<float>(const c64*, int64_t, int64_t, Rows, int, int, double*, double*, int64_t, hipStream_t,
+                                 const int*);
 
 void dgks_select(const double* before, const double* after, int s, int nslot, const int* wmap, int* wmap2,
                  hipStream_t st) {

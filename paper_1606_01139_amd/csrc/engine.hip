@@ -208,7 +208,9 @@ void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, i
   // classical Gram-Schmidt; the second pass runs only for windows whose
   // block lost more than half of a column's squared norm in the first
   if (J > 0) {
-    col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.nb.p, st, wm);
+    double* cpart = reinterpret_cast<double*>(B.part.p);
+    const int64_t ccap = 2 * int64_t(B.part.n);
+    col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.nb.p, cpart, ccap, st, wm);
     for (int pass = 0; pass < 2; ++pass) {
       const int* wp = pass == 0 ? wm : B.wmap2.p;
       gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, int64_t(B.m) * b, nw, B.part.p,
@@ -216,7 +218,7 @@ void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, i
       gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wp,
                    -1.0);
       if (pass == 0) {
-        col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.na.p, st, wm);
+        col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.na.p, cpart, ccap, st, wm);
         dgks_select(B.nb.p, B.na.p, b, nw, wm, B.wmap2.p, st);
       }
     }
@@ -430,6 +432,9 @@ void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& 
   if (k < round_up(nvmax, b)) k = round_up(nvmax, b);
   if (k + b > m) throw InvalidArg("basis too small for the requested eigenpairs (need keep + block <= basis)");
   if (k + nvmax > m) throw InvalidArg("basis too small: keep + nev must not exceed basis");
+  // the restart basis is orthonormalised in LDS: (k + m) * 8 complex values
+  if (int64_t(k + m) * 8 * 16 + int64_t(m) * 4 > 150 * 1024)
+    throw InvalidArg("basis too large: keep + basis must stay below about 1200");
 }
 
 // FP64 finish of one window's nev vectors (device c128, N x nev, ld N):

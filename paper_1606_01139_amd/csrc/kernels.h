@@ -99,8 +99,8 @@ void scale_cols(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* scale, Rows ro
 
 // Squared 2-norms of the s columns of each window: out[w*s + j].
 template <typename T>
-void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, double* out, hipStream_t st,
-                 const int* wmap = nullptr);
+void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, int nwin, double* out, double* partials,
+                 int64_t cap, hipStream_t st, const int* wmap = nullptr);
 // wmap2[slot] = wmap[slot] where some column kept less than half its squared
 // norm through a Gram-Schmidt pass (after < before / 2), else -1.
 void dgks_select(const double* before, const double* after, int s, int nslot, const int* wmap, int* wmap2,

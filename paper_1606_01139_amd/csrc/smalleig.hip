@@ -17,6 +17,7 @@ namespace tsg {
 namespace {
 
 constexpr int kEigThreads = 512;
+constexpr int kSB = 8;  // column block of the restart-basis orthonormalisation
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -90,21 +91,32 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
       }
     }
     __syncthreads();
-    // right: row r of H and of Z: row[k+1..] -= beta (row[k+1..] v) v^H (one wavefront per row)
-    for (int r = wv; r < 2 * m; r += NW) {
-      c128* row = (r < m) ? (H + int64_t(r) * m) : (Z + int64_t(r - m) * m);
-      double sr = 0.0, si = 0.0;
-      for (int j = lane; j < len; j += 64) {
-        const c128 a = row[k + 1 + j], b = v[j];
-        sr += a.re * b.re - a.im * b.im;
-        si += a.re * b.im + a.im * b.re;
-      }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      const c128 sc = beta * c128{sr, si};
-      for (int j = lane; j < len; j += 64) {
-        c128& h = row[k + 1 + j];
-        h = h - sc * conj(v[j]);
+    // right: row r of H and of Z: row[k+1..] -= beta (row[k+1..] v) v^H;
+    // four rows per wavefront, 16 lanes per row
+    {
+      const int sub = lane & 15, rsel = lane >> 4;
+      for (int r0 = wv * 4; r0 < 2 * m; r0 += NW * 4) {
+        const int r = r0 + rsel;
+        const bool ok = r < 2 * m;
+        c128* row = !ok ? H : (r < m) ? (H + int64_t(r) * m) : (Z + int64_t(r - m) * m);
+        double sr = 0.0, si = 0.0;
+        if (ok)
+          for (int j = sub; j < len; j += 16) {
+            const c128 a = row[k + 1 + j], b = v[j];
+            sr += a.re * b.re - a.im * b.im;
+            si += a.re * b.im + a.im * b.re;
+          }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          sr += __shfl_xor(sr, o, 16);
+          si += __shfl_xor(si, o, 16);
+        }
+        const c128 sc = beta * c128{sr, si};
+        if (ok)
+          for (int j = sub; j < len; j += 16) {
+            c128& h = row[k + 1 + j];
+            h = h - sc * conj(v[j]);
+          }
       }
     }
     __syncthreads();
@@ -193,8 +205,8 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
                                                              int64_t wss, const int* __restrict__ wmap) {
   extern __shared__ unsigned char smraw[];
   int* order = reinterpret_cast<int*>(smraw);                       // m
-  c128* vec = reinterpret_cast<c128*>(smraw + ((m * sizeof(int) + 15) / 16) * 16);  // m
-  c128* coef = vec + m;                                              // k
+  c128* coef = reinterpret_cast<c128*>(smraw + ((m * sizeof(int) + 15) / 16) * 16);  // k * kSB
+  c128* Wb = coef + size_t(k > 0 ? k : 1) * kSB;                                      // m * kSB
   __shared__ double red[256];
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
@@ -222,37 +234,80 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
     for (int i = t; i < m; i += 256) out[int64_t(i) * ld + k + q] = Y[int64_t(i) * m + src];
     if (t == 0) thsel[int64_t(w) * wss + q] = th[src];
   }
-  // orthonormal basis of the first k selected eigenvectors (CGS2)
-  for (int q = 0; q < k; ++q) {
-    const int src = order[q];
-    for (int i = t; i < m; i += 256) vec[i] = Y[int64_t(i) * m + src];
+  // orthonormal basis of the first k selected eigenvectors: blocks of kSB
+  // columns staged in LDS, each made orthogonal to the columns before it by
+  // two passes of block classical Gram-Schmidt, then orthonormalised inside
+  // the block by two passes of classical Gram-Schmidt column by column
+  for (int q0 = 0; q0 < k; q0 += kSB) {
+    const int nb = min(kSB, k - q0);
+    for (int e = t; e < m * kSB; e += 256) {
+      const int i = e / kSB, j = e % kSB;
+      Wb[e] = j < nb ? Y[int64_t(i) * m + order[q0 + j]] : c128{0.0, 0.0};
+    }
     __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int p = t; p < q; p += 256) {
-        c128 s{0.0, 0.0};
-        for (int i = 0; i < m; ++i) fma_cacc(s, out[int64_t(i) * ld + p], vec[i]);
-        coef[p] = s;
+    for (int pass = 0; pass < 2 && q0 > 0; ++pass) {
+      // C = out[:, :q0]^H W  (q0 x nb)
+      for (int e = t; e < q0 * nb; e += 256) {
+        const int p = e % q0, j = e / q0;
+        c128 s0{0.0, 0.0}, s1{0.0, 0.0};
+        int i = 0;
+        for (; i + 1 < m; i += 2) {
+          fma_cacc(s0, out[int64_t(i) * ld + p], Wb[i * kSB + j]);
+          fma_cacc(s1, out[int64_t(i + 1) * ld + p], Wb[(i + 1) * kSB + j]);
+        }
+        if (i < m) fma_cacc(s0, out[int64_t(i) * ld + p], Wb[i * kSB + j]);
+        coef[p * kSB + j] = s0 + s1;
       }
       __syncthreads();
+      // W -= out[:, :q0] C, one thread per row
       for (int i = t; i < m; i += 256) {
-        c128 v = vec[i];
-        for (int p = 0; p < q; ++p) v = v - out[int64_t(i) * ld + p] * coef[p];
-        vec[i] = v;
+        c128 acc[kSB];
+#pragma unroll
+        for (int j = 0; j < kSB; ++j) acc[j] = c128{0.0, 0.0};
+        const c128* row = out + int64_t(i) * ld;
+        for (int p = 0; p < q0; ++p) {
+          const c128 a = row[p];
+#pragma unroll
+          for (int j = 0; j < kSB; ++j) fma_acc(acc[j], a, coef[p * kSB + j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kSB; ++j) Wb[i * kSB + j] = Wb[i * kSB + j] - acc[j];
       }
       __syncthreads();
     }
-    double part = 0.0;
-    for (int i = t; i < m; i += 256) part += norm2(vec[i]);
-    red[t] = part;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (t < o) red[t] += red[t + o];
+    for (int q = 0; q < nb; ++q) {
+      for (int pass = 0; pass < 2 && q > 0; ++pass) {
+        if (t < q) {
+          c128 s{0.0, 0.0};
+          for (int i = 0; i < m; ++i) fma_cacc(s, Wb[i * kSB + t], Wb[i * kSB + q]);
+          coef[t] = s;
+        }
+        __syncthreads();
+        for (int i = t; i < m; i += 256) {
+          c128 v = Wb[i * kSB + q];
+          for (int p = 0; p < q; ++p) v = v - Wb[i * kSB + p] * coef[p];
+          Wb[i * kSB + q] = v;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int i = t; i < m; i += 256) part += norm2(Wb[i * kSB + q]);
+      red[t] = part;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+      }
+      const double nrm = sqrt(red[0]);
+      __syncthreads();
+      const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = t; i < m; i += 256) Wb[i * kSB + q] = f * Wb[i * kSB + q];
       __syncthreads();
     }
-    const double nrm = sqrt(red[0]);
-    __syncthreads();
-    const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int i = t; i < m; i += 256) out[int64_t(i) * ld + q] = f * vec[i];
+    for (int e = t; e < m * nb; e += 256) {
+      const int i = e / nb, j = e % nb;
+      out[int64_t(i) * ld + q0 + j] = Wb[i * kSB + j];
+    }
     __syncthreads();
   }
 }
@@ -279,7 +334,19 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
                     int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss, int nwin, hipStream_t st,
                     const int* wmap) {
   if (nwin <= 0) return;
-  const size_t smem = ((m * sizeof(int) + 15) / 16) * 16 + size_t(m + k) * sizeof(c128);
+  const size_t smem = ((m * sizeof(int) + 15) / 16) * 16 + size_t(std::max(k, 1) + m) * kSB * sizeof(c128);
+  // beyond the default 64 KiB the kernel must be allowed more dynamic LDS
+  // (its static part is 2 KiB of the 160 KiB)
+  if (smem > size_t(150) * 1024) throw DeviceError("select_restart: basis too large for the LDS");
+  if (smem > size_t(64) * 1024) {
+    static size_t granted = 0;
+    if (smem > granted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(select_restart_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(smem));
+      if (e != hipSuccess) throw DeviceError(std::string("select_restart: LDS attribute: ") + hipGetErrorString(e));
+      granted = smem;
+    }
+  }
   hipLaunchKernelGGL(select_restart_kernel, dim3(nwin), dim3(256), smem, st, theta, wst, Y, wsy, m, sigma, mode, k,
                      nev, out, wso, theta_sel, wss, wmap);
 }

@@ -479,8 +479,9 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta
   }
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(schur_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(schur_lds_bytes()));
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(schur_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(schur_lds_bytes()));
+    if (e != hipSuccess) throw DeviceError(std::string("schur: LDS attribute: ") + hipGetErrorString(e));
     attr_set = true;
   }
   hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, theta, wst,
