@@ -46,9 +46,10 @@ __device__ double block_sum(double v, double* red) {
 // (H v) run one wavefront per row so that every load is coalesced.
 __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Zall,
                                                                  int64_t wsz, const int* __restrict__ wmap) {
-  extern __shared__ c128 sm[];  // v[m]
+  extern __shared__ c128 sm[];  // v[m], then 4 x kEigThreads partial column sums
   __shared__ double red[kEigThreads / 64];
   c128* v = sm;
+  c128* pd = sm + m;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
@@ -78,16 +79,42 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
     if (t == 0) v[0] = x0 + alpha * ph;
     __syncthreads();
     const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
-    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k (one thread per column)
-    for (int j = k + t; j < m; j += kEigThreads) {
+    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k; each column
+    // is split over P row ranges (P threads per column, partial sums in LDS)
+    {
+      const int ncols = m - k;
+      const int P = max(1, min(4, kEigThreads / ncols));
+      const int col = k + t % ncols, part = t / ncols;
+      const bool act = part < P;
+      const int r0 = act ? (part * len) / P : 0, r1 = act ? ((part + 1) * len) / P : 0;
       c128 sacc{0.0, 0.0};
+      if (act) {
 #pragma unroll 8
-      for (int i = 0; i < len; ++i) fma_cacc(sacc, v[i], H[int64_t(k + 1 + i) * m + j]);
-      sacc = beta * sacc;
+        for (int i = r0; i < r1; ++i) fma_cacc(sacc, v[i], H[int64_t(k + 1 + i) * m + col]);
+        pd[part * kEigThreads + (col - k)] = sacc;
+      }
+      __syncthreads();
+      if (act) {
+        c128 tot{0.0, 0.0};
+        for (int q = 0; q < P; ++q) tot = tot + pd[q * kEigThreads + (col - k)];
+        tot = beta * tot;
 #pragma unroll 8
-      for (int i = 0; i < len; ++i) {
-        c128& h = H[int64_t(k + 1 + i) * m + j];
-        h = h - v[i] * sacc;
+        for (int i = r0; i < r1; ++i) {
+          c128& h = H[int64_t(k + 1 + i) * m + col];
+          h = h - v[i] * tot;
+        }
+      }
+      // columns beyond what one pass of threads covers (ncols > kEigThreads)
+      for (int j = k + kEigThreads + t; j < m && P == 1; j += kEigThreads) {
+        c128 sa{0.0, 0.0};
+#pragma unroll 8
+        for (int i = 0; i < len; ++i) fma_cacc(sa, v[i], H[int64_t(k + 1 + i) * m + j]);
+        sa = beta * sa;
+#pragma unroll 8
+        for (int i = 0; i < len; ++i) {
+          c128& h = H[int64_t(k + 1 + i) * m + j];
+          h = h - v[i] * sa;
+        }
       }
     }
     __syncthreads();
@@ -321,7 +348,7 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   if (nwin <= 0 || m <= 0) return;
   c128* Z = work;               // m*m per window at stride wsw
   c128* X = work + int64_t(m) * m;
-  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), size_t(m) * sizeof(c128), st, H, wsh, m,
+  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), (size_t(m) + 4 * kEigThreads) * sizeof(c128), st, H, wsh, m,
                      Z, wsw, wmap);
   launch_schur(H, wsh, m, Z, wsw, theta, wst, info, nwin, st, wmap);
   hipLaunchKernelGGL(trevc_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, H, wsh, m, X, wsw, wmap);

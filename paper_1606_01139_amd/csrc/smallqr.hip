@@ -23,7 +23,10 @@
 namespace tsg {
 namespace {
 
-constexpr int kQT = 1024;     // threads per workgroup
+#ifndef TSG_SCHUR_THREADS
+#define TSG_SCHUR_THREADS 1024
+#endif
+constexpr int kQT = TSG_SCHUR_THREADS;  // threads per workgroup
 constexpr int kFin = 64;      // largest block finished in LDS
 constexpr int kMaxShift = 64;
 // Shifts per multishift sweep.  Measured on gfx950 (m = 304, 8 matrices):
@@ -31,6 +34,12 @@ constexpr int kMaxShift = 64;
 // computation (an eigenvalue QR of the trailing block in one wavefront)
 // grows with the cube of the count.
 constexpr int kShifts = 16;
+// Rotation items a thread loads before it stores any (memory-level
+// parallelism of the chase phases).
+#ifndef TSG_SCHUR_BATCH
+#define TSG_SCHUR_BATCH 4
+#endif
+constexpr int kBatch = TSG_SCHUR_BATCH;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -380,11 +389,11 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       {
         const int W = m - lo;
         const int total = nact * W;
-        for (int base = t; base < total; base += kQT * 4) {
-          c128 av[4], bv[4];
-          int pr[4], cl[4];
+        for (int base = t; base < total; base += kQT * kBatch) {
+          c128 av[kBatch], bv[kBatch];
+          int pr[kBatch], cl[kBatch];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
             pr[q] = -1;
             if (idx < total) {
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
             }
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kBatch; ++q) {
             if (pr[q] < 0) continue;
             const int j = pr[q], p = S.bp[j], col = cl[q];
             const double c = S.bc[j];
@@ -418,12 +427,12 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       {
         const int Rh = ihi + 1;
         const int total = (Rh + m) * nact;
-        for (int base = t; base < total; base += kQT * 4) {
-          c128 av[4], bv[4];
-          c128* rp[4];
-          int pr[4];
+        for (int base = t; base < total; base += kQT * kBatch) {
+          c128 av[kBatch], bv[kBatch];
+          c128* rp[kBatch];
+          int pr[kBatch];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
             pr[q] = -1;
             if (idx < total && nact > 0) {
@@ -446,7 +455,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
             }
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kBatch; ++q) {
             if (pr[q] < 0) continue;
             const int j = pr[q], p = S.bp[j];
             const double c = S.bc[j];
