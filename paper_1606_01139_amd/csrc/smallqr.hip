@@ -37,7 +37,7 @@ constexpr int kShifts = 16;
 // Rotation items a thread loads before it stores any (memory-level
 // parallelism of the chase phases).
 #ifndef TSG_SCHUR_BATCH
-#define TSG_SCHUR_BATCH 4
+#define TSG_SCHUR_BATCH 2
 #endif
 constexpr int kBatch = TSG_SCHUR_BATCH;
 
