@@ -114,3 +114,18 @@ def extremal_real(A, which: str, dense: bool):
     w = sla.eigs(A, k=1, which=which, tol=1e-13, ncv=40, maxiter=200000,
                  return_eigenvectors=False)
     return complex(w[0])
+
+
+def lowest_real(A_sparse: sp.spmatrix, k: int, tol: float = 1e-13) -> np.ndarray:
+    """The k eigenvalues of smallest real part (Section 2.2: the exterior end of
+    the spectrum where the partitioned interval starts), by ARPACK 'SR' with
+    eigenvectors; each eigenvalue is replaced by its c-Rayleigh quotient and the
+    result is sorted by real part."""
+    N = A_sparse.shape[0]
+    kk = min(k + 4, N - 2)
+    w, U = sla.eigs(A_sparse, k=kk, which="SR", tol=tol, ncv=min(N - 1, max(40, 3 * kk)),
+                    maxiter=200000)
+    U = c_normalize(U)
+    eps = np.sum(U * (A_sparse @ U), axis=0) / np.sum(U * U, axis=0)
+    return eps[order_real(eps)][:k]
+

@@ -38,7 +38,16 @@ Readings where the paper is silent or garbled:
     n_{r,1} + ... + n_{r,j-1} and n_{r,1} + ... + n_{r,j} (the interval
     midpoints of Section 3); beyond the last sample the last density is
     extended.  The region's top is guessed from the free-particle counting
-    function of the box (Weyl's law), which only decides where to sample.
+    function of the box (Weyl's law), which only decides where to sample;
+  * the repeat loop of Algorithm 1 (hole filling) orders the partitions by
+    shift, so that interface j lies between partitions j and j+1; the gap of
+    a flagged interface is min Re of the upper partition's eigenvalues minus
+    max Re of the lower one's; the inserted count n = ceil(3/2 gap / Delta)
+    with Delta = (E_max - E_min)/N is clamped to [1, n_cap], n_cap being the
+    largest planned n_{r,j}: Delta is a mean over the whole spectrum, so at
+    its low end, where eigenvalues are sparser than the mean, the formula
+    asks for far more than one window holds, and the loop repeats instead.
+    The loop stops when no flag is left or after a given number of rounds.
 """
 from __future__ import annotations
 
@@ -223,3 +232,46 @@ def combine(windows: Sequence[Tuple[np.ndarray, np.ndarray]], norm_a: float,
     if keep_lowest and len(eps) > keep_lowest:
         eps, U, own = eps[:keep_lowest], U[:, :keep_lowest], own[:keep_lowest]
     return Combined(eps, U, own, holes, removed)
+
+
+def hole_fill_windows(parts_eps: Sequence[np.ndarray], holes: Sequence[bool], e_min: float,
+                      e_max: float, n: int, n_cap: int) -> List[Tuple[float, int]]:
+    """One pass of Algorithm 1's repeat loop: a new partition for every
+    flagged interface between partitions j and j+1 (ordered by shift), centred
+    at the middle of the gap between their eigenvalues, holding
+    3/2 gap / Delta eigenpairs (clamped, module notes)."""
+    delta = (e_max - e_min) / n
+    out = []
+    for j, flagged in enumerate(holes):
+        if not flagged:
+            continue
+        lo = float(np.max(np.real(parts_eps[j])))
+        hi = float(np.min(np.real(parts_eps[j + 1])))
+        gap = hi - lo
+        cnt = math.ceil(1.5 * gap / delta) if gap > 0 else 1
+        out.append((0.5 * (lo + hi), int(min(max(cnt, 1), n_cap))))
+    return out
+
+
+def solve_with_hole_filling(solve, windows: Sequence[Tuple[float, int]], norm_a: float, e_min: float,
+                            e_max: float, n: int, n_cap: int, max_rounds: int):
+    """Algorithm 1's partitions followed by its repeat loop: solve the
+    windows (solve(shift, nev) -> (eps, U)), combine (Algorithm 2), and while
+    an interface is flagged, insert the hole_fill_windows partitions, solve
+    them, reorder by shift and combine again.
+    Returns (Combined, final window list ordered by shift, rounds run)."""
+    wins = sorted(((float(s), int(k)) for s, k in windows), key=lambda t: t[0])
+    sols = [solve(s, k) for s, k in wins]
+    comb = combine(sols, norm_a)
+    rounds = 0
+    while rounds < max_rounds and bool(np.any(comb.holes)):
+        new = hole_fill_windows([e for e, _ in sols], comb.holes, e_min, e_max, n, n_cap)
+        rounds += 1
+        wins = wins + new
+        sols = sols + [solve(s, k) for s, k in new]
+        order = sorted(range(len(wins)), key=lambda i: wins[i][0])
+        wins = [wins[i] for i in order]
+        sols = [sols[i] for i in order]
+        comb = combine(sols, norm_a)
+    return comb, wins, rounds
+

@@ -208,3 +208,59 @@ def test_ragged_batch_matches_oracle(torch_cuda, precision):
         _match_sets(eps, ref.eps, 1e-10)
         _check_vectors(op_.eigenvectors().cpu().numpy(), ref.U, A, eps, nrm, ea)
         op_.close()
+
+
+@pytest.fixture(scope="module")
+def c2_solved(torch_cuda):
+    # the bench's configuration: c2, semiclassical windows, 8 x 50, FP64
+    from paper_1606_01139_amd import Operator, default_opts, PLAN_SEMICLASSICAL
+    from synth.workloads import workload
+    print("c2 full-size solve (about a minute)", flush=True)
+    w = workload("c2")
+    g = w.grid
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    opts = default_opts(tol=1e-8)
+    wins, _ = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    n, holes, status = oper.solve_all_partitions(wins, opts)
+    assert status == 0 and n >= w.n_windows * w.nev_per_window - 2 * w.n_windows
+    yield w, oper, wins
+    oper.close()
+
+
+def test_c2_full_size_sampled_parity(c2_solved):
+    # Sampled outputs at the full c2 size, each computed independently by the
+    # oracle: the lowest eigenvalues (ARPACK 'SR'), backward errors and
+    # c-products of sampled vectors with the oracle's sparse operator, and
+    # T(E) at sampled energies.
+    from oracle import operator as op, eigen, transport
+    w, oper, wins = c2_solved
+    g = w.grid
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
+    A = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR).tocsr()
+    nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
+    eps = oper.eigenvalues()
+    # (1) the 10 lowest eigenvalues: the first window reaches the bottom end
+    e_ref = eigen.lowest_real(A, 10)
+    for e in e_ref:
+        d = np.min(np.abs(eps - e))
+        assert d <= 1e-10 * max(abs(e), 1.0), (e, d)
+    # (2) backward errors and c-normalisation of 24 sampled eigenvectors
+    Uall = oper.eigenvectors().cpu().numpy()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(eps), size=min(24, len(eps)), replace=False)
+    Us = Uall[:, idx]
+    for c, k in enumerate(idx):
+        u = Us[:, c]
+        r = A @ u - eps[k] * u
+        assert np.linalg.norm(r) / (nrm * np.linalg.norm(u)) <= 1e-8
+        assert abs(u @ u - 1.0) <= 1e-10
+    # (3) c-orthogonality among the sample (distinct eigenvalues)
+    G = Us.T @ Us
+    assert np.abs(G - np.eye(len(idx))).max() <= 1e-6
+    # (4) T(E) at sampled energies, evaluated by the oracle's formula on the
+    # GPU's eigenpairs (checks the Gamma-weighted grams and the sweep at size)
+    E = np.linspace(eps.real.min(), eps.real.max(), 5)
+    T = oper.transmission(E)
+    Tref = transport.transmission_spectral(eps, Uall, gL, gR, E)
+    assert np.abs(T - Tref).max() <= 1e-6
+    assert (T >= -1e-10).all()

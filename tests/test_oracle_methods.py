@@ -54,6 +54,17 @@ def test_window_arpack_matches_dense():
         assert eigen.backward_error(A, U2[:, k], e2[k], nrm) < 1e-12
 
 
+def test_lowest_real_matches_dense():
+    # ARPACK 'SR' (sparse) against the dense spectrum sorted by real part
+    w = small_workload(7, 6, 12, 3, seed=22)
+    A, gL, gR = _dense(w)
+    eps_all, _ = eigen.dense_spectrum(A)
+    import scipy.sparse as sp
+    got = eigen.lowest_real(sp.csr_matrix(A), 8)
+    want = eps_all[np.argsort(eps_all.real)][:8]
+    np.testing.assert_allclose(got, want, atol=1e-10)
+
+
 def test_c_rayleigh_is_quadratic():
     w = small_workload(5, 5, 8, 2, seed=8)
     A, _, _ = _dense(w)
@@ -300,3 +311,42 @@ def test_semiclassical_windows_are_interval_midpoints():
         n = partition.semiclassical_count(w.V, g.h, shape, s)
         assert acc - 1e-6 <= n <= acc + c + 1e-6
         acc += c
+
+
+# ---------------------------------------------------------- hole filling
+def test_hole_fill_windows_worked_values():
+    # Algorithm 1's repeat loop: E_S at the middle of the gap, n = 3/2 gap / Delta.
+    # E_max - E_min = 8, N = 1024: Delta = 1/128; gap 0.5 -> 96 eigenpairs.
+    parts = [np.array([1.0, 1.2, 1.5]), np.array([2.0, 2.3]), np.array([2.2, 2.6]), np.array([2.5, 3.0])]
+    holes = [True, False, True]
+    got = partition.hole_fill_windows(parts, holes, 0.0, 8.0, 1024, 200)
+    # interface 2: gap 2.5 - 2.6 < 0 -> one eigenpair at the midpoint
+    assert got == [(1.75, 96), (2.55, 1)]
+    got = partition.hole_fill_windows(parts, holes, 0.0, 8.0, 1024, 50)
+    assert got == [(1.75, 50), (2.55, 1)]
+    assert partition.hole_fill_windows(parts, [False] * 3, 0.0, 8.0, 1024, 50) == []
+
+
+def test_hole_filling_closes_gaps_brute_force():
+    # two windows far apart: the loop inserts partitions until no interface is
+    # flagged, and the combined set is then every eigenvalue of the dense
+    # spectrum between its lowest and highest real part
+    w = small_workload(7, 6, 12, 3, seed=21)
+    A, gL, gR = _dense(w)
+    g = w.grid
+    ea, Ua = eigen.dense_spectrum(A)
+    nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
+    emin = float(ea.real.min())
+    emax = op.kinetic_upper_bound(g.h) + float(w.V.max())
+    er = np.sort(ea.real)
+    solve = lambda s, k: eigen.window_from_spectrum(ea, Ua, s, k)
+    comb0 = partition.combine([solve(er[2], 6), solve(er[45], 6)], nrm)
+    assert comb0.holes[0]
+    comb, wins, rounds = partition.solve_with_hole_filling(solve, [(er[45], 6), (er[2], 6)], nrm, emin, emax,
+                                                           g.n, 6, 10)
+    assert rounds >= 2 and not comb.holes.any()
+    assert [s for s, _ in wins] == sorted(s for s, _ in wins)
+    lo, hi = comb.eps.real.min(), comb.eps.real.max()
+    want = np.sort_complex(ea[(ea.real >= lo) & (ea.real <= hi)])
+    np.testing.assert_allclose(np.sort_complex(comb.eps), want, atol=1e-12)
+    np.testing.assert_allclose(comb.U.T @ comb.U, np.eye(len(comb.eps)), atol=1e-8)
