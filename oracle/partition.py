@@ -16,8 +16,12 @@ Readings where the paper is silent or garbled:
     when ||v_k||_2 after the projections is below 1e-3 of its value before,
     and kept pairs are c-normalised (u^T u = 1) rather than scaled by |v_k|,
     because the transport formula needs U^T U = I;
-  * the garbled flag index holes_{k-1} is read as the interface between the
-    partitions that own lambda_m and lambda_k, when they are adjacent;
+  * the garbled flag index holes_{k-1} is read as the interfaces between the
+    partitions that own lambda_m and lambda_k: when they are adjacent, the one
+    interface between them; when they are not, every interface between them,
+    since two windows that share an eigenvalue overlap, so the partitions
+    ordered between them cannot hide a gap (without this, a small window
+    between two wide ones stays flagged although its neighbours overlap);
   * E_max (Algorithm 1's upper extremal eigenvalue) is taken as the exact
     upper bound on the real parts, max V + 3 max|symbol| / (2 h^2), instead of
     a second exterior solve: Re eps = u^H (K + V) u / u^H u lies below it;
@@ -218,8 +222,7 @@ def combine(windows: Sequence[Tuple[np.ndarray, np.ndarray]], norm_a: float,
             if partners and after < drop_ratio * before:
                 removed += 1
                 for o in partners:
-                    if abs(o - j) == 1:
-                        holes[min(o, j)] = False
+                    holes[min(o, j):max(o, j)] = False
                 continue
             kept_eps.append(lam)
             kept_vec.append(v / np.sqrt(v @ v))

@@ -139,6 +139,19 @@ def test_combine_duplicate_window_removed():
     np.testing.assert_allclose(c.eps, wins[0][0], atol=1e-12)
 
 
+def test_combine_flags_between_overlapping_non_adjacent_windows():
+    # unit vectors with eigenvalues 1..8: window 1 (between the others by
+    # shift) holds only 3; windows 0 and 2 share 4, so no interface can hide
+    # a gap; with window 2 moved to {6, 7} the interface 1-2 is a real gap
+    N = 8
+    I = np.eye(N, dtype=np.complex128)
+    win = lambda ks: (np.array(ks, dtype=np.complex128), I[:, [k - 1 for k in ks]])
+    c = partition.combine([win([1, 2, 3, 4]), win([3]), win([4, 5, 6])], 10.0)
+    assert list(c.holes) == [False, False] and c.removed == 2 and len(c.eps) == 6
+    c = partition.combine([win([1, 2, 3, 4]), win([3]), win([6, 7])], 10.0)
+    assert list(c.holes) == [False, True]
+
+
 def test_combine_far_windows_flag_hole():
     w = small_workload(6, 6, 10, 3, seed=4)
     A, gL, gR, ea, Ua, nrm, wins = _windows(w, [2, 60], 5)
