@@ -80,7 +80,7 @@ typedef struct {
   int32_t precision;    /* TSG_FP64, or TSG_FP32_BULK: complex64 block work then an FP64 polish */
   double tol;           /* backward error ||A u - theta u|| / (||A||_G ||u||) to reach (default 1e-8) */
   int32_t block;        /* vectors per block step b (default 2) */
-  int32_t basis;        /* basis size m per window (0: automatic, about 6 n_{r,j}) */
+  int32_t basis;        /* basis size m per window (0: automatic, about 6 n_{r,j} and at least 40) */
   int32_t keep;         /* vectors kept at a restart k (0: automatic, about m/2) */
   int32_t max_restarts; /* per window (default 2000) */
   uint64_t seed;        /* start-vector seed */
@@ -148,7 +148,8 @@ tsg_status tsg_plan_windows(tsg_ctx* ctx, int32_t n_r, int32_t p, int32_t mode, 
 /* Solves one partition of Eq. (3): the win.nev eigenpairs of A closest to
  * win.shift (Section 2.1, 'SM' on the shifted operator, no inversion), and
  * appends it to the context's list of partitions (a continuation run in the
- * sense of Section 2).  *n_conv gets the number converged.
+ * sense of Section 2).  *n_conv gets the number converged: a partition keeps
+ * only the pairs whose backward error is at most opts->tol.
  * Errors: TSG_EINVAL, TSG_ENOCONV (converged subset kept), TSG_EDEVICE. */
 tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opts, int32_t* n_conv);
 
@@ -161,6 +162,32 @@ tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opt
  * Errors: as tsg_solve_partition. */
 tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int32_t p, const tsg_opts* opts,
                                     int32_t* n_unique, uint8_t* hole_flags);
+
+/* Algorithm 1's repeat loop (Section 2.2) on the stored partitions after a
+ * solve.  The partitions are reordered by shift (stable), so that interface
+ * j lies between partitions j and j+1, and combined as by tsg_combine.
+ * While an interface is flagged and fewer than max_rounds rounds have run,
+ * every flagged interface gets a new partition centred between the largest
+ * real part among the lower partition's eigenvalues and the smallest among
+ * the upper one's, holding ceil(3/2 gap / Delta) eigenpairs with
+ * Delta = (E_max - E_min)/N, clamped to [1, n_cap] (a gap <= 0 gives 1); a
+ * round's new partitions are solved together (one batched iteration), then
+ * all partitions are reordered and combined again.  Partition indices of
+ * tsg_get_partition and tsg_get_stats follow the new order.
+ *   e_min:      E_min of the plan (e_range[0] of tsg_plan_windows); E_max is
+ *               the bound tsg_plan_windows uses;
+ *   n_cap:      largest count of an inserted partition (>= 1), for example
+ *               the largest planned n_{r,j}: Delta is the mean spacing over
+ *               the whole spectrum, and where eigenvalues are sparser than
+ *               that the formula asks for more than one window should hold;
+ *   max_rounds: >= 0;
+ *   n_added, rounds, n_unique, holes_left: host outputs or NULL (partitions
+ *               inserted, rounds run, combined count, interfaces still
+ *               flagged after the last combine).
+ * Errors: TSG_EINVAL, TSG_ESTATE (no partitions), TSG_ENOCONV (an inserted
+ * partition did not converge; its converged subset is kept), TSG_EDEVICE. */
+tsg_status tsg_fill_holes(tsg_ctx* ctx, double e_min, int32_t n_cap, int32_t max_rounds, const tsg_opts* opts,
+                          int32_t* n_added, int32_t* rounds, int32_t* n_unique, int32_t* holes_left);
 
 /* The windows of n_sys independent systems (one context each, same device
  * and fd_radius) in one batched iteration: every kernel launch covers all
@@ -181,8 +208,9 @@ tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window*
 /* Algorithm 2 (Section 2.2) over the stored partitions in order: pairs
  * whose eigenvalues agree within 1e-6 ||A||_G are Gram-Schmidt
  * bi-orthogonalised under the unconjugated product; a pair whose vector
- * norm falls below 1e-3 of its value is removed and clears the hole flag of
- * the interface between the two partitions.  The result is sorted by real
+ * norm falls below 1e-3 of its value is removed and clears the hole flags of
+ * the interfaces between the two partitions that hold it (windows sharing an
+ * eigenvalue overlap, so no interface between them hides a gap).  The result is sorted by real
  * part and c-normalised (u^T u = 1); keep_lowest > 0 truncates it.
  *   hole_flags: host, (number of partitions - 1) bytes, or NULL.
  * Errors: TSG_ESTATE (no partitions), TSG_EDEVICE. */

@@ -27,7 +27,7 @@ C128, C64 = 0, 1
 # Every symbol include/transec_gpu.h declares.
 EXPORTS = [
     "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
-    "tsg_solve_all_partitions", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
+    "tsg_solve_all_partitions", "tsg_fill_holes", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
     "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_transmission_vjp", "tsg_apply_operator",
     "tsg_dense_eig",
     "tsg_last_error", "tsg_destroy",
@@ -87,6 +87,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_solve_partition.argtypes = [vp, TsgWindow, C.POINTER(TsgOpts), C.POINTER(i32)]
     lib.tsg_solve_all_partitions.argtypes = [vp, C.POINTER(TsgWindow), i32, C.POINTER(TsgOpts), C.POINTER(i32),
                                              C.POINTER(C.c_uint8)]
+    lib.tsg_fill_holes.argtypes = [vp, C.c_double, i32, i32, C.POINTER(TsgOpts), C.POINTER(i32), C.POINTER(i32),
+                                   C.POINTER(i32), C.POINTER(i32)]
     lib.tsg_solve_batch.argtypes = [C.POINTER(vp), i32, C.POINTER(C.POINTER(TsgWindow)), C.POINTER(i32),
                                     C.POINTER(TsgOpts), C.POINTER(i32)]
     lib.tsg_combine.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_uint8)]
@@ -231,6 +233,16 @@ class Operator:
                                               holes)
         status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
         return n.value, [bool(holes[i]) for i in range(p - 1)], status
+
+    def fill_holes(self, e_min: float, n_cap: int, max_rounds: int, opts: Optional[TsgOpts] = None,
+                   allow_noconv=False):
+        """Algorithm 1's repeat loop on the stored partitions (tsg_fill_holes).
+        Returns (partitions added, rounds run, combined count, flags left, status)."""
+        out = [C.c_int32() for _ in range(4)]
+        s = self.lib.tsg_fill_holes(self.ctx, float(e_min), int(n_cap), int(max_rounds),
+                                    C.byref(opts) if opts else None, *[C.byref(x) for x in out])
+        status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
+        return (*[x.value for x in out], status)
 
     def combine(self, keep_lowest: int = 0):
         n = C.c_int32()

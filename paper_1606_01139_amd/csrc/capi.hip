@@ -179,6 +179,26 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
   });
 }
 
+tsg_status tsg_fill_holes(tsg_ctx* ctx, double e_min, int32_t n_cap, int32_t max_rounds, const tsg_opts* opts,
+                          int32_t* n_added, int32_t* rounds, int32_t* n_unique, int32_t* holes_left) {
+  if (!ctx) return fail(ctx, TSG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() {
+    tsg_opts o;
+    if (opts) o = *opts; else tsg_default_opts(&o);
+    const tsg::FillResult r = tsg::fill_holes(ctx, e_min, n_cap, max_rounds, o);
+    if (n_added) *n_added = r.added;
+    if (rounds) *rounds = r.rounds;
+    if (n_unique) *n_unique = ctx->nc;
+    if (holes_left) *holes_left = r.holes_left;
+    if (!r.converged) {
+      ctx->err = "an inserted partition did not converge within max_restarts";
+      g_last_error = ctx->err;
+      return TSG_ENOCONV;
+    }
+    return TSG_OK;
+  });
+}
+
 tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window* const* windows, const int32_t* p,
                            const tsg_opts* opts, int32_t* n_unique) {
   if (!ctx || !windows || !p) return fail(nullptr, TSG_EINVAL, "null argument");

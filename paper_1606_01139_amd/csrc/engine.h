@@ -119,6 +119,12 @@ bool solve_windows(tsg_ctx* c, const std::vector<WindowSpec>& wins, const tsg_op
 void solve_batch(const std::vector<tsg_ctx*>& ctx, const std::vector<std::vector<WindowSpec>>& wins,
                  const tsg_opts& o, std::vector<bool>& ok);
 void combine(tsg_ctx* c, int keep_lowest);
+double upper_bound_real(const tsg_ctx* c);
+struct FillResult {
+  int added = 0, rounds = 0, holes_left = 0;
+  bool converged = true;
+};
+FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const tsg_opts& o);
 void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::vector<WindowSpec>& out,
                   double* e_range);
 void transmission(tsg_ctx* c, const double* E, int nE, double* T);

@@ -425,7 +425,10 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
 
 void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& b) {
   b = o.block > 0 ? o.block : 2;
-  m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max(6 * nvmax, nvmax + 4 * b), b);
+  // automatic: about 6 nev, and at least 40 so that a window of few pairs
+  // (hole filling inserts such) still has room for the Ritz values crowding
+  // its shift
+  m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max({6 * nvmax, nvmax + 4 * b, 40}), b);
   const int mcap = int(std::min<int64_t>(N / b, 4096) * b) - b;
   if (m > mcap) m = std::max(mcap, 2 * b);
   k = o.keep > 0 ? (o.keep / b) * b : ((m / 2) / b) * b;
@@ -439,9 +442,10 @@ void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& 
 
 // FP64 finish of one window's nev vectors (device c128, N x nev, ld N):
 // fresh A u, c-Rayleigh quotient, backward error, c-normalisation, sort by
-// real part.  Returns the partition.
+// real part.  Returns the partition, which keeps only the pairs whose
+// backward error is at most tol (all of them when the iteration converged).
 Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr<c128>&& U, int nev,
-                        const WinOut& o, int restarts_bulk) {
+                        const WinOut& o, int restarts_bulk, double tol) {
   const int64_t N = c->N;
   Systems S;
   one_system(S, c, st);
@@ -484,30 +488,35 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
   P.shift = ws.shift;
   P.nev = ws.nev;
   double maxrho = 0.0;
+  std::vector<double> rho(nev);
   for (int i = 0; i < nev; ++i) {
-    const double rho = std::sqrt(std::max(hr[2 * i], 0.0)) / (c->normA * std::sqrt(std::max(hr[2 * i + 1], 1e-300)));
-    maxrho = std::max(maxrho, std::isfinite(rho) ? rho : 1e300);
+    const double r = std::sqrt(std::max(hr[2 * i], 0.0)) / (c->normA * std::sqrt(std::max(hr[2 * i + 1], 1e-300)));
+    rho[i] = std::isfinite(r) ? r : 1e300;
+    maxrho = std::max(maxrho, rho[i]);
   }
-  // gather sorted, c-normalised columns
-  std::vector<const c128*> srcs(nev);
-  std::vector<c128> scs(nev);
-  P.eps.resize(nev);
+  // gather the kept pairs as sorted, c-normalised columns
+  std::vector<const c128*> srcs;
+  std::vector<c128> scs;
   for (int i = 0; i < nev; ++i) {
-    srcs[i] = U.p + int64_t(ord[i]) * N;
-    scs[i] = sc[ord[i]];
-    P.eps[i] = thc[ord[i]];
+    if (!(rho[ord[i]] <= tol)) continue;
+    srcs.push_back(U.p + int64_t(ord[i]) * N);
+    scs.push_back(sc[ord[i]]);
+    P.eps.push_back(thc[ord[i]]);
   }
-  DevArr<const c128*> dsrc;
-  DevArr<c128> dsc;
-  dsrc.alloc(nev); dsc.alloc(nev);
-  check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nev, hipMemcpyHostToDevice, st), "srcs");
-  check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nev, hipMemcpyHostToDevice, st), "sc");
-  P.U.alloc(size_t(N) * nev);
-  gather_columns(P.U.p, N, dsrc.p, dsc.p, nev, N, st);
-  check(hipStreamSynchronize(st), "sync");
+  const int nk = int(srcs.size());
+  P.U.alloc(size_t(N) * std::max(nk, 1));
+  if (nk > 0) {
+    DevArr<const c128*> dsrc;
+    DevArr<c128> dsc;
+    dsrc.alloc(nk); dsc.alloc(nk);
+    check(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(void*) * nk, hipMemcpyHostToDevice, st), "srcs");
+    check(hipMemcpyAsync(dsc.p, scs.data(), sizeof(c128) * nk, hipMemcpyHostToDevice, st), "sc");
+    gather_columns(P.U.p, N, dsrc.p, dsc.p, nk, N, st);
+    check(hipStreamSynchronize(st), "sync");
+  }
   P.stats.shift = ws.shift;
   P.stats.nev = ws.nev;
-  P.stats.n_conv = o.converged ? nev : 0;
+  P.stats.n_conv = nk;
   P.stats.restarts = o.restarts;
   P.stats.matvecs = o.matvecs + nev;
   P.stats.max_backward_error = maxrho;
@@ -588,12 +597,9 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
   conv.assign(nw, true);
   for (int w = 0; w < nw; ++w) {
     outs[w].matvecs += bulk_mv[w];
-    Partition P = finish_window(S.of(w), st, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w]);
-    if (!outs[w].converged || P.stats.max_backward_error > o.tol) {
-      conv[w] = false;
-      P.stats.n_conv = 0;
-      for (size_t i = 0; i < outs[w].rho.size(); ++i) P.stats.n_conv += outs[w].rho[i] <= o.tol;
-    }
+    Partition P = finish_window(S.of(w), st, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w],
+                                o.tol);
+    conv[w] = outs[w].converged && P.stats.n_conv == wins[w].nev;
     parts.push_back(std::move(P));
   }
 }
@@ -846,9 +852,11 @@ void combine(tsg_ctx* c, int keep_lowest) {
       check(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st), "norms");
       check(hipStreamSynchronize(st), "sync");
       if (h[1] < 1e-3 * h[0]) {
+        // partitions o and j share this eigenvalue, so their windows overlap
+        // and no interface between them hides a gap
         for (int q : pt) {
           const int o = kown[q];
-          if (std::abs(o - j) == 1) holes[std::min(o, j)] = 0;
+          for (int t = std::min(o, j); t < std::max(o, j); ++t) holes[t] = 0;
         }
         continue;
       }
@@ -892,6 +900,51 @@ void combine(tsg_ctx* c, int keep_lowest) {
   c->have_grams = false;
 }
 
+// Algorithm 1's repeat loop (Section 2.2): partitions ordered by shift, so
+// interface j lies between partitions j and j+1; each flagged interface gets
+// a partition centred in the gap between the two partitions' eigenvalues with
+// 3/2 gap / Delta eigenpairs, clamped to [1, n_cap] (Delta is the spectrum's
+// mean spacing, which overstates the count where eigenvalues are sparse, so
+// the cap keeps one window's basis bounded and the loop repeats instead).
+FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const tsg_opts& o) {
+  if (c->parts.empty()) throw StateError("no partitions: run a solve first");
+  if (n_cap < 1 || max_rounds < 0) throw InvalidArg("need n_cap >= 1 and max_rounds >= 0");
+  const double e_max = upper_bound_real(c);
+  if (!std::isfinite(e_min) || !(e_min < e_max)) throw InvalidArg("e_min must be finite and below E_max");
+  const double delta = (e_max - e_min) / double(c->N);
+  auto reorder = [&]() {
+    std::stable_sort(c->parts.begin(), c->parts.end(),
+                     [](const Partition& a, const Partition& b) { return a.shift < b.shift; });
+  };
+  FillResult r;
+  reorder();
+  combine(c, o.keep_lowest);
+  while (r.rounds < max_rounds) {
+    std::vector<WindowSpec> add;
+    for (size_t j = 0; j + 1 < c->parts.size(); ++j) {
+      if (!c->holes[j]) continue;
+      const auto& lo = c->parts[j].eps;
+      const auto& hi = c->parts[j + 1].eps;
+      if (lo.empty() || hi.empty()) continue;
+      double a = lo[0].re, b = hi[0].re;
+      for (const c128& e : lo) a = std::max(a, e.re);
+      for (const c128& e : hi) b = std::min(b, e.re);
+      const double gap = b - a;
+      double cnt = gap > 0 ? std::ceil(1.5 * gap / delta) : 1.0;
+      cnt = std::min(std::max(cnt, 1.0), double(n_cap));
+      add.push_back(WindowSpec{0.5 * (a + b), int(cnt)});
+    }
+    if (add.empty()) break;
+    ++r.rounds;
+    r.added += int(add.size());
+    r.converged = solve_windows(c, add, o) && r.converged;
+    reorder();
+    combine(c, o.keep_lowest);
+  }
+  for (uint8_t h : c->holes) r.holes_left += h ? 1 : 0;
+  return r;
+}
+
 namespace {
 
 std::vector<int> window_counts(int n_r, int p, int mode) {
@@ -925,9 +978,10 @@ double smallest_real_part(tsg_ctx* c, const tsg_opts& o) {
   oe.select = TSG_SELECT_SMALLEST_REAL;
   oe.max_restarts = std::max(o.max_restarts, 2000);
   const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
-  const double e = c->parts.back().eps[0].re;
+  const bool found = ok && !c->parts.back().eps.empty();
+  const double e = found ? c->parts.back().eps[0].re : 0.0;
   c->parts.resize(keep_parts);
-  if (!ok) throw StateError("exterior eigenvalue did not converge");
+  if (!found) throw StateError("exterior eigenvalue did not converge");
   return e;
 }
 
@@ -1022,25 +1076,27 @@ void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::
     op.select = TSG_SELECT_NEAREST;
     op.max_restarts = std::max(o.max_restarts, 2000);
     (void)solve_windows(c, probes, op);
-    std::vector<double> pc(S + 1), rho(S + 1);
+    std::vector<double> pc(1, e_min), rho(1, 0.0);
     for (int i = 0; i < S; ++i) {
       const Partition& P = c->parts[keep_parts + i];
+      if (P.eps.size() < 2) continue;  // a probe left with fewer than two pairs gives no density
       double lo = P.eps[0].re, hi = P.eps[0].re, sum = 0.0;
       for (const auto& e : P.eps) { lo = std::min(lo, e.re); hi = std::max(hi, e.re); sum += e.re; }
-      pc[i + 1] = sum / P.eps.size();
-      rho[i + 1] = double(P.eps.size() - 1) / std::max(hi - lo, 1e-12);
+      pc.push_back(sum / P.eps.size());
+      rho.push_back(double(P.eps.size() - 1) / std::max(hi - lo, 1e-12));
     }
     c->parts.resize(keep_parts);
-    pc[0] = e_min;
+    const int nsv = int(pc.size()) - 1;
+    if (nsv < 1) throw StateError("density sampling: no probe converged");
     rho[0] = rho[1];
     // order the sample points, then integrate the piecewise-linear density
-    std::vector<int> ord(S + 1);
+    std::vector<int> ord(nsv + 1);
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](int a, int b2) { return pc[a] < pc[b2]; });
     std::vector<double> xs, cum;
     xs.push_back(pc[ord[0]]);
     cum.push_back(0.0);
-    for (int q = 1; q <= S; ++q) {
+    for (int q = 1; q <= nsv; ++q) {
       const double x0 = pc[ord[q - 1]], x1 = pc[ord[q]];
       xs.push_back(x1);
       cum.push_back(cum.back() + 0.5 * (rho[ord[q - 1]] + rho[ord[q]]) * (x1 - x0));
@@ -1051,7 +1107,7 @@ void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::
           const double f = (target - cum[q - 1]) / std::max(cum[q] - cum[q - 1], 1e-300);
           return xs[q - 1] + f * (xs[q] - xs[q - 1]);
         }
-      const double last_rho = rho[ord[S]];
+      const double last_rho = rho[ord[nsv]];
       return xs.back() + (target - cum.back()) / std::max(last_rho, 1e-12);
     };
     double acc = 0.0;

@@ -210,6 +210,43 @@ def test_ragged_batch_matches_oracle(torch_cuda, precision):
         op_.close()
 
 
+def test_hole_filling_matches_oracle(torch_cuda):
+    # Algorithm 1's repeat loop from two windows far apart: the same inserted
+    # partitions, round count and final combined set as the oracle's loop
+    # over the dense spectrum
+    from oracle import eigen, partition, operator as op
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import small_workload
+    w = small_workload(7, 6, 12, 3, seed=21)
+    g = w.grid
+    print("hole filling 7x6x12", flush=True)
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    er = np.sort(ea.real)
+    emin = float(er[0])
+    emax = op.kinetic_upper_bound(g.h) + float(w.V.max())
+    solve = lambda s, k: eigen.window_from_spectrum(ea, Ua, s, k)
+    wins = [(float(er[45]), 6), (float(er[2]), 6)]
+    ref, ref_wins, ref_rounds = partition.solve_with_hole_filling(solve, wins, nrm, emin, emax, g.n, 6, 10)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    opts = default_opts()
+    n, holes, _ = oper.solve_all_partitions(wins, opts)
+    assert holes == [True]
+    added, rounds, n_unique, left, status = oper.fill_holes(emin, 6, 10, opts)
+    assert status == 0 and left == 0 and not ref.holes.any()
+    assert rounds == ref_rounds and added == len(ref_wins) - 2
+    got_wins = [(oper.stats(j).shift, oper.stats(j).nev) for j in range(len(ref_wins))]
+    assert [k for _, k in got_wins] == [k for _, k in ref_wins]
+    np.testing.assert_allclose([s for s, _ in got_wins], [s for s, _ in ref_wins], rtol=0, atol=1e-8)
+    for j in range(len(ref_wins)):
+        st = oper.stats(j)
+        assert st.n_conv == st.nev and st.max_backward_error <= 1e-8
+    eps = oper.eigenvalues()
+    assert n_unique == len(ref.eps)
+    _match_sets(eps, ref.eps, 1e-10)
+    _check_vectors(oper.eigenvectors().cpu().numpy(), ref.U, A, eps, nrm, ea)
+    oper.close()
+
+
 @pytest.fixture(scope="module")
 def c2_solved(torch_cuda):
     # the bench's configuration: c2, semiclassical windows, 8 x 50, FP64
@@ -220,9 +257,16 @@ def c2_solved(torch_cuda):
     g = w.grid
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
     opts = default_opts(tol=1e-8)
-    wins, _ = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    wins, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
     n, holes, status = oper.solve_all_partitions(wins, opts)
-    assert status == 0 and n >= w.n_windows * w.nev_per_window - 2 * w.n_windows
+    assert status == 0
+    # Algorithm 1's repeat loop, as the bench runs it
+    added, rounds, n, left, status = oper.fill_holes(erange[0], w.nev_per_window, 4, opts)
+    print(f"c2: {n} unique, {added} partitions inserted in {rounds} rounds, {left} flags left", flush=True)
+    assert status == 0 and left == 0
+    for j in range(len(wins) + added):
+        st = oper.stats(j)
+        assert st.n_conv == st.nev and st.max_backward_error <= 1e-8
     yield w, oper, wins
     oper.close()
 
