@@ -52,6 +52,12 @@ Readings where the paper is silent or garbled:
     its low end, where eigenvalues are sparser than the mean, the formula
     asks for far more than one window holds, and the loop repeats instead.
     The loop stops when no flag is left or after a given number of rounds.
+    The partitioned interval starts at E_min, itself an eigenvalue (found by
+    the exterior solve); the loop treats it as a partition of one pair below
+    the first window, so when the lowest computed real part lies more than
+    Algorithm 2's tau above E_min, that gap is a hole like the others (a
+    first window placed where the spectrum is sparse need not reach down to
+    E_min).
 """
 from __future__ import annotations
 
@@ -238,21 +244,27 @@ def combine(windows: Sequence[Tuple[np.ndarray, np.ndarray]], norm_a: float,
 
 
 def hole_fill_windows(parts_eps: Sequence[np.ndarray], holes: Sequence[bool], e_min: float,
-                      e_max: float, n: int, n_cap: int) -> List[Tuple[float, int]]:
-    """One pass of Algorithm 1's repeat loop: a new partition for every
-    flagged interface between partitions j and j+1 (ordered by shift), centred
-    at the middle of the gap between their eigenvalues, holding
-    3/2 gap / Delta eigenpairs (clamped, module notes)."""
+                      e_max: float, n: int, n_cap: int, tau: float) -> List[Tuple[float, int]]:
+    """One pass of Algorithm 1's repeat loop: a new partition for the gap
+    between E_min and the lowest computed real part when it exceeds tau, and
+    for every flagged interface between partitions j and j+1 (ordered by
+    shift), centred at the middle of the gap, holding 3/2 gap / Delta
+    eigenpairs (clamped, module notes)."""
     delta = (e_max - e_min) / n
+
+    def window(lo, hi):
+        gap = hi - lo
+        cnt = math.ceil(1.5 * gap / delta) if gap > 0 else 1
+        return (0.5 * (lo + hi), int(min(max(cnt, 1), n_cap)))
+
     out = []
+    low = min(float(np.min(np.real(e))) for e in parts_eps if len(e))
+    if low > e_min + tau:
+        out.append(window(e_min, low))
     for j, flagged in enumerate(holes):
         if not flagged:
             continue
-        lo = float(np.max(np.real(parts_eps[j])))
-        hi = float(np.min(np.real(parts_eps[j + 1])))
-        gap = hi - lo
-        cnt = math.ceil(1.5 * gap / delta) if gap > 0 else 1
-        out.append((0.5 * (lo + hi), int(min(max(cnt, 1), n_cap))))
+        out.append(window(float(np.max(np.real(parts_eps[j]))), float(np.min(np.real(parts_eps[j + 1])))))
     return out
 
 
@@ -260,15 +272,19 @@ def solve_with_hole_filling(solve, windows: Sequence[Tuple[float, int]], norm_a:
                             e_max: float, n: int, n_cap: int, max_rounds: int):
     """Algorithm 1's partitions followed by its repeat loop: solve the
     windows (solve(shift, nev) -> (eps, U)), combine (Algorithm 2), and while
-    an interface is flagged, insert the hole_fill_windows partitions, solve
-    them, reorder by shift and combine again.
+    hole_fill_windows finds a gap (a flagged interface, or the stretch above
+    E_min), insert its partitions, solve them, reorder by shift and combine
+    again.
     Returns (Combined, final window list ordered by shift, rounds run)."""
     wins = sorted(((float(s), int(k)) for s, k in windows), key=lambda t: t[0])
     sols = [solve(s, k) for s, k in wins]
     comb = combine(sols, norm_a)
     rounds = 0
-    while rounds < max_rounds and bool(np.any(comb.holes)):
-        new = hole_fill_windows([e for e, _ in sols], comb.holes, e_min, e_max, n, n_cap)
+    tau = 1e-6 * norm_a
+    while rounds < max_rounds:
+        new = hole_fill_windows([e for e, _ in sols], comb.holes, e_min, e_max, n, n_cap, tau)
+        if not new:
+            break
         rounds += 1
         wins = wins + new
         sols = sols + [solve(s, k) for s, k in new]

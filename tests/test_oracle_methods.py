@@ -332,18 +332,24 @@ def test_hole_fill_windows_worked_values():
     # E_max - E_min = 8, N = 1024: Delta = 1/128; gap 0.5 -> 96 eigenpairs.
     parts = [np.array([1.0, 1.2, 1.5]), np.array([2.0, 2.3]), np.array([2.2, 2.6]), np.array([2.5, 3.0])]
     holes = [True, False, True]
-    got = partition.hole_fill_windows(parts, holes, 0.0, 8.0, 1024, 200)
+    got = partition.hole_fill_windows(parts, holes, 1.0, 9.0, 1024, 200, 1e-6)
     # interface 2: gap 2.5 - 2.6 < 0 -> one eigenpair at the midpoint
     assert got == [(1.75, 96), (2.55, 1)]
-    got = partition.hole_fill_windows(parts, holes, 0.0, 8.0, 1024, 50)
+    got = partition.hole_fill_windows(parts, holes, 1.0, 9.0, 1024, 50, 1e-6)
     assert got == [(1.75, 50), (2.55, 1)]
-    assert partition.hole_fill_windows(parts, [False] * 3, 0.0, 8.0, 1024, 50) == []
+    assert partition.hole_fill_windows(parts, [False] * 3, 1.0, 9.0, 1024, 50, 1e-6) == []
+    # E_min = 0.5 lies below the lowest computed value 1.0: gap 0.5 at the bottom
+    got = partition.hole_fill_windows(parts, [False] * 3, 0.5, 8.5, 1024, 200, 1e-6)
+    assert got == [(0.75, 96)]
+    # within tau of E_min: no bottom gap
+    assert partition.hole_fill_windows(parts, [False] * 3, 1.0 - 1e-9, 9.0, 1024, 200, 1e-6) == []
 
 
 def test_hole_filling_closes_gaps_brute_force():
-    # two windows far apart: the loop inserts partitions until no interface is
-    # flagged, and the combined set is then every eigenvalue of the dense
-    # spectrum between its lowest and highest real part
+    # two windows far apart, neither reaching E_min: the loop inserts
+    # partitions until no interface is flagged and E_min is reached, and the
+    # combined set is then every eigenvalue of the dense spectrum up to its
+    # highest real part
     w = small_workload(7, 6, 12, 3, seed=21)
     A, gL, gR = _dense(w)
     g = w.grid
@@ -360,6 +366,7 @@ def test_hole_filling_closes_gaps_brute_force():
     assert rounds >= 2 and not comb.holes.any()
     assert [s for s, _ in wins] == sorted(s for s, _ in wins)
     lo, hi = comb.eps.real.min(), comb.eps.real.max()
+    assert lo == emin
     want = np.sort_complex(ea[(ea.real >= lo) & (ea.real <= hi)])
     np.testing.assert_allclose(np.sort_complex(comb.eps), want, atol=1e-12)
     np.testing.assert_allclose(comb.U.T @ comb.U, np.eye(len(comb.eps)), atol=1e-8)
