@@ -47,8 +47,9 @@ def run_step(w, n_r, p, opts, max_windows=None, plan="semiclassical", fill_round
         wins = wins[:max_windows]
     n, holes, status = oper.solve_all_partitions(wins, opts, allow_noconv=True)
     oper.fill = {"rounds": 0, "inserted": 0, "holes_left": int(sum(holes))}
-    if fill_rounds and any(holes):
-        # Algorithm 1's repeat loop: partitions inserted where no redundancy was found
+    if fill_rounds:
+        # Algorithm 1's repeat loop: partitions inserted where no redundancy
+        # was found, and above E_min if the first window does not reach it
         added, rounds, n, left, st2 = oper.fill_holes(erange[0], max(k for _, k in wins), fill_rounds, opts,
                                                       allow_noconv=True)
         oper.fill = {"rounds": rounds, "inserted": added, "holes_left": left}

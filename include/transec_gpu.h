@@ -166,10 +166,13 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
 /* Algorithm 1's repeat loop (Section 2.2) on the stored partitions after a
  * solve.  The partitions are reordered by shift (stable), so that interface
  * j lies between partitions j and j+1, and combined as by tsg_combine.
- * While an interface is flagged and fewer than max_rounds rounds have run,
- * every flagged interface gets a new partition centred between the largest
+ * While a gap is left and fewer than max_rounds rounds have run, every gap
+ * gets a new partition.  A gap is a flagged interface, between the largest
  * real part among the lower partition's eigenvalues and the smallest among
- * the upper one's, holding ceil(3/2 gap / Delta) eigenpairs with
+ * the upper one's, or the stretch from E_min (itself an eigenvalue) up to the
+ * lowest computed real part when that lies more than Algorithm 2's tau
+ * (1e-6 ||A||_G) above E_min.  The new partition sits at the middle of the
+ * gap and holds ceil(3/2 gap / Delta) eigenpairs with
  * Delta = (E_max - E_min)/N, clamped to [1, n_cap] (a gap <= 0 gives 1); a
  * round's new partitions are solved together (one batched iteration), then
  * all partitions are reordered and combined again.  Partition indices of
@@ -182,8 +185,8 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
  *               that the formula asks for more than one window should hold;
  *   max_rounds: >= 0;
  *   n_added, rounds, n_unique, holes_left: host outputs or NULL (partitions
- *               inserted, rounds run, combined count, interfaces still
- *               flagged after the last combine).
+ *               inserted, rounds run, combined count, gaps left after the
+ *               last combine).
  * Errors: TSG_EINVAL, TSG_ESTATE (no partitions), TSG_ENOCONV (an inserted
  * partition did not converge; its converged subset is kept), TSG_EDEVICE. */
 tsg_status tsg_fill_holes(tsg_ctx* ctx, double e_min, int32_t n_cap, int32_t max_rounds, const tsg_opts* opts,

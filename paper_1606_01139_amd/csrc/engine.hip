@@ -901,8 +901,9 @@ void combine(tsg_ctx* c, int keep_lowest) {
 }
 
 // Algorithm 1's repeat loop (Section 2.2): partitions ordered by shift, so
-// interface j lies between partitions j and j+1; each flagged interface gets
-// a partition centred in the gap between the two partitions' eigenvalues with
+// interface j lies between partitions j and j+1; each flagged interface (and
+// the stretch above E_min when no computed pair reaches down to it) gets a
+// partition centred in the gap between the two partitions' eigenvalues with
 // 3/2 gap / Delta eigenpairs, clamped to [1, n_cap] (Delta is the spectrum's
 // mean spacing, which overstates the count where eigenvalues are sparse, so
 // the cap keeps one window's basis bounded and the loop repeats instead).
@@ -912,6 +913,21 @@ FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const
   const double e_max = upper_bound_real(c);
   if (!std::isfinite(e_min) || !(e_min < e_max)) throw InvalidArg("e_min must be finite and below E_max");
   const double delta = (e_max - e_min) / double(c->N);
+  const double tau = 1e-6 * c->normA;
+  auto window = [&](double lo, double hi) {
+    const double gap = hi - lo;
+    double cnt = gap > 0 ? std::ceil(1.5 * gap / delta) : 1.0;
+    cnt = std::min(std::max(cnt, 1.0), double(n_cap));
+    return WindowSpec{0.5 * (lo + hi), int(cnt)};
+  };
+  // the interval starts at E_min, itself an eigenvalue: a lowest computed
+  // real part more than tau above it leaves a gap at the bottom
+  auto lowest = [&]() {
+    double low = HUGE_VAL;
+    for (const Partition& P : c->parts)
+      for (const c128& e : P.eps) low = std::min(low, e.re);
+    return low;
+  };
   auto reorder = [&]() {
     std::stable_sort(c->parts.begin(), c->parts.end(),
                      [](const Partition& a, const Partition& b) { return a.shift < b.shift; });
@@ -921,6 +937,8 @@ FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const
   combine(c, o.keep_lowest);
   while (r.rounds < max_rounds) {
     std::vector<WindowSpec> add;
+    const double low = lowest();
+    if (std::isfinite(low) && low > e_min + tau) add.push_back(window(e_min, low));
     for (size_t j = 0; j + 1 < c->parts.size(); ++j) {
       if (!c->holes[j]) continue;
       const auto& lo = c->parts[j].eps;
@@ -929,10 +947,7 @@ FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const
       double a = lo[0].re, b = hi[0].re;
       for (const c128& e : lo) a = std::max(a, e.re);
       for (const c128& e : hi) b = std::min(b, e.re);
-      const double gap = b - a;
-      double cnt = gap > 0 ? std::ceil(1.5 * gap / delta) : 1.0;
-      cnt = std::min(std::max(cnt, 1.0), double(n_cap));
-      add.push_back(WindowSpec{0.5 * (a + b), int(cnt)});
+      add.push_back(window(a, b));
     }
     if (add.empty()) break;
     ++r.rounds;
@@ -942,6 +957,8 @@ FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const
     combine(c, o.keep_lowest);
   }
   for (uint8_t h : c->holes) r.holes_left += h ? 1 : 0;
+  const double low = lowest();
+  if (std::isfinite(low) && low > e_min + tau) r.holes_left += 1;
   return r;
 }
 
