@@ -15,6 +15,9 @@
 //     touch disjoint row pairs (left) and column pairs (right), and left and
 //     right rotations commute, so each step applies all left rotations, then
 //     all right rotations.
+// Z is held transposed while the kernel runs (Z(r, c) at Z[c m + r]): a
+// right rotation then touches two contiguous columns of Z, so the lanes of
+// a wavefront read and write consecutive addresses.
 #include <cstdio>
 #include <cstdlib>
 
@@ -247,6 +250,38 @@ __device__ void apply_left(c128* Y, int64_t ld, int r0, int c0, int c1, const c1
   }
 }
 
+// Y(:, c0 : c0+n) <- Y(:, c0 : c0+n) Q for an m x m matrix held transposed
+// (Y(r, c) at Yt[c m + r]); Q in LDS (n x n).
+__device__ void apply_right_t(c128* Yt, int m, int c0, const c128* Q, int n) {
+  const int t = threadIdx.x;
+  const int per = max(1, kQT / n);  // rows per pass
+  for (int rb = 0; rb < m; rb += per) {
+    const int r = rb + t / n, j = t % n;
+    c128 acc{0.0, 0.0};
+    const bool ok = (t < per * n) && r < m;
+    if (ok) {
+      for (int p = 0; p < n; ++p) fma_acc(acc, Yt[int64_t(c0 + p) * m + r], Q[p * n + j]);
+    }
+    __syncthreads();
+    if (ok) Yt[int64_t(c0 + j) * m + r] = acc;
+    __syncthreads();
+  }
+}
+
+// In-place transpose of an m x m matrix (each off-diagonal pair swapped by
+// one thread).
+__device__ void transpose_sq(c128* A, int m) {
+  for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kQT) {
+    const int i = int(e / m), j = int(e % m);
+    if (i < j) {
+      const c128 a = A[int64_t(i) * m + j];
+      A[int64_t(i) * m + j] = A[int64_t(j) * m + i];
+      A[int64_t(j) * m + i] = a;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
                                                     c128* theta, int64_t wst, int* info, const int* __restrict__ wmap,
                                                     int prof, int nshift_max) {
@@ -258,6 +293,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   c128* Z = Zall + int64_t(w) * wsz;
   c128* th = theta + int64_t(w) * wst;
   const int t = threadIdx.x;
+  transpose_sq(Z, m);
   const double ulp = 2.220446049250313e-16;
   int ihi = m - 1;
   int sweeps = 0;
@@ -319,7 +355,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       }
       for (int i = t; i < n; i += kQT) th[lo + i] = B[i * n + i];
       __syncthreads();
-      apply_right(Z, m, 0, m, lo, Q, n);
+      apply_right_t(Z, m, lo, Q, n);
       apply_right(H, m, 0, lo, lo, Q, n);
       apply_left(H, m, lo, ihi + 1, m, Q, n);
       tick(6);
@@ -384,34 +420,37 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       const int jb = min(ns - 1, step / 3);
       const int nact = jb >= ja ? jb - ja + 1 : 0;
       // all left rotations: rows p, p+1, columns from max(p-1, lo) to m-1.
-      // Items (bulge, column), column fastest; each thread loads a batch of
-      // independent items before storing any.
+      // Items (bulge, column), column fastest, over the columns from the
+      // last active bulge's first one (no bulge starts further left); each
+      // thread loads a batch of independent items before storing any.
       {
-        const int W = m - lo;
+        const int cstart = nact > 0 ? max(lo + step - 3 * jb - 1, lo) : lo;
+        const int W = m - cstart;
         const int total = nact * W;
         for (int base = t; base < total; base += kQT * kBatch) {
+          // every item loads (a skipped one from H's first elements) so that
+          // the batch's loads are all in flight before the first is used
           c128 av[kBatch], bv[kBatch];
-          int pr[kBatch], cl[kBatch];
+          int pr[kBatch], cl[kBatch], pp[kBatch];
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
-            pr[q] = -1;
-            if (idx < total) {
-              const int j = ja + idx / W, col = lo + idx % W;
-              const int p = S.bp[j];
-              const int c0 = (p > lo) ? p - 1 : lo;
-              if (p >= 0 && col >= c0) {
-                pr[q] = j;
-                cl[q] = col;
-                av[q] = H[int64_t(p) * m + col];
-                bv[q] = H[int64_t(p + 1) * m + col];
-              }
-            }
+            const bool in = idx < total;
+            const int j = in ? ja + idx / W : ja;
+            const int col = in ? cstart + idx % W : lo;
+            const int p = in ? S.bp[j] : -1;
+            const int c0 = (p > lo) ? p - 1 : lo;
+            const bool ok = p >= 0 && col >= c0;
+            pr[q] = ok ? j : -1;
+            pp[q] = ok ? p : 0;
+            cl[q] = ok ? col : 0;
+            av[q] = H[int64_t(pp[q]) * m + cl[q]];
+            bv[q] = H[int64_t(pp[q] + 1) * m + cl[q]];
           }
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             if (pr[q] < 0) continue;
-            const int j = pr[q], p = S.bp[j], col = cl[q];
+            const int j = pr[q], p = pp[q], col = cl[q];
             const double c = S.bc[j];
             const c128 sj = S.bs[j];
             H[int64_t(p) * m + col] = c * av[q] + sj * bv[q];
@@ -421,54 +460,56 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       }
       __syncthreads();
       tick(3);
-      // all right rotations: columns p, p+1 for rows 0..min(p+2, ihi), and
-      // every row of Z.  Items (row, bulge), bulge fastest: neighbouring
-      // lanes touch nearby column pairs of the same row.
+      // all right rotations: columns p, p+1 of H for rows 0..min(p+2, ihi)
+      // (items (row, bulge), bulge fastest: neighbouring lanes touch nearby
+      // column pairs of one row), then columns p, p+1 of every row of Z
+      // (items (bulge, row), row fastest: contiguous in the transposed Z).
       {
-        const int Rh = ihi + 1;
-        const int total = (Rh + m) * nact;
+        // rows below the deepest active bulge's last one are untouched
+        const int Rh = nact > 0 ? min(lo + step - 3 * ja + 2, ihi) + 1 : 0;
+        const int nh = Rh * nact;
+        const int total = nh + m * nact;
         for (int base = t; base < total; base += kQT * kBatch) {
+          // every item loads (a skipped one from H's first elements) so that
+          // the batch's loads are all in flight before the first is used
           c128 av[kBatch], bv[kBatch];
-          c128* rp[kBatch];
+          c128* ap[kBatch];
+          int64_t dq[kBatch];
           int pr[kBatch];
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
-            pr[q] = -1;
-            if (idx < total && nact > 0) {
-              const int r = idx / nact, j = ja + idx % nact;
-              const int p = S.bp[j];
-              bool ok = p >= 0;
-              c128* row;
-              if (r < Rh) {
-                row = H + int64_t(r) * m;
-                ok = ok && r <= min(p + 2, ihi);
-              } else {
-                row = Z + int64_t(r - Rh) * m;
-              }
-              if (ok) {
-                pr[q] = j;
-                rp[q] = row;
-                av[q] = row[p];
-                bv[q] = row[p + 1];
-              }
-            }
+            const bool in = idx < total;
+            const bool hitem = idx < nh;
+            const int z = (in && !hitem) ? idx - nh : 0;
+            const int r = hitem ? idx / nact : z % m;
+            const int j = hitem ? ja + idx % nact : ja + z / m;
+            const int p = in ? S.bp[j] : -1;
+            const bool ok = p >= 0 && (!hitem || r <= min(p + 2, ihi));
+            pr[q] = ok ? j : -1;
+            ap[q] = !ok ? H : hitem ? H + int64_t(r) * m + p : Z + int64_t(p) * m + r;
+            dq[q] = (ok && !hitem) ? int64_t(m) : int64_t(1);
+            av[q] = ap[q][0];
+            bv[q] = ap[q][dq[q]];
           }
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             if (pr[q] < 0) continue;
-            const int j = pr[q], p = S.bp[j];
+            const int j = pr[q];
             const double c = S.bc[j];
             const c128 sj = S.bs[j];
-            rp[q][p] = c * av[q] + conj(sj) * bv[q];
-            rp[q][p + 1] = c * bv[q] - sj * av[q];
+            ap[q][0] = c * av[q] + conj(sj) * bv[q];
+            ap[q][dq[q]] = c * bv[q] - sj * av[q];
           }
         }
       }
       __syncthreads();
       tick(4);
+      if (prof && t == 0) atomicAdd(&g_k4prof[7], 1ull);
     }
   }
+  __syncthreads();
+  transpose_sq(Z, m);
   if (t == 0) info[w] = failed ? max(ihi + 1, 1) : 0;
   if (failed) {
     for (int i = t; i <= ihi; i += kQT) th[i] = H[int64_t(i) * m + i];
@@ -499,9 +540,10 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta
     unsigned long long z[8];
     (void)hipMemcpyFromSymbolAsync(z, HIP_SYMBOL(g_k4prof), sizeof(z), 0, hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
-    std::fprintf(stderr, "[k4] m=%d nwin=%d us: scan %.0f shifts %.0f chaseA %.0f chaseB %.0f chaseC %.0f fin %.0f apply %.0f\n",
+    std::fprintf(stderr, "[k4] m=%d nwin=%d us: scan %.0f shifts %.0f chaseA %.0f chaseB %.0f chaseC %.0f fin %.0f apply %.0f"
+                 " chase steps %llu\n",
                  m, nwin, z[0] / 100.0, z[1] / 100.0, z[2] / 100.0, z[3] / 100.0, z[4] / 100.0, z[5] / 100.0,
-                 z[6] / 100.0);
+                 z[6] / 100.0, z[7]);
   }
 }
 
