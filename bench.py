@@ -208,9 +208,11 @@ def cpu_baseline(w, shift, nev=10):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(nev / dt, 4), "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nev} eigenpairs nearest the first window's shift {shift:.4f} Ha on the "
+            "sample": f"{nev} eigenpairs nearest the first planned window's shift {shift:.4f} Ha on the "
                       f"{g.nx}x{g.ny}x{g.nz} grid, ARPACK SM on the shifted operator (scipy, FP64), "
-                      f"{dt:.1f} s; cores = the threads BLAS may use, the sparse products run on one"}
+                      f"{dt:.1f} s; this is the workload's easiest window (bound states), the oracle's time "
+                      f"per pair grows steeply for the interior windows; cores = the threads BLAS may use, "
+                      f"the sparse products run on one"}
 
 
 def timed_steps(w, opts, args, label):
@@ -256,6 +258,8 @@ def main():
     ap.add_argument("--keep", type=int, default=0)
     ap.add_argument("--groups", type=int, default=0, help="window groups iterating concurrently (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--k4-only", action="store_true",
+                    help="time only the batched small eigensolve at the solve's shape and print its roofline object")
     ap.add_argument("--n-sys", type=int, default=64, help="systems of the ragged batch (config c3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -267,6 +271,18 @@ def main():
     from synth.workloads import workload
 
     torch.cuda.set_device(0)
+    if args.k4_only:
+        w = workload(args.config)
+        out = {"roofline": k4_roofline(args.basis or 6 * w.nev_per_window, w.n_windows)}
+        # a plain device copy of known size, the reference for HBM byte counters
+        nb = 512 << 20
+        x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nb
+        print(json.dumps(out), flush=True)
+        return
     if args.config == "c3":
         run_batch(args)
         return
