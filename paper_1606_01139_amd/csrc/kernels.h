@@ -120,9 +120,11 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
               int64_t wsw, int* info, int nwin, hipStream_t st, const int* wmap = nullptr);
 int64_t smalleig_workspace(int m);
 // Schur form of upper Hessenberg H (in place) with Schur vectors accumulated
-// into Z (which holds the Hessenberg reduction's unitary on entry).
-void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta, int64_t wst, int* info, int nwin,
-                  hipStream_t st, const int* wmap);
+// into Z (which holds the Hessenberg reduction's unitary on entry); log is
+// scratch of schur_log_size(m) c128 per window (stride wsl).
+void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, int64_t wsl, c128* theta,
+                  int64_t wst, int* info, int nwin, hipStream_t st, const int* wmap);
+int64_t schur_log_size(int m);
 
 // Selection by |theta - sigma| (ties: Re, then Im) and restart basis:
 // out (m x (k + nev), row-major, ld = k + nev):

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
 
 }  // namespace
 
-int64_t smalleig_workspace(int m) { return 2 * int64_t(m) * m; }
+int64_t smalleig_workspace(int m) { return 2 * int64_t(m) * m + schur_log_size(m); }
 
 void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, int64_t wsy, c128* work, int64_t wsw,
               int* info, int nwin, hipStream_t st, const int* wmap) {
@@ -350,7 +350,7 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   c128* X = work + int64_t(m) * m;
   hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), (size_t(m) + 4 * kEigThreads) * sizeof(c128), st, H, wsh, m,
                      Z, wsw, wmap);
-  launch_schur(H, wsh, m, Z, wsw, theta, wst, info, nwin, st, wmap);
+  launch_schur(H, wsh, m, Z, wsw, work + 2 * int64_t(m) * m, wsw, theta, wst, info, nwin, st, wmap);
   hipLaunchKernelGGL(trevc_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, H, wsh, m, X, wsw, wmap);
   hipLaunchKernelGGL(small_gemm_kernel, dim3((m + 15) / 16, (m + 15) / 16, nwin), dim3(256), 0, st, Z, wsw, X, wsw,
                      Y, wsy, m, wmap);

@@ -15,11 +15,15 @@
 //     touch disjoint row pairs (left) and column pairs (right), and left and
 //     right rotations commute, so each step applies all left rotations, then
 //     all right rotations.
-// Z is held transposed while the kernel runs (Z(r, c) at Z[c m + r]): a
-// right rotation then touches two contiguous columns of Z, so the lanes of
-// a wavefront read and write consecutive addresses.
+// The chase updates H only.  Every step's rotations (and every unitary of a
+// block finished in LDS) go to a per-window log, and a second kernel replays
+// the log onto the rows of Z, many workgroups per window: a row of Z is
+// transformed by right rotations independently of every other row, so the
+// replay is parallel over rows and off the chase's critical path.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 
 #include "kernels.h"
 
@@ -43,6 +47,26 @@ constexpr int kShifts = 16;
 #define TSG_SCHUR_BATCH 2
 #endif
 constexpr int kBatch = TSG_SCHUR_BATCH;
+
+// One logged rotation: Z(:, [p, p+1]) <- Z(:, [p, p+1]) [c -s; conj(s) c].
+// A step holds kShifts records (p = -1: inactive slot).  A step whose first
+// record has p = -2 stands for the unitary of a block finished in LDS:
+// Z(:, lo:lo+n) <- Z(:, lo:lo+n) Q, with lo = c, n = s.re and Q the block
+// (n x n, row-major) at offset s.im of the Q store (blocks packed).
+struct RotRec {
+  double c;
+  int p;
+  int pad;
+  c128 s;
+};
+static_assert(sizeof(RotRec) == 32, "RotRec layout");
+constexpr int kQCap = 32 * kFin * kFin;  // Q store entries before the chase flushes the log
+
+// Per-window log, in c128 units: a 2-entry header (steps, Q blocks), the
+// step records, the Q store.  The capacity covers 80 multishift sweeps; a
+// chase that needs more flushes the log onto Z itself and starts over.
+__host__ __device__ inline int64_t log_steps_cap(int m) { return int64_t(80) * (m + 3 * kShifts); }
+__host__ __device__ inline int64_t log_qstore_offset(int m) { return 2 + log_steps_cap(m) * kShifts * 2; }
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -250,41 +274,66 @@ __device__ void apply_left(c128* Y, int64_t ld, int r0, int c0, int c1, const c1
   }
 }
 
-// Y(:, c0 : c0+n) <- Y(:, c0 : c0+n) Q for an m x m matrix held transposed
-// (Y(r, c) at Yt[c m + r]); Q in LDS (n x n).
-__device__ void apply_right_t(c128* Yt, int m, int c0, const c128* Q, int n) {
-  const int t = threadIdx.x;
-  const int per = max(1, kQT / n);  // rows per pass
-  for (int rb = 0; rb < m; rb += per) {
-    const int r = rb + t / n, j = t % n;
-    c128 acc{0.0, 0.0};
-    const bool ok = (t < per * n) && r < m;
-    if (ok) {
-      for (int p = 0; p < n; ++p) fma_acc(acc, Yt[int64_t(c0 + p) * m + r], Q[p * n + j]);
-    }
-    __syncthreads();
-    if (ok) Yt[int64_t(c0 + j) * m + r] = acc;
-    __syncthreads();
+// Applies one logged rotation to a row of Z (length m).
+__device__ inline void replay_rot(c128* row, const RotRec& R) {
+  const int p = R.p;
+  const c128 u = row[p], v = row[p + 1];
+  row[p] = R.c * u + conj(R.s) * v;
+  row[p + 1] = R.c * v - R.s * u;
+}
+
+// Outputs j, j + kShifts, ... of row[lo : lo+n] Q for a logged Q block
+// (the caller stores them with qstore_row after a barrier).
+__device__ inline void qblock_row(const c128* row, const RotRec& R0, const c128* qs, int j,
+                                  c128 (&acc)[kFin / kShifts]) {
+  const int lo = int(R0.c), n = int(R0.s.re);
+  const c128* Q = qs + int64_t(R0.s.im);
+#pragma unroll
+  for (int q = 0; q < kFin / kShifts; ++q) {
+    const int jj = j + q * kShifts;
+    c128 a{0.0, 0.0};
+    if (jj < n)
+      for (int pp = 0; pp < n; ++pp) fma_acc(a, row[lo + pp], Q[pp * n + jj]);
+    acc[q] = a;
   }
 }
 
-// In-place transpose of an m x m matrix (each off-diagonal pair swapped by
-// one thread).
-__device__ void transpose_sq(c128* A, int m) {
-  for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kQT) {
-    const int i = int(e / m), j = int(e % m);
-    if (i < j) {
-      const c128 a = A[int64_t(i) * m + j];
-      A[int64_t(i) * m + j] = A[int64_t(j) * m + i];
-      A[int64_t(j) * m + i] = a;
+__device__ inline void qstore_row(c128* row, const RotRec& R0, int j, const c128 (&acc)[kFin / kShifts]) {
+  const int lo = int(R0.c), n = int(R0.s.re);
+#pragma unroll
+  for (int q = 0; q < kFin / kShifts; ++q) {
+    const int jj = j + q * kShifts;
+    if (jj < n) row[lo + jj] = acc[q];
+  }
+}
+
+// The chase's own replay of its log onto every row of Z (global memory),
+// used only when the log is full; kQT / kShifts rows at a time, lane j of a
+// row applying record j of each step.
+__device__ __attribute__((noinline)) void flush_log(c128* Z, int m, const RotRec* rec, int nstep, const c128* qs) {
+  const int t = threadIdx.x, j = t % kShifts;
+  for (int r0 = 0; r0 < m; r0 += kQT / kShifts) {
+    const int r = r0 + t / kShifts;
+    c128* row = Z + int64_t(min(r, m - 1)) * m;
+    for (int st = 0; st < nstep; ++st) {
+      const RotRec* R = rec + int64_t(st) * kShifts;
+      if (R[0].p <= -2) {
+        c128 acc[kFin / kShifts];
+        if (r < m) qblock_row(row, R[0], qs, j, acc);
+        __syncthreads();
+        if (r < m) qstore_row(row, R[0], j, acc);
+      } else {
+        const RotRec Rj = R[j];
+        if (r < m && Rj.p >= 0) replay_rot(row, Rj);
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
-                                                    c128* theta, int64_t wst, int* info, const int* __restrict__ wmap,
-                                                    int prof, int nshift_max) {
+                                                    c128* logall, int64_t wsl, c128* theta, int64_t wst, int* info,
+                                                    const int* __restrict__ wmap, int prof, int nshift_max) {
   extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
   __shared__ QRShared S;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
@@ -292,8 +341,19 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   c128* th = theta + int64_t(w) * wst;
+  c128* lg = logall + int64_t(w) * wsl;
+  RotRec* rec = reinterpret_cast<RotRec*>(lg + 2);
+  c128* qs = lg + log_qstore_offset(m);
+  const int64_t cap = log_steps_cap(m);
+  int nstep = 0, nq = 0;  // steps logged, Q store entries used: the same in every thread
+  auto make_room = [&](int qneed) {
+    if (nstep < cap && nq + qneed <= kQCap) return;
+    __syncthreads();
+    flush_log(Z, m, rec, nstep, qs);
+    nstep = 0;
+    nq = 0;
+  };
   const int t = threadIdx.x;
-  transpose_sq(Z, m);
   const double ulp = 2.220446049250313e-16;
   int ihi = m - 1;
   int sweeps = 0;
@@ -354,8 +414,22 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         H[int64_t(lo + i) * m + lo + j] = B[e];
       }
       for (int i = t; i < n; i += kQT) th[lo + i] = B[i * n + i];
+      make_room(n * n);
+      {
+        c128* Qd = qs + nq;
+        for (int e = t; e < n * n; e += kQT) Qd[e] = Q[e];
+        if (t < kShifts) {
+          RotRec R;
+          R.c = t == 0 ? double(lo) : 0.0;
+          R.p = t == 0 ? -2 : -1;
+          R.pad = 0;
+          R.s = c128{t == 0 ? double(n) : 0.0, t == 0 ? double(nq) : 0.0};
+          rec[int64_t(nstep) * kShifts + t] = R;
+        }
+        ++nstep;
+        nq += n * n;
+      }
       __syncthreads();
-      apply_right_t(Z, m, lo, Q, n);
       apply_right(H, m, 0, lo, lo, Q, n);
       apply_left(H, m, lo, ihi + 1, m, Q, n);
       tick(6);
@@ -391,6 +465,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     // pipelined chase: bulge j sits at position lo + step - 3 j
     const int nsteps = (ihi - lo) + 3 * (ns - 1);
     for (int step = 0; step < nsteps; ++step) {
+      make_room(0);
       if (t < ns) {
         const int p = lo + step - 3 * t;
         if (p >= lo && p < ihi) {
@@ -412,6 +487,15 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         }
       }
       __syncthreads();
+      if (t < kShifts) {
+        RotRec R;
+        R.c = t < ns ? S.bc[t] : 1.0;
+        R.p = t < ns ? S.bp[t] : -1;
+        R.pad = 0;
+        R.s = t < ns ? S.bs[t] : c128{0.0, 0.0};
+        rec[int64_t(nstep) * kShifts + t] = R;
+      }
+      ++nstep;
       tick(2);
       // active bulges form the contiguous range [ja, jb]
       // bulge j is at p = lo + step - 3 j, active while lo <= p <= ihi - 1
@@ -461,36 +545,30 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       __syncthreads();
       tick(3);
       // all right rotations: columns p, p+1 of H for rows 0..min(p+2, ihi)
-      // (items (row, bulge), bulge fastest: neighbouring lanes touch nearby
-      // column pairs of one row), then columns p, p+1 of every row of Z
-      // (items (bulge, row), row fastest: contiguous in the transposed Z).
+      // (Z gets them from the log).  Items (row, bulge), bulge fastest:
+      // neighbouring lanes touch nearby column pairs of one row.
       {
         // rows below the deepest active bulge's last one are untouched
         const int Rh = nact > 0 ? min(lo + step - 3 * ja + 2, ihi) + 1 : 0;
-        const int nh = Rh * nact;
-        const int total = nh + m * nact;
+        const int total = Rh * nact;
         for (int base = t; base < total; base += kQT * kBatch) {
           // every item loads (a skipped one from H's first elements) so that
           // the batch's loads are all in flight before the first is used
           c128 av[kBatch], bv[kBatch];
           c128* ap[kBatch];
-          int64_t dq[kBatch];
           int pr[kBatch];
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
             const bool in = idx < total;
-            const bool hitem = idx < nh;
-            const int z = (in && !hitem) ? idx - nh : 0;
-            const int r = hitem ? idx / nact : z % m;
-            const int j = hitem ? ja + idx % nact : ja + z / m;
+            const int r = in ? idx / nact : 0;
+            const int j = in ? ja + idx % nact : ja;
             const int p = in ? S.bp[j] : -1;
-            const bool ok = p >= 0 && (!hitem || r <= min(p + 2, ihi));
+            const bool ok = p >= 0 && r <= min(p + 2, ihi);
             pr[q] = ok ? j : -1;
-            ap[q] = !ok ? H : hitem ? H + int64_t(r) * m + p : Z + int64_t(p) * m + r;
-            dq[q] = (ok && !hitem) ? int64_t(m) : int64_t(1);
+            ap[q] = ok ? H + int64_t(r) * m + p : H;
             av[q] = ap[q][0];
-            bv[q] = ap[q][dq[q]];
+            bv[q] = ap[q][1];
           }
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
@@ -499,7 +577,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
             const double c = S.bc[j];
             const c128 sj = S.bs[j];
             ap[q][0] = c * av[q] + conj(sj) * bv[q];
-            ap[q][dq[q]] = c * bv[q] - sj * av[q];
+            ap[q][1] = c * bv[q] - sj * av[q];
           }
         }
       }
@@ -508,20 +586,71 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       if (prof && t == 0) atomicAdd(&g_k4prof[7], 1ull);
     }
   }
-  __syncthreads();
-  transpose_sq(Z, m);
-  if (t == 0) info[w] = failed ? max(ihi + 1, 1) : 0;
+  if (t == 0) {
+    info[w] = failed ? max(ihi + 1, 1) : 0;
+    int* hdr = reinterpret_cast<int*>(lg);
+    hdr[0] = nstep;
+    hdr[1] = nq;
+  }
   if (failed) {
     for (int i = t; i <= ihi; i += kQT) th[i] = H[int64_t(i) * m + i];
   }
+}
+
+// Replays a window's log onto rows [r0, r0 + rows) of Z, held in LDS; the
+// step records are staged through LDS in chunks of kChunk steps.  Lane j of
+// a row applies record j of each step.
+constexpr int kChunk = 32;
+
+__global__ __launch_bounds__(256) void zreplay_kernel(c128* Zall, int64_t wsz, int m, const c128* __restrict__ logall,
+                                                     int64_t wsl, int rows, const int* __restrict__ wmap) {
+  extern __shared__ c128 zl[];  // rows x m, then kChunk x kShifts records
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  if (w < 0) return;
+  const int r0 = int(blockIdx.x) * rows;
+  if (r0 >= m) return;
+  const int nr = min(rows, m - r0);
+  c128* Z = Zall + int64_t(w) * wsz;
+  const c128* lg = logall + int64_t(w) * wsl;
+  const int nstep = reinterpret_cast<const int*>(lg)[0];
+  const RotRec* rec = reinterpret_cast<const RotRec*>(lg + 2);
+  const c128* qs = lg + log_qstore_offset(m);
+  RotRec* chunk = reinterpret_cast<RotRec*>(zl + int64_t(rows) * m);
+  const int t = threadIdx.x, nt = blockDim.x, j = t % kShifts, r = t / kShifts;
+  for (int e = t; e < nr * m; e += nt) zl[e] = Z[int64_t(r0) * m + e];
+  c128* row = zl + int64_t(min(r, nr - 1)) * m;
+  const bool mine = r < nr;
+  for (int c0 = 0; c0 < nstep; c0 += kChunk) {
+    const int nc = min(kChunk, nstep - c0);
+    __syncthreads();
+    for (int e = t; e < nc * kShifts; e += nt) chunk[e] = rec[int64_t(c0) * kShifts + e];
+    __syncthreads();
+    for (int st = 0; st < nc; ++st) {
+      const RotRec* R = chunk + st * kShifts;
+      if (R[0].p <= -2) {
+        c128 acc[kFin / kShifts];
+        if (mine) qblock_row(row, R[0], qs, j, acc);
+        __syncthreads();
+        if (mine) qstore_row(row, R[0], j, acc);
+      } else {
+        const RotRec Rj = R[j];
+        if (mine && Rj.p >= 0) replay_rot(row, Rj);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nr * m; e += nt) Z[int64_t(r0) * m + e] = zl[e];
 }
 
 }  // namespace
 
 size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
 
-void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta, int64_t wst, int* info, int nwin,
-                  hipStream_t st, const int* wmap) {
+int64_t schur_log_size(int m) { return log_qstore_offset(m) + int64_t(kQCap); }
+
+void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, int64_t wsl, c128* theta,
+                  int64_t wst, int* info, int nwin, hipStream_t st, const int* wmap) {
   static const int prof = [] { const char* v = std::getenv("TSG_K4PROF"); return (v && v[0] == '1') ? 1 : 0; }();
   if (prof) {
     unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -534,8 +663,26 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* theta
     if (e != hipSuccess) throw DeviceError(std::string("schur: LDS attribute: ") + hipGetErrorString(e));
     attr_set = true;
   }
-  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, theta, wst,
-                     info, wmap, prof, kShifts);
+  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, log, wsl,
+                     theta, wst, info, wmap, prof, kShifts);
+  // rows of Z per replay workgroup: as many as 150 KiB of LDS hold next to
+  // the staged records, at most 256 / kShifts
+  const size_t rec_bytes = size_t(kChunk) * kShifts * sizeof(RotRec);
+  const int rows = int(std::max<size_t>(1, std::min<size_t>(256 / kShifts,
+                                                          (size_t(150) * 1024 - rec_bytes) / (size_t(m) * sizeof(c128)))));
+  const size_t lds = size_t(rows) * m * sizeof(c128) + rec_bytes;
+  if (lds > size_t(150) * 1024) throw DeviceError("schur: basis too large for the Z replay");
+  if (lds > size_t(64) * 1024) {
+    static size_t granted = 0;
+    if (lds > granted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(zreplay_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) throw DeviceError(std::string("zreplay: LDS attribute: ") + hipGetErrorString(e));
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(zreplay_kernel, dim3((m + rows - 1) / rows, nwin), dim3(rows * kShifts), lds, st, Z, wsz, m,
+                     log, wsl, rows, wmap);
   if (prof) {
     unsigned long long z[8];
     (void)hipMemcpyFromSymbolAsync(z, HIP_SYMBOL(g_k4prof), sizeof(z), 0, hipMemcpyDeviceToHost, st);
