@@ -41,11 +41,14 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------- Hessenberg
-// Householder reduction H <- P^H H P to upper Hessenberg form, Z <- Z P.
-// Column reductions (v^H H) run one thread per column; row reductions
-// (H v) run one wavefront per row so that every load is coalesced.
-__global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Zall,
-                                                                 int64_t wsz, const int* __restrict__ wmap) {
+// Householder reduction H <- P^H H P to upper Hessenberg form.  Column
+// reductions (v^H H) run one thread per column; row reductions (H v) run
+// sixteen lanes per row so that every load is coalesced.  The reflectors
+// (v_k at R[k][k+1..m-1], beta_k at R[k][0]) are kept, and the product
+// Z = P_0 P_1 ... is formed afterwards by householder_z_kernel, many
+// workgroups per matrix: each row of Z is transformed independently.
+__global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Rall,
+                                                                 int64_t wsr, const int* __restrict__ wmap) {
   extern __shared__ c128 sm[];  // v[m], then 4 x kEigThreads partial column sums
   __shared__ double red[kEigThreads / 64];
   c128* v = sm;
@@ -53,14 +56,9 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
-  c128* Z = Zall + int64_t(w) * wsz;
+  c128* Rf = Rall + int64_t(w) * wsr;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   constexpr int NW = kEigThreads / 64;
-  for (int64_t e = t; e < int64_t(m) * m; e += kEigThreads) {
-    const int i = int(e / m), j = int(e % m);
-    Z[e] = c128{i == j ? 1.0 : 0.0, 0.0};
-  }
-  __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
     const int len = m - k - 1;  // rows k+1 .. m-1
     double part = 0.0;
@@ -74,11 +72,16 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
     __syncthreads();  // every thread has read v[0] before it is rewritten
     const double ax0 = cabs(x0);
     const double alpha = sqrt(alpha2);
-    if (alpha == 0.0 || alpha2 - ax0 * ax0 <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) continue;
+    if (alpha == 0.0 || alpha2 - ax0 * ax0 <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) {
+      if (t == 0) Rf[int64_t(k) * m] = c128{0.0, 0.0};  // no reflector: beta = 0
+      continue;
+    }
     const c128 ph = ax0 > 0.0 ? c128{x0.re / ax0, x0.im / ax0} : c128{1.0, 0.0};
     if (t == 0) v[0] = x0 + alpha * ph;
     __syncthreads();
     const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
+    for (int i = t; i < len; i += kEigThreads) Rf[int64_t(k) * m + k + 1 + i] = v[i];
+    if (t == 0) Rf[int64_t(k) * m] = c128{beta, 0.0};
     // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k; each column
     // is split over P row ranges (P threads per column, partial sums in LDS)
     {
@@ -118,14 +121,14 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
       }
     }
     __syncthreads();
-    // right: row r of H and of Z: row[k+1..] -= beta (row[k+1..] v) v^H;
-    // four rows per wavefront, 16 lanes per row
+    // right: row r of H: row[k+1..] -= beta (row[k+1..] v) v^H; four rows
+    // per wavefront, 16 lanes per row
     {
       const int sub = lane & 15, rsel = lane >> 4;
-      for (int r0 = wv * 4; r0 < 2 * m; r0 += NW * 4) {
+      for (int r0 = wv * 4; r0 < m; r0 += NW * 4) {
         const int r = r0 + rsel;
-        const bool ok = r < 2 * m;
-        c128* row = !ok ? H : (r < m) ? (H + int64_t(r) * m) : (Z + int64_t(r - m) * m);
+        const bool ok = r < m;
+        c128* row = H + int64_t(ok ? r : 0) * m;
         double sr = 0.0, si = 0.0;
         if (ok)
           for (int j = sub; j < len; j += 16) {
@@ -152,33 +155,114 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
   }
 }
 
+// Z = P_0 P_1 ... P_{m-3} from the reflectors R of hessenberg_kernel, rows
+// [r0, r0 + 16) per workgroup: each row starts as e_r and takes
+// z[k+1..] -= beta_k (z[k+1..] v_k) v_k^H in order, sixteen lanes per row
+// (the arithmetic of applying the reflectors to Z inside the reduction).
+constexpr int kZRows = 16;
+
+__global__ __launch_bounds__(kZRows * 16) void householder_z_kernel(const c128* __restrict__ Rall, int64_t wsr, int m,
+                                                                   c128* Zall, int64_t wsz,
+                                                                   const int* __restrict__ wmap) {
+  extern __shared__ c128 zr[];  // kZRows x m
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  if (w < 0) return;
+  const int r0 = int(blockIdx.x) * kZRows;
+  if (r0 >= m) return;
+  const c128* Rf = Rall + int64_t(w) * wsr;
+  c128* Z = Zall + int64_t(w) * wsz;
+  const int t = threadIdx.x, sub = t & 15, rr = t >> 4;
+  const int r = r0 + rr;
+  const bool ok = r < m;
+  c128* row = zr + int64_t(rr) * m;
+  for (int j = sub; j < m; j += 16) row[j] = c128{ok && j == r ? 1.0 : 0.0, 0.0};
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    const double beta = Rf[int64_t(k) * m].re;
+    if (beta == 0.0) continue;  // uniform: no reflector at this column
+    const int len = m - k - 1;
+    const c128* v = Rf + int64_t(k) * m + k + 1;
+    double sr = 0.0, si = 0.0;
+    for (int j = sub; j < len; j += 16) {
+      const c128 a = row[k + 1 + j], b = v[j];
+      sr += a.re * b.re - a.im * b.im;
+      si += a.re * b.im + a.im * b.re;
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o, 16);
+      si += __shfl_xor(si, o, 16);
+    }
+    const c128 sc = beta * c128{sr, si};
+    for (int j = sub; j < len; j += 16) {
+      c128& h = row[k + 1 + j];
+      h = h - sc * conj(v[j]);
+    }
+    __syncthreads();
+  }
+  if (ok)
+    for (int j = sub; j < m; j += 16) Z[int64_t(r) * m + j] = row[j];
+}
+
 // ---------------------------------------------------------------- vectors
-// X[:, j] = eigenvector of upper triangular T for T[j, j] (x_j = 1, x_i = 0 for i > j).
-__global__ void trevc_kernel(const c128* Tall, int64_t wst, int m, c128* Xall, int64_t wsx,
-                             const int* __restrict__ wmap) {
+// X[:, j] = eigenvector of upper triangular T for T[j, j] (x_j = 1, x_i = 0
+// for i > j), by back substitution.  One wavefront per eigenvector: each
+// x_i needs the dot product of row i of T (contiguous) with the x_p already
+// found, which the lanes split and reduce; x lives in LDS.
+constexpr int kTrevcWaves = 4;
+
+// Orders one wavefront's LDS traffic: its lanes run in lockstep and its LDS
+// operations complete in order, so a fence plus a wave barrier suffices.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline c128 wave_sum(c128 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_xor(v.re, o, 64);
+    v.im += __shfl_xor(v.im, o, 64);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(64 * kTrevcWaves) void trevc_kernel(const c128* Tall, int64_t wst, int m, c128* Xall,
+                                                                 int64_t wsx, const int* __restrict__ wmap) {
+  extern __shared__ c128 xs_all[];  // kTrevcWaves x m
   const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
   if (w < 0) return;  // idle slot (whole workgroup)
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = int(blockIdx.x) * kTrevcWaves + wv;
+  if (j >= m) return;  // whole wavefront
   const c128* T = Tall + int64_t(w) * wst;
   c128* X = Xall + int64_t(w) * wsx;
+  c128* xs = xs_all + int64_t(wv) * m;
   const c128 lam = T[int64_t(j) * m + j];
   double tnorm = 0.0;
-  for (int i = 0; i < m; ++i) tnorm = fmax(tnorm, cabs1(T[int64_t(i) * m + i]));
+  for (int i = lane; i < m; i += 64) tnorm = fmax(tnorm, cabs1(T[int64_t(i) * m + i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tnorm = fmax(tnorm, __shfl_xor(tnorm, o, 64));
   const double smin = fmax(2.220446049250313e-16 * tnorm, 1e-290);
-  for (int i = m - 1; i > j; --i) X[int64_t(i) * m + j] = c128{0.0, 0.0};
-  X[int64_t(j) * m + j] = c128{1.0, 0.0};
+  if (lane == 0) xs[j] = c128{1.0, 0.0};
+  wave_lds_sync();
   for (int i = j - 1; i >= 0; --i) {
-    c128 s{0.0, 0.0};
-    for (int p = i + 1; p <= j; ++p) fma_acc(s, T[int64_t(i) * m + p], X[int64_t(p) * m + j]);
-    c128 d = T[int64_t(i) * m + i] - lam;
+    const c128* Ti = T + int64_t(i) * m;
+    c128 part{0.0, 0.0};
+    for (int p = i + 1 + lane; p <= j; p += 64) fma_acc(part, Ti[p], xs[p]);
+    const c128 sum = wave_sum(part);
+    c128 d = Ti[i] - lam;
     if (cabs1(d) < smin) d = c128{smin, 0.0};
-    const c128 xi = cdiv(c128{-s.re, -s.im}, d);
-    X[int64_t(i) * m + j] = xi;
+    const c128 xi = cdiv(c128{-sum.re, -sum.im}, d);
+    if (lane == 0) xs[i] = xi;
+    wave_lds_sync();
     if (cabs1(xi) > 1e150) {  // rescale to keep the back substitution finite
-      for (int p = i; p <= j; ++p) X[int64_t(p) * m + j] = 1e-150 * X[int64_t(p) * m + j];
+      for (int p = i + lane; p <= j; p += 64) xs[p] = 1e-150 * xs[p];
+      wave_lds_sync();
     }
   }
+  for (int p = lane; p < m; p += 64) X[int64_t(p) * m + j] = p <= j ? xs[p] : c128{0.0, 0.0};
 }
 
 // Y = Z X (m x m, row-major, 16 x 16 tiles), then each column of Y is
@@ -348,10 +432,36 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   if (nwin <= 0 || m <= 0) return;
   c128* Z = work;               // m*m per window at stride wsw
   c128* X = work + int64_t(m) * m;
+  // the reflectors go to X, which is free until the eigenvector step
   hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), (size_t(m) + 4 * kEigThreads) * sizeof(c128), st, H, wsh, m,
-                     Z, wsw, wmap);
+                     X, wsw, wmap);
+  const size_t zlds = size_t(kZRows) * m * sizeof(c128);
+  if (zlds > size_t(150) * 1024) throw DeviceError("householder_z: basis too large for the LDS");
+  if (zlds > size_t(64) * 1024) {
+    static size_t granted = 0;
+    if (zlds > granted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(householder_z_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(zlds));
+      if (e != hipSuccess) throw DeviceError(std::string("householder_z: LDS attribute: ") + hipGetErrorString(e));
+      granted = zlds;
+    }
+  }
+  hipLaunchKernelGGL(householder_z_kernel, dim3((m + kZRows - 1) / kZRows, nwin), dim3(kZRows * 16), zlds, st, X, wsw,
+                     m, Z, wsw, wmap);
   launch_schur(H, wsh, m, Z, wsw, work + 2 * int64_t(m) * m, wsw, theta, wst, info, nwin, st, wmap);
-  hipLaunchKernelGGL(trevc_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, H, wsh, m, X, wsw, wmap);
+  const size_t tlds = size_t(kTrevcWaves) * m * sizeof(c128);
+  if (tlds > size_t(150) * 1024) throw DeviceError("trevc: basis too large for the LDS");
+  if (tlds > size_t(64) * 1024) {
+    static size_t granted = 0;
+    if (tlds > granted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(trevc_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(tlds));
+      if (e != hipSuccess) throw DeviceError(std::string("trevc: LDS attribute: ") + hipGetErrorString(e));
+      granted = tlds;
+    }
+  }
+  hipLaunchKernelGGL(trevc_kernel, dim3((m + kTrevcWaves - 1) / kTrevcWaves, nwin), dim3(64 * kTrevcWaves), tlds, st,
+                     H, wsh, m, X, wsw, wmap);
   hipLaunchKernelGGL(small_gemm_kernel, dim3((m + 15) / 16, (m + 15) / 16, nwin), dim3(256), 0, st, Z, wsw, X, wsw,
                      Y, wsy, m, wmap);
   hipLaunchKernelGGL(colnorm_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, Y, wsy, m, wmap);
