@@ -340,11 +340,11 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
   }
   __syncthreads();
   // nearest nev eigenvectors and their values
-  for (int q = 0; q < nev; ++q) {
-    const int src = order[q];
-    for (int i = t; i < m; i += 256) out[int64_t(i) * ld + k + q] = Y[int64_t(i) * m + src];
-    if (t == 0) thsel[int64_t(w) * wss + q] = th[src];
+  for (int e = t; e < m * nev; e += 256) {
+    const int i = e / nev, q = e % nev;
+    out[int64_t(i) * ld + k + q] = Y[int64_t(i) * m + order[q]];
   }
+  for (int q = t; q < nev; q += 256) thsel[int64_t(w) * wss + q] = th[order[q]];
   // orthonormal basis of the first k selected eigenvectors: blocks of kSB
   // columns staged in LDS, each made orthogonal to the columns before it by
   // two passes of block classical Gram-Schmidt, then orthonormalised inside
@@ -360,14 +360,20 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
       // C = out[:, :q0]^H W  (q0 x nb)
       for (int e = t; e < q0 * nb; e += 256) {
         const int p = e % q0, j = e / q0;
-        c128 s0{0.0, 0.0}, s1{0.0, 0.0};
+        // eight partial sums keep eight loads in flight
+        c128 sp[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sp[u] = c128{0.0, 0.0};
         int i = 0;
-        for (; i + 1 < m; i += 2) {
-          fma_cacc(s0, out[int64_t(i) * ld + p], Wb[i * kSB + j]);
-          fma_cacc(s1, out[int64_t(i + 1) * ld + p], Wb[(i + 1) * kSB + j]);
+        for (; i + 7 < m; i += 8) {
+          c128 a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = out[int64_t(i + u) * ld + p];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) fma_cacc(sp[u], a[u], Wb[(i + u) * kSB + j]);
         }
-        if (i < m) fma_cacc(s0, out[int64_t(i) * ld + p], Wb[i * kSB + j]);
-        coef[p * kSB + j] = s0 + s1;
+        for (; i < m; ++i) fma_cacc(sp[0], out[int64_t(i) * ld + p], Wb[i * kSB + j]);
+        coef[p * kSB + j] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
       }
       __syncthreads();
       // W -= out[:, :q0] C, one thread per row
@@ -376,7 +382,17 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
 #pragma unroll
         for (int j = 0; j < kSB; ++j) acc[j] = c128{0.0, 0.0};
         const c128* row = out + int64_t(i) * ld;
-        for (int p = 0; p < q0; ++p) {
+        int p = 0;
+        for (; p + 3 < q0; p += 4) {
+          c128 a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[u] = row[p + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < kSB; ++j) fma_acc(acc[j], a[u], coef[(p + u) * kSB + j]);
+        }
+        for (; p < q0; ++p) {
           const c128 a = row[p];
 #pragma unroll
           for (int j = 0; j < kSB; ++j) fma_acc(acc[j], a, coef[p * kSB + j]);
