@@ -713,6 +713,128 @@ void dgks_select(const double* before, const double* after, int s, int nslot, co
   hipLaunchKernelGGL(dgks_kernel, dim3((nslot + 63) / 64), dim3(64), 0, st, before, after, s, nslot, wmap, wmap2);
 }
 
+// Lagged second Gram-Schmidt pass (one workgroup per window).  G is the
+// (j + b) x 2b product [V_j P]^H [P W] of a block step: S = V_j^H P (rows
+// 0..j-1, columns 0..b-1), C = V_j^H W (rows 0..j-1, columns b..2b-1),
+// P^H P and P^H W (rows j..j+b-1).  After [P W] -= V_j [S C], the pending
+// block P' = P - V_j S has Gram P'^H P' = P^H P - S^H S = R^H R and
+// P'^H W' = P^H W - S^H C; M (2b x 2b) maps [P' W'] to
+// [P' R^-1, W' - P' R^-1 D] with D = R^-H (P^H W - S^H C), i.e. the final
+// block and W' made orthogonal to it.
+constexpr int kLagThreads = 64 * 2 * kLagMax * kLagMax / 4;  // 8 wavefronts
+
+__global__ __launch_bounds__(kLagThreads) void lagfix_kernel(const c128* G, int64_t wsg, int j, int b, c128* M,
+                                                             int64_t wsm, int* flags, const int* __restrict__ wmap) {
+  __shared__ c128 A[kLagMax * kLagMax], E[kLagMax * kLagMax], R[kLagMax * kLagMax], Ri[kLagMax * kLagMax];
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const c128* Gw = G + int64_t(w) * wsg;
+  c128* Mw = M + int64_t(w) * wsm;
+  const int t = threadIdx.x, ld = 2 * b, lane = t & 63;
+  // A = P^H P - S^H S and E = P^H W - S^H C: one wavefront per entry, the
+  // sum over the basis rows split over its lanes
+  for (int e = t >> 6; e < 2 * b * b; e += kLagThreads / 64) {
+    const int which = e / (b * b), pq = e % (b * b), p = pq / b, q = pq % b;
+    const int col = which ? b + q : q;
+    c128 v{0.0, 0.0};
+    for (int i = lane; i < j; i += 64) fma_cacc(v, Gw[int64_t(i) * ld + p], Gw[int64_t(i) * ld + col]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      v.re += __shfl_xor(v.re, o, 64);
+      v.im += __shfl_xor(v.im, o, 64);
+    }
+    if (lane == 0) (which ? E : A)[p * b + q] = Gw[int64_t(j + p) * ld + col] - v;
+  }
+  __syncthreads();
+  if (t == 0) {
+    // Cholesky A = R^H R (R upper), then R^-1
+    int bad = 0;
+    double tr = 0.0;
+    for (int i = 0; i < b; ++i) tr += A[i * b + i].re;
+    const double floor = 1e-26 * (tr > 0 ? tr : 1.0);
+    for (int k = 0; k < b; ++k) {
+      double d = A[k * b + k].re;
+      for (int p = 0; p < k; ++p) d -= norm2(R[p * b + k]);
+      if (!(d > floor)) { bad = 1; d = floor > 0 ? floor : 1e-300; }
+      d = sqrt(d);
+      R[k * b + k] = c128{d, 0.0};
+      for (int q = k + 1; q < b; ++q) {
+        c128 v = A[k * b + q];
+        for (int p = 0; p < k; ++p) v = v - conj(R[p * b + k]) * R[p * b + q];
+        R[k * b + q] = (1.0 / d) * v;
+      }
+      for (int i = k + 1; i < b; ++i) R[i * b + k] = c128{0.0, 0.0};
+    }
+    for (int q = 0; q < b; ++q)
+      for (int i = b - 1; i >= 0; --i) {
+        c128 v = (i == q) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+        for (int p = i + 1; p <= q; ++p) v = v - R[i * b + p] * Ri[p * b + q];
+        Ri[i * b + q] = (i > q) ? c128{0.0, 0.0} : (1.0 / R[i * b + i].re) * v;
+      }
+    // D = R^-H E (lower-triangular solve R^H D = E), kept in A
+    for (int q = 0; q < b; ++q)
+      for (int i = 0; i < b; ++i) {
+        c128 v = E[i * b + q];
+        for (int p = 0; p < i; ++p) v = v - conj(R[p * b + i]) * A[p * b + q];
+        A[i * b + q] = (1.0 / R[i * b + i].re) * v;
+      }
+    // M = [[R^-1, -R^-1 D], [0, I]]
+    for (int p = 0; p < b; ++p)
+      for (int q = 0; q < b; ++q) {
+        c128 v{0.0, 0.0};
+        for (int i = 0; i < b; ++i) v = v + Ri[p * b + i] * A[i * b + q];
+        Mw[p * ld + q] = Ri[p * b + q];
+        Mw[p * ld + b + q] = c128{-v.re, -v.im};
+        Mw[(b + p) * ld + q] = c128{0.0, 0.0};
+        Mw[(b + p) * ld + b + q] = c128{p == q ? 1.0 : 0.0, 0.0};
+      }
+    flags[w] = bad;
+  }
+}
+
+// Y[w] (N x s, s <= kLagMax * 2 contiguous columns) <- Y[w] M[w] (s x s,
+// row-major), in place: each thread owns one row.
+template <typename T>
+__global__ __launch_bounds__(256) void rowmix_kernel(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* M, int64_t wsm,
+                                                     Rows rows, int s, const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.z] : blockIdx.z;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (n >= rows.of(w)) return;
+  cplx<T>* y = Y + int64_t(w) * wsy + n;
+  const c128* Mw = M + int64_t(w) * wsm;
+  c128 x[2 * kLagMax];
+  for (int p = 0; p < s; ++p) {
+    const cplx<T> v = y[int64_t(p) * ldy];
+    x[p] = c128{double(v.re), double(v.im)};
+  }
+  for (int q = 0; q < s; ++q) {
+    c128 acc{0.0, 0.0};
+    for (int p = 0; p < s; ++p) fma_acc(acc, x[p], Mw[p * s + q]);
+    y[int64_t(q) * ldy] = cplx<T>{T(acc.re), T(acc.im)};
+  }
+}
+
+void lagfix(const c128* G, int64_t wsg, int j, int b, c128* M, int64_t wsm, int* flags, int nwin, hipStream_t st,
+            const int* wmap) {
+  if (nwin <= 0) return;
+  if (b > kLagMax) throw DeviceError("block size too large for the lagged Gram-Schmidt pass");
+  hipLaunchKernelGGL(lagfix_kernel, dim3(nwin), dim3(kLagThreads), 0, st, G, wsg, j, b, M, wsm, flags, wmap);
+}
+
+template <typename T>
+void rowmix(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* M, int64_t wsm, Rows rows, int s, int nwin,
+            hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || s <= 0) return;
+  if (s > 2 * kLagMax) throw DeviceError("rowmix: too many columns");
+  hipLaunchKernelGGL((rowmix_kernel<T>), dim3(unsigned((rows.N + 255) / 256), 1, nwin), dim3(256), 0, st, Y, ldy, wsy,
+                     M, wsm, rows, s, wmap);
+}
+template void rowmix<double>(cplx<double>*, int64_t, int64_t, const c128*, int64_t, Rows, int, int, hipStream_t,
+                             const int*);
+template void rowmix<float>(cplx<float>*, int64_t, int64_t, const c128*, int64_t, Rows, int, int, hipStream_t,
+                            const int*);
+
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
                   const int* wmap) {
   if (nwin <= 0) return;

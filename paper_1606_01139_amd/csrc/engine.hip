@@ -157,34 +157,37 @@ struct SolveStream {
 
 // ------------------------------------------------------------------ batch
 // Device state of one batched solve in storage precision T.  Window w's
-// basis V (ldN x m, contiguous columns) starts at V + w * ldN * m; likewise
-// AV and the rotation targets Vr, AVr.  F holds each window's continuation
-// block (ldN x b).
+// basis V (ldN x (m + b), contiguous columns) starts at V + w * ws(): the m
+// basis columns, then the next block (the continuation of the cycle);
+// likewise the rotation target Vr.  AV (ldN x m, window stride ldN m) holds
+// A V for the Rayleigh-Ritz projection; AR (ldN x nev, window stride ws())
+// holds A times the wanted Ritz vectors.  Ft is a b-column temporary.
 template <typename T> struct Batch {
   int nw = 0, m = 0, k = 0, b = 0, nv = 0;
   int64_t ldN = 0;
   Rows rows;
-  DevArr<cplx<T>> V, AV, Vr, AVr, F, Ft;
-  DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, part;
+  DevArr<cplx<T>> V, AV, Vr, AR, Ft;
+  DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, Mx, part;
   DevArr<double> res, sig, nb, na;
   DevArr<int> flags, info, wmap, wmap2, sel;
 
   void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
     nw = nw_; ldN = S.ldN; rows = S.rows_arg(); m = m_; k = k_; b = b_; nv = nv_;
     const int64_t N = S.Nmax;
-    const size_t nm = size_t(ldN) * m * nw;
-    V.alloc(nm); AV.alloc(nm); Vr.alloc(nm); AVr.alloc(nm);
-    F.alloc(size_t(ldN) * b * nw); Ft.alloc(size_t(ldN) * b * nw);
+    V.alloc(size_t(ws()) * nw); Vr.alloc(size_t(ws()) * nw);
+    AV.alloc(size_t(ldN) * m * nw); AR.alloc(size_t(ws()) * nw);
+    Ft.alloc(size_t(ldN) * b * nw);
     H.alloc(size_t(m) * m * nw); Ys.alloc(size_t(m) * m * nw);
     work.alloc(size_t(smalleig_workspace(m)) * nw);
     theta.alloc(size_t(m) * nw);
     Ysel.alloc(size_t(m) * (k + nv) * nw);
     thsel.alloc(size_t(nv) * nw);
-    C.alloc(size_t(m) * b * nw);
+    C.alloc(size_t(wsc()) * nw);
     G.alloc(size_t(b) * b * nw);
     Rinv.alloc(size_t(b) * b * nw);
+    Mx.alloc(size_t(4) * b * b * nw);
     int64_t pw = gram_workspace(N, m, m, nw);
-    pw = std::max(pw, gram_workspace(N, m, b, nw));
+    pw = std::max(pw, gram_workspace(N, m + b, 2 * b, nw));
     pw = std::max(pw, gram_workspace(N, b, b, nw));
     pw = std::max(pw, residual_workspace(N, nv, nw));
     part.alloc(size_t(pw));
@@ -193,7 +196,8 @@ template <typename T> struct Batch {
     flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
     wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * b); na.alloc(size_t(nw) * b);
   }
-  int64_t ws() const { return ldN * m; }
+  int64_t ws() const { return ldN * (m + b); }
+  int64_t wsc() const { return int64_t(m + b) * 2 * b; }
 };
 
 // dest (ldN x b per window, column stride ldd, window stride wsd) is made
@@ -233,6 +237,37 @@ void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, i
     cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, nw, st, wm);
     gemm_cols<T>(src, lds, wss, B.Rinv.p, b, int64_t(b) * b, dst, ldo, wso, B.rows, b, b, 0.0, nw, st, wm, 1.0);
   }
+}
+
+// One block step of the expansion with the second Gram-Schmidt pass lagged
+// by one step (two sweeps over the basis instead of four).  On entry the
+// columns [0, j) of V are final and P = V[:, j:j+b] is pending: orthogonal to
+// them after one pass and orthonormal within itself.  The step computes
+// W = A P into V[:, j+b:j+2b]; one Gram pass gives [V_j P]^H [P W]; one update
+// pass applies P' = P - V_j S (the second pass for P) and W' = W - V_j C; a
+// b-column mix makes P' orthonormal (final) and W' orthogonal to it; W' is
+// then normalised (Cholesky-QR) and becomes the pending block.  W is taken
+// from the pending P: the terms A V_j S it carries lie in the span of the
+// basis and are projected out with the rest.
+template <typename T>
+void expand_step(const Systems& S, Batch<T>& B, int j) {
+  const int b = B.b, nw = B.nw;
+  const int* wm = B.wmap.p;
+  hipStream_t st = S.st;
+  const int64_t ldN = B.ldN, wsV = B.ws();
+  cplx<T>* P = B.V.p + j * ldN;
+  cplx<T>* W = B.V.p + (j + b) * ldN;
+  stencil<T>(S, P, ldN, wsV, W, ldN, wsV, b, nw, wm);
+  gram<T, T>(B.V.p, ldN, wsV, P, ldN, wsV, B.rows, j + b, 2 * b, B.C.p, 2 * b, B.wsc(), nw, B.part.p,
+             int64_t(B.part.n), st, wm);
+  lagfix(B.C.p, B.wsc(), j, b, B.Mx.p, int64_t(4) * b * b, B.flags.p, nw, st, wm);
+  if (j > 0)
+    gemm_cols<T>(B.V.p, ldN, wsV, B.C.p, 2 * b, B.wsc(), P, ldN, wsV, B.rows, j, 2 * b, 1.0, nw, st, wm, -1.0);
+  rowmix<T>(P, ldN, wsV, B.Mx.p, int64_t(4) * b * b, B.rows, 2 * b, nw, st, wm);
+  gram<T, T>(W, ldN, wsV, W, ldN, wsV, B.rows, b, b, B.G.p, b, int64_t(b) * b, nw, B.part.p, int64_t(B.part.n), st,
+             wm);
+  cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, nw, st, wm);
+  rowmix<T>(W, ldN, wsV, B.Rinv.p, int64_t(b) * b, B.rows, b, nw, st, wm);
 }
 
 struct WinOut {
@@ -287,45 +322,41 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
     random_block<T>(B.V.p, ldN, wsV, rows, b, nw, seed, st, wm);
     orthonormalize<T>(S, B, B.V.p, ldN, wsV, 0);
   } else {
-    // promote the complex64 kept basis and continuation block, re-orthonormalise
-    // block by block in this precision and recompute A V for the kept part
+    // promote the complex64 kept basis and continuation block and
+    // re-orthonormalise them block by block in this precision
     copy_block<float, T>(init_from, ldN, ldN * (k + b), B.V.p, ldN, wsV, rows, k + b, nw, st, wm);
     for (int j = 0; j <= k; j += b) orthonormalize<T>(S, B, B.V.p + j * ldN, ldN, wsV, j);
-    stencil<T>(S, B.V.p, ldN, wsV, B.AV.p, ldN, wsV, k, nw, wm);
-    for (int w = 0; w < nw; ++w) out[w].matvecs += k;
     j0 = k;
   }
   // expansion from column j0, projection, small eigenproblem, selection,
   // rotation and residual norms; with `cont`, first the continuation block
-  // (and in Davidson mode the residual block that feeds it)
+  // left pending after the previous cycle's last step (in Davidson mode the
+  // residual block of the wanted Ritz pairs instead, orthonormalised)
   auto body = [&](int jstart, bool cont) {
     if (cont) {
-      if (davidson)
-        residual_block<T>(B.V.p + k * ldN, B.AV.p + k * ldN, ldN, wsV, B.thsel.p, nv, B.sel.p, b, B.F.p, ldN,
-                          ldN * b, rows, nw, st, wm);
-      copy_block<T, T>(B.F.p, ldN, ldN * b, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
-      orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
+      if (davidson) {
+        residual_block<T>(B.V.p + k * ldN, B.AR.p, ldN, wsV, B.thsel.p, nv, B.sel.p, b, B.Ft.p, ldN, ldN * b, rows,
+                          nw, st, wm);
+        copy_block<T, T>(B.Ft.p, ldN, ldN * b, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
+        orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
+      } else {
+        copy_block<T, T>(B.Vr.p + m * ldN, ldN, wsV, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
+      }
     }
-    for (int j = jstart; j < m; j += b) {
-      stencil<T>(S, B.V.p + j * ldN, ldN, wsV, B.AV.p + j * ldN, ldN, wsV, b, nw, wm);
-      const bool last = j + b >= m;
-      cplx<T>* dest = last ? B.F.p : B.V.p + (j + b) * ldN;
-      const int64_t wsd = last ? ldN * b : wsV;
-      copy_block<T, T>(B.AV.p + j * ldN, ldN, wsV, dest, ldN, wsd, rows, b, nw, st, wm);
-      orthonormalize<T>(S, B, dest, ldN, wsd, j + b);
-    }
-    gram<T, T>(B.V.p, ldN, wsV, B.AV.p, ldN, wsV, rows, m, m, B.H.p, m, int64_t(m) * m, nw, B.part.p,
+    for (int j = jstart; j < m; j += b) expand_step<T>(S, B, j);
+    // Rayleigh-Ritz on the final basis: A V afresh, then H = V^H A V
+    stencil<T>(S, B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, m, nw, wm);
+    gram<T, T>(B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, rows, m, m, B.H.p, m, int64_t(m) * m, nw, B.part.p,
                int64_t(B.part.n), st, wm);
     smalleig(B.H.p, int64_t(m) * m, m, B.theta.p, m, B.Ys.p, int64_t(m) * m, B.work.p, smalleig_workspace(m),
              B.info.p, nw, st, wm);
     select_restart(B.theta.p, m, B.Ys.p, int64_t(m) * m, m, B.sig.p, mode, k, nv, B.Ysel.p, int64_t(m) * (k + nv),
                    B.thsel.p, nv, nw, st, wm);
-    // rotation: [V Q_k | V Y_nev] and the same for A V
+    // rotation [V Q_k | V Y_nev], then A times the wanted Ritz vectors
     gemm_cols<T>(B.V.p, ldN, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.Vr.p, ldN, wsV, rows, m, k + nv, 0.0,
                  nw, st, wm);
-    gemm_cols<T>(B.AV.p, ldN, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.AVr.p, ldN, wsV, rows, m, k + nv, 0.0,
-                 nw, st, wm);
-    residual_norms<T>(B.Vr.p + k * ldN, ldN, wsV, B.AVr.p + k * ldN, ldN, wsV, B.thsel.p, nv, rows, nv, nw, B.res.p,
+    stencil<T>(S, B.Vr.p + k * ldN, ldN, wsV, B.AR.p, ldN, wsV, nv, nw, wm);
+    residual_norms<T>(B.Vr.p + k * ldN, ldN, wsV, B.AR.p, ldN, wsV, B.thsel.p, nv, rows, nv, nw, B.res.p,
                       reinterpret_cast<double*>(B.part.p), 2 * int64_t(B.part.n), st, wm);
   };
   CycleGraphs graphs;
@@ -355,13 +386,12 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
     } else {
       body(steady ? k : j0, steady);
     }
-    for (int w : active) out[w].matvecs += (m - (steady ? k : j0));
+    for (int w : active) out[w].matvecs += (m - (steady ? k : j0)) + m + nv;
     check(hipMemcpyAsync(hres.data(), B.res.p, sizeof(double) * 2 * nv * nw, hipMemcpyDeviceToHost, st), "res");
     check(hipMemcpyAsync(hth.data(), B.thsel.p, sizeof(c128) * nv * nw, hipMemcpyDeviceToHost, st), "theta");
     check(hipMemcpyAsync(hinfo.data(), B.info.p, sizeof(int) * nw, hipMemcpyDeviceToHost, st), "info");
     check(hipStreamSynchronize(st), "sync");
     std::swap(B.V, B.Vr);
-    std::swap(B.AV, B.AVr);
     std::vector<int> still;
     for (int w : active) {
       WinOut& o = out[w];
@@ -559,7 +589,7 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
     return [&](int w) {
       const int64_t Nw = S.of(w)->N;
       results[w].alloc(size_t(Nw) * wins[w].nev);
-      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * Nw, Bd.V.p + size_t(w) * ldN * m + size_t(k) * ldN,
+      check(hipMemcpy2DAsync(results[w].p, sizeof(c128) * Nw, Bd.V.p + size_t(w) * Bd.ws() + size_t(k) * ldN,
                              sizeof(c128) * ldN, sizeof(c128) * Nw, wins[w].nev, hipMemcpyDeviceToDevice, st),
             "save");
     };
@@ -574,11 +604,13 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
       std::vector<WinOut> fo;
       const double btol = std::max(o.bulk_tol > 0 ? o.bulk_tol : 1e-5, o.tol);
       iterate<float>(S, Bf, wins, normA, o.select, btol, o.max_restarts, o.seed, nullptr, fo, [&](int w) {
-        // V (already swapped) holds the kept basis in columns [0, k); F the continuation
-        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b), Bf.V.p + size_t(w) * ldN * m,
+        // V (already swapped) holds the kept basis in columns [0, k); the
+        // other buffer the cycle's pending continuation block in [m, m + b)
+        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b), Bf.V.p + size_t(w) * Bf.ws(),
                              sizeof(c64) * ldN * k, hipMemcpyDeviceToDevice, st), "handoff");
-        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b) + size_t(k) * ldN, Bf.F.p + size_t(w) * ldN * b,
-                             sizeof(c64) * ldN * b, hipMemcpyDeviceToDevice, st), "handoff");
+        check(hipMemcpyAsync(hand.p + size_t(w) * ldN * (k + b) + size_t(k) * ldN,
+                             Bf.Vr.p + size_t(w) * Bf.ws() + size_t(m) * ldN, sizeof(c64) * ldN * b,
+                             hipMemcpyDeviceToDevice, st), "handoff");
       }, use_graphs, 100.0 * btol);
       for (int w = 0; w < nw; ++w) { bulk_restarts[w] = fo[w].restarts; bulk_mv[w] = fo[w].matvecs; }
     }

@@ -106,6 +106,18 @@ void col_sqnorms(const cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, int s, i
 void dgks_select(const double* before, const double* after, int s, int nslot, const int* wmap, int* wmap2,
                  hipStream_t st);
 
+// Lagged second Gram-Schmidt pass of a block step: from the (j + b) x 2b
+// product G = [V_j P]^H [P W] (ld 2b, window stride wsg) forms the 2b x 2b
+// matrix M with [P' W'] M = [final P, W' orthogonal to it] (see dense.hip);
+// flags[w] = 1 on a Cholesky breakdown.  b <= kLagMax.
+constexpr int kLagMax = 4;
+void lagfix(const c128* G, int64_t wsg, int j, int b, c128* M, int64_t wsm, int* flags, int nwin, hipStream_t st,
+            const int* wmap = nullptr);
+// Y[w] (N x s contiguous columns) <- Y[w] M[w] (s x s, row-major), in place; s <= 2 kLagMax.
+template <typename T>
+void rowmix(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* M, int64_t wsm, Rows rows, int s, int nwin,
+            hipStream_t st, const int* wmap = nullptr);
+
 // Small per-window kernels on b x b Gram matrices (one workgroup per window):
 // G = R^H R (Cholesky), writes Rinv (upper triangular) and a breakdown flag.
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
