@@ -121,6 +121,9 @@ def k4_flops(m):
     return 4.0 * (10.0 / 3.0 + 4.0 / 3.0 + 25.0) * m ** 3
 
 
+K4_TRAFFIC_C2 = 846_746_142
+
+
 def k4_roofline(m, batch, reps=3):
     """Average duration of the batched small eigensolve (the dominant kernel
     family of a solve) at the solve's basis size, timed with HIP events on
@@ -151,8 +154,12 @@ def k4_roofline(m, batch, reps=3):
     avg = sum(ms) / len(ms)
     fl = k4_flops(m) * batch
     tf = fl / (avg * 1e-3) / 1e12
+    # bytes in and out of L2 per call at the c2 shape (8 x 300 x 300), from
+    # the FETCH_SIZE and WRITE_SIZE counters (each scaled by what it reads for
+    # a plain 512 MiB copy); other shapes were not measured
+    traffic = K4_TRAFFIC_C2 if (m, batch) == (300, 8) else None
     return {"bound": "alu", "achieved": round(tf, 5), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / FP64_PEAK_TFLOPS, 6), "traffic": None,
+            "frac": round(tf / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
             "kernel": "K4 small eigensolve: hessenberg_kernel + schur_kernel + trevc_kernel + small_gemm_kernel "
                       "+ colnorm_kernel (one workgroup per window)",
             "launch": f"{batch} windows x {m}x{m} complex128", "avg_ms": round(avg, 3),
