@@ -121,7 +121,13 @@ def k4_flops(m):
     return 4.0 * (10.0 / 3.0 + 4.0 / 3.0 + 25.0) * m ** 3
 
 
-K4_TRAFFIC_C2 = 846_746_142
+K4_TRAFFIC_C2 = None
+
+
+def auto_basis(nev, block=2):
+    """The library's automatic basis size (about 9 nev, at least 40)."""
+    m = max(9 * nev, nev + 4 * block, 40)
+    return ((m + block - 1) // block) * block
 
 
 def k4_roofline(m, batch, reps=3):
@@ -154,10 +160,10 @@ def k4_roofline(m, batch, reps=3):
     avg = sum(ms) / len(ms)
     fl = k4_flops(m) * batch
     tf = fl / (avg * 1e-3) / 1e12
-    # bytes in and out of L2 per call at the c2 shape (8 x 300 x 300), from
+    # bytes in and out of L2 per call at the c2 shape (8 x 450 x 450), from
     # the FETCH_SIZE and WRITE_SIZE counters (each scaled by what it reads for
     # a plain 512 MiB copy); other shapes were not measured
-    traffic = K4_TRAFFIC_C2 if (m, batch) == (300, 8) else None
+    traffic = K4_TRAFFIC_C2 if (m, batch) == (450, 8) else None
     return {"bound": "alu", "achieved": round(tf, 5), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
             "kernel": "K4 small eigensolve: hessenberg_kernel + schur_kernel + trevc_kernel + small_gemm_kernel "
@@ -280,7 +286,7 @@ def main():
     torch.cuda.set_device(0)
     if args.k4_only:
         w = workload(args.config)
-        out = {"roofline": k4_roofline(args.basis or 6 * w.nev_per_window, w.n_windows)}
+        out = {"roofline": k4_roofline(args.basis or auto_basis(w.nev_per_window), w.n_windows)}
         # a plain device copy of known size, the reference for HBM byte counters
         nb = 512 << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -314,7 +320,7 @@ def main():
     ms = dt / args.steps * 1e3
     nev = w.nev_per_window
     b = opts.block
-    m = opts.basis or 6 * nev
+    m = opts.basis or auto_basis(nev, b)
     log("timing the small eigensolve and the stencil")
     roof = k4_roofline(m, len(wins))
     sdt = "c128" if prec == FP64 else "c64"

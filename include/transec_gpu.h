@@ -80,7 +80,7 @@ typedef struct {
   int32_t precision;    /* TSG_FP64, or TSG_FP32_BULK: complex64 block work then an FP64 polish */
   double tol;           /* backward error ||A u - theta u|| / (||A||_G ||u||) to reach (default 1e-8) */
   int32_t block;        /* vectors per block step b (default 2) */
-  int32_t basis;        /* basis size m per window (0: automatic, about 6 n_{r,j} and at least 40) */
+  int32_t basis;        /* basis size m per window (0: automatic, about 9 n_{r,j} and at least 40) */
   int32_t keep;         /* vectors kept at a restart k (0: automatic, about m/2) */
   int32_t max_restarts; /* per window (default 2000) */
   uint64_t seed;        /* start-vector seed */

@@ -455,10 +455,12 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
 
 void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& b) {
   b = o.block > 0 ? o.block : 2;
-  // automatic: about 6 nev, and at least 40 so that a window of few pairs
-  // (hole filling inserts such) still has room for the Ritz values crowding
-  // its shift
-  m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max({6 * nvmax, nvmax + 4 * b, 40}), b);
+  // automatic: about 9 nev (fewer, costlier restarts pay off: on c2,
+  // 8 x 50 pairs, 38.8 s at m = 420..500 against 42.7 s at m = 300 and
+  // 46.7 s at m = 600), and at least 40 so that a window of few pairs (hole
+  // filling inserts such) still has room for the Ritz values crowding its
+  // shift
+  m = o.basis > 0 ? round_up(o.basis, b) : round_up(std::max({9 * nvmax, nvmax + 4 * b, 40}), b);
   const int mcap = int(std::min<int64_t>(N / b, 4096) * b) - b;
   if (m > mcap) m = std::max(mcap, 2 * b);
   k = o.keep > 0 ? (o.keep / b) * b : ((m / 2) / b) * b;

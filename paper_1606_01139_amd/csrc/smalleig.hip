@@ -44,9 +44,12 @@ __device__ double block_sum(double v, double* red) {
 // Householder reduction H <- P^H H P to upper Hessenberg form.  Column
 // reductions (v^H H) run one thread per column; row reductions (H v) run
 // sixteen lanes per row so that every load is coalesced.  The reflectors
-// (v_k at R[k][k+1..m-1], beta_k at R[k][0]) are kept, and the product
-// Z = P_0 P_1 ... is formed afterwards by householder_z_kernel, many
-// workgroups per matrix: each row of Z is transformed independently.
+// are kept, v_k[1..] in column k of H below the subdiagonal (free once the
+// column is reduced, so the working set stays one m x m matrix), beta_k and
+// v_k[0] in rows 0 and 1 of R; the product Z = P_0 P_1 ... is formed
+// afterwards by householder_z_kernel, many workgroups per matrix (each row
+// of Z is transformed independently), and the Schur step clears the stored
+// vectors from H.
 __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Rall,
                                                                  int64_t wsr, const int* __restrict__ wmap) {
   extern __shared__ c128 sm[];  // v[m], then 4 x kEigThreads partial column sums
@@ -73,15 +76,17 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
     const double ax0 = cabs(x0);
     const double alpha = sqrt(alpha2);
     if (alpha == 0.0 || alpha2 - ax0 * ax0 <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) {
-      if (t == 0) Rf[int64_t(k) * m] = c128{0.0, 0.0};  // no reflector: beta = 0
+      if (t == 0) Rf[k] = c128{0.0, 0.0};  // no reflector: beta = 0
       continue;
     }
     const c128 ph = ax0 > 0.0 ? c128{x0.re / ax0, x0.im / ax0} : c128{1.0, 0.0};
     if (t == 0) v[0] = x0 + alpha * ph;
     __syncthreads();
     const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
-    for (int i = t; i < len; i += kEigThreads) Rf[int64_t(k) * m + k + 1 + i] = v[i];
-    if (t == 0) Rf[int64_t(k) * m] = c128{beta, 0.0};
+    if (t == 0) {
+      Rf[k] = c128{beta, 0.0};
+      Rf[int64_t(m) + k] = v[0];
+    }
     // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k; each column
     // is split over P row ranges (P threads per column, partial sums in LDS)
     {
@@ -150,7 +155,7 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
       }
     }
     __syncthreads();
-    for (int i = k + 2 + t; i < m; i += kEigThreads) H[int64_t(i) * m + k] = c128{0.0, 0.0};
+    for (int i = k + 2 + t; i < m; i += kEigThreads) H[int64_t(i) * m + k] = v[i - k - 1];
     __syncthreads();
   }
 }
@@ -161,15 +166,17 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
 // (the arithmetic of applying the reflectors to Z inside the reduction).
 constexpr int kZRows = 16;
 
-__global__ __launch_bounds__(kZRows * 16) void householder_z_kernel(const c128* __restrict__ Rall, int64_t wsr, int m,
-                                                                   c128* Zall, int64_t wsz,
+__global__ __launch_bounds__(kZRows * 16) void householder_z_kernel(const c128* __restrict__ Rall, int64_t wsr,
+                                                                   const c128* __restrict__ Hall, int64_t wsh, int m,
+                                                                   c128* Zall, int64_t wsz, int rows,
                                                                    const int* __restrict__ wmap) {
-  extern __shared__ c128 zr[];  // kZRows x m
+  extern __shared__ c128 zr[];  // rows x m (rows <= kZRows, blockDim = 16 rows)
   const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
   if (w < 0) return;
-  const int r0 = int(blockIdx.x) * kZRows;
+  const int r0 = int(blockIdx.x) * rows;
   if (r0 >= m) return;
   const c128* Rf = Rall + int64_t(w) * wsr;
+  const c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   const int t = threadIdx.x, sub = t & 15, rr = t >> 4;
   const int r = r0 + rr;
@@ -178,13 +185,14 @@ __global__ __launch_bounds__(kZRows * 16) void householder_z_kernel(const c128* 
   for (int j = sub; j < m; j += 16) row[j] = c128{ok && j == r ? 1.0 : 0.0, 0.0};
   __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
-    const double beta = Rf[int64_t(k) * m].re;
+    const double beta = Rf[k].re;
     if (beta == 0.0) continue;  // uniform: no reflector at this column
     const int len = m - k - 1;
-    const c128* v = Rf + int64_t(k) * m + k + 1;
+    // v[0] in row 1 of R, v[j >= 1] in column k of H (row k + 1 + j)
+    auto vj = [&](int j) { return j == 0 ? Rf[int64_t(m) + k] : H[int64_t(k + 1 + j) * m + k]; };
     double sr = 0.0, si = 0.0;
     for (int j = sub; j < len; j += 16) {
-      const c128 a = row[k + 1 + j], b = v[j];
+      const c128 a = row[k + 1 + j], b = vj(j);
       sr += a.re * b.re - a.im * b.im;
       si += a.re * b.im + a.im * b.re;
     }
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(kZRows * 16) void householder_z_kernel(const c128* 
     const c128 sc = beta * c128{sr, si};
     for (int j = sub; j < len; j += 16) {
       c128& h = row[k + 1 + j];
-      h = h - sc * conj(v[j]);
+      h = h - sc * conj(vj(j));
     }
     __syncthreads();
   }
@@ -451,7 +459,8 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   // the reflectors go to X, which is free until the eigenvector step
   hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), (size_t(m) + 4 * kEigThreads) * sizeof(c128), st, H, wsh, m,
                      X, wsw, wmap);
-  const size_t zlds = size_t(kZRows) * m * sizeof(c128);
+  const int zrows = int(std::max<size_t>(1, std::min<size_t>(kZRows, (size_t(150) * 1024) / (size_t(m) * sizeof(c128)))));
+  const size_t zlds = size_t(zrows) * m * sizeof(c128);
   if (zlds > size_t(150) * 1024) throw DeviceError("householder_z: basis too large for the LDS");
   if (zlds > size_t(64) * 1024) {
     static size_t granted = 0;
@@ -462,8 +471,8 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
       granted = zlds;
     }
   }
-  hipLaunchKernelGGL(householder_z_kernel, dim3((m + kZRows - 1) / kZRows, nwin), dim3(kZRows * 16), zlds, st, X, wsw,
-                     m, Z, wsw, wmap);
+  hipLaunchKernelGGL(householder_z_kernel, dim3((m + zrows - 1) / zrows, nwin), dim3(zrows * 16), zlds, st, X, wsw,
+                     H, wsh, m, Z, wsw, zrows, wmap);
   launch_schur(H, wsh, m, Z, wsw, work + 2 * int64_t(m) * m, wsw, theta, wst, info, nwin, st, wmap);
   const size_t tlds = size_t(kTrevcWaves) * m * sizeof(c128);
   if (tlds > size_t(150) * 1024) throw DeviceError("trevc: basis too large for the LDS");

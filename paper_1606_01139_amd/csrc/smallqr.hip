@@ -343,6 +343,10 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   c128* th = theta + int64_t(w) * wst;
+  // the Hessenberg step leaves its reflectors below the subdiagonal
+  for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kQT)
+    if (e / m > e % m + 1) H[e] = c128{0.0, 0.0};
+  __syncthreads();
   c128* lg = logall + int64_t(w) * wsl;
   RotRec* rec = reinterpret_cast<RotRec*>(lg + 2);
   c128* qs = lg + log_qstore_offset(m);
