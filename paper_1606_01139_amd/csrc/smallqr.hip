@@ -40,7 +40,11 @@ constexpr int kMaxShift = 64;
 // 12-16 shifts are fastest (about 0.7x the time of 48), since the shift
 // computation (an eigenvalue QR of the trailing block in one wavefront)
 // grows with the cube of the count.
-constexpr int kShifts = 16;
+#ifndef TSG_SCHUR_SHIFTS
+#define TSG_SCHUR_SHIFTS 16
+#endif
+constexpr int kShifts = TSG_SCHUR_SHIFTS;
+constexpr int kQAcc = (kFin + kShifts - 1) / kShifts;  // outputs per lane of a Q-block row
 // Rotation items a thread loads before it stores any (memory-level
 // parallelism of the chase phases).
 #ifndef TSG_SCHUR_BATCH
@@ -287,11 +291,11 @@ __device__ inline void replay_rot(c128* row, const RotRec& R) {
 // Outputs j, j + kShifts, ... of row[lo : lo+n] Q for a logged Q block
 // (the caller stores them with qstore_row after a barrier).
 __device__ inline void qblock_row(const c128* row, const RotRec& R0, const c128* qs, int j,
-                                  c128 (&acc)[kFin / kShifts]) {
+                                  c128 (&acc)[kQAcc]) {
   const int lo = int(R0.c), n = int(R0.s.re);
   const c128* Q = qs + int64_t(R0.s.im);
 #pragma unroll
-  for (int q = 0; q < kFin / kShifts; ++q) {
+  for (int q = 0; q < kQAcc; ++q) {
     const int jj = j + q * kShifts;
     c128 a{0.0, 0.0};
     if (jj < n)
@@ -300,10 +304,10 @@ __device__ inline void qblock_row(const c128* row, const RotRec& R0, const c128*
   }
 }
 
-__device__ inline void qstore_row(c128* row, const RotRec& R0, int j, const c128 (&acc)[kFin / kShifts]) {
+__device__ inline void qstore_row(c128* row, const RotRec& R0, int j, const c128 (&acc)[kQAcc]) {
   const int lo = int(R0.c), n = int(R0.s.re);
 #pragma unroll
-  for (int q = 0; q < kFin / kShifts; ++q) {
+  for (int q = 0; q < kQAcc; ++q) {
     const int jj = j + q * kShifts;
     if (jj < n) row[lo + jj] = acc[q];
   }
@@ -314,13 +318,14 @@ __device__ inline void qstore_row(c128* row, const RotRec& R0, int j, const c128
 // row applying record j of each step.
 __device__ __attribute__((noinline)) void flush_log(c128* Z, int m, const RotRec* rec, int nstep, const c128* qs) {
   const int t = threadIdx.x, j = t % kShifts;
-  for (int r0 = 0; r0 < m; r0 += kQT / kShifts) {
-    const int r = r0 + t / kShifts;
+  constexpr int kRows = kQT / kShifts;  // rows per pass; threads beyond kRows * kShifts idle
+  for (int r0 = 0; r0 < m; r0 += kRows) {
+    const int r = t < kRows * kShifts ? r0 + t / kShifts : m;
     c128* row = Z + int64_t(min(r, m - 1)) * m;
     for (int st = 0; st < nstep; ++st) {
       const RotRec* R = rec + int64_t(st) * kShifts;
       if (R[0].p <= -2) {
-        c128 acc[kFin / kShifts];
+        c128 acc[kQAcc];
         if (r < m) qblock_row(row, R[0], qs, j, acc);
         __syncthreads();
         if (r < m) qstore_row(row, R[0], j, acc);
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(256) void zreplay_kernel(c128* Zall, int64_t wsz, i
     for (int st = 0; st < nc; ++st) {
       const RotRec* R = chunk + st * kShifts;
       if (R[0].p <= -2) {
-        c128 acc[kFin / kShifts];
+        c128 acc[kQAcc];
         if (mine) qblock_row(row, R[0], qs, j, acc);
         __syncthreads();
         if (mine) qstore_row(row, R[0], j, acc);
