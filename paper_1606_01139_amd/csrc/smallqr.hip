@@ -339,8 +339,9 @@ __device__ __attribute__((noinline)) void flush_log(c128* Z, int m, const RotRec
 }
 
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
-                                                    c128* logall, int64_t wsl, c128* theta, int64_t wst, int* info,
-                                                    const int* __restrict__ wmap, int prof, int nshift_max) {
+                                                    c128* logall, int64_t wsl, int64_t cap, c128* theta, int64_t wst,
+                                                    int* info, const int* __restrict__ wmap, int prof,
+                                                    int nshift_max) {
   extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
   __shared__ QRShared S;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
@@ -355,7 +356,6 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   c128* lg = logall + int64_t(w) * wsl;
   RotRec* rec = reinterpret_cast<RotRec*>(lg + 2);
   c128* qs = lg + log_qstore_offset(m);
-  const int64_t cap = log_steps_cap(m);
   int nstep = 0, nq = 0;  // steps logged, Q store entries used: the same in every thread
   auto make_room = [&](int qneed) {
     if (nstep < cap && nq + qneed <= kQCap) return;
@@ -674,7 +674,14 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, 
     if (e != hipSuccess) throw DeviceError(std::string("schur: LDS attribute: ") + hipGetErrorString(e));
     attr_set = true;
   }
-  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, log, wsl,
+  // steps a log holds before the chase applies it to Z itself; the
+  // TSG_SCHUR_LOG_STEPS environment variable may lower it (for testing that path)
+  int64_t cap = log_steps_cap(m);
+  if (const char* e = std::getenv("TSG_SCHUR_LOG_STEPS")) {
+    const long v = std::atol(e);
+    if (v >= 1 && v < cap) cap = v;
+  }
+  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, log, wsl, cap,
                      theta, wst, info, wmap, prof, kShifts);
   // rows of Z per replay workgroup: as many as 150 KiB of LDS hold next to
   // the staged records, at most 256 / kShifts

@@ -114,3 +114,34 @@ def test_dense_eig_matches_lapack(torch_cuda, m, batch):
         R = H[b] @ Y[b] - Y[b] * th[b][None, :]
         assert np.abs(R).max() <= 1e-11 * max(nrm, 1.0)
         np.testing.assert_allclose(np.linalg.norm(Y[b], axis=0), 1.0, atol=1e-12)
+
+
+def test_dense_eig_log_flush_path_is_identical(torch_cuda, monkeypatch):
+    # The Schur chase logs its rotations and a second kernel applies them to
+    # the Schur vectors; when the log is full the chase applies it itself.
+    # With a 5-step log that path runs many times per matrix and must give
+    # the same eigenvalues and vectors, bit for bit (same operations, same
+    # order per element).
+    torch = torch_cuda
+    from paper_1606_01139_amd import dense_eig
+    rng = np.random.default_rng(5)
+    m, batch = 100, 2
+    Hs = []
+    for _ in range(batch):
+        X = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        Hs.append((X + X.conj().T) / 2 - 0.05j * (X @ X.conj().T) / m)
+    H = np.stack(Hs)
+    print("dense_eig with a 5-step rotation log", flush=True)
+    monkeypatch.delenv("TSG_SCHUR_LOG_STEPS", raising=False)
+    th0, Y0, info0 = dense_eig(torch.tensor(H, device="cuda"))
+    torch.cuda.synchronize()
+    monkeypatch.setenv("TSG_SCHUR_LOG_STEPS", "5")
+    th1, Y1, info1 = dense_eig(torch.tensor(H, device="cuda"))
+    torch.cuda.synchronize()
+    monkeypatch.delenv("TSG_SCHUR_LOG_STEPS")
+    assert (info0.cpu().numpy() == 0).all() and (info1.cpu().numpy() == 0).all()
+    assert np.array_equal(th0.cpu().numpy(), th1.cpu().numpy())
+    assert np.array_equal(Y0.cpu().numpy(), Y1.cpu().numpy())
+    for b in range(batch):
+        R = H[b] @ Y1[b].cpu().numpy() - Y1[b].cpu().numpy() * th1[b].cpu().numpy()[None, :]
+        assert np.abs(R).max() <= 1e-11 * max(np.linalg.norm(H[b], 2), 1.0)
