@@ -41,27 +41,35 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------- Hessenberg
-// Householder reduction H <- P^H H P to upper Hessenberg form.  Column
-// reductions (v^H H) run one thread per column; row reductions (H v) run
-// sixteen lanes per row so that every load is coalesced.  The reflectors
-// are kept, v_k[1..] in column k of H below the subdiagonal (free once the
-// column is reduced, so the working set stays one m x m matrix), beta_k and
-// v_k[0] in rows 0 and 1 of R; the product Z = P_0 P_1 ... is formed
-// afterwards by householder_z_kernel, many workgroups per matrix (each row
-// of Z is transformed independently), and the Schur step clears the stored
-// vectors from H.
+// Householder reduction H <- P^H H P to upper Hessenberg form.  One column
+// step applies P = I - beta v v^H from both sides in two sweeps over the
+// trailing columns (P H P = H - beta v y - beta z v^H with y = v^H H,
+// x = H v and z = x - beta (y v) v): the first sweep reads each element once
+// for both products (wavefronts take rows, lanes take columns, so every load
+// is coalesced; a lane keeps its columns' share of y and its columns' entries
+// of v in registers), the second applies the rank-2 update.  That is half
+// the matrix traffic of applying the two sides one after the other.  The
+// reflectors are kept, v_k[1..] in column k of H below the subdiagonal (free
+// once the column is reduced, so the working set stays one m x m matrix),
+// beta_k and v_k[0] in rows 0 and 1 of R; the product Z = P_0 P_1 ... is
+// formed afterwards by householder_z_kernel, many workgroups per matrix
+// (each row of Z is transformed independently), and the Schur step clears
+// the stored vectors from H.
+template <int NQ, int RPI>
 __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int64_t wsh, int m, c128* Rall,
                                                                  int64_t wsr, const int* __restrict__ wmap) {
-  extern __shared__ c128 sm[];  // v[m], then 4 x kEigThreads partial column sums
+  extern __shared__ c128 sm[];  // v[m], x[m], y[m], then NW x m partial y
   __shared__ double red[kEigThreads / 64];
+  constexpr int NW = kEigThreads / 64;
   c128* v = sm;
-  c128* pd = sm + m;
+  c128* xs = sm + m;
+  c128* ys = sm + 2 * m;
+  c128* yp = sm + 3 * m;
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
   c128* Rf = Rall + int64_t(w) * wsr;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  constexpr int NW = kEigThreads / 64;
   for (int k = 0; k + 2 < m; ++k) {
     const int len = m - k - 1;  // rows k+1 .. m-1
     double part = 0.0;
@@ -87,71 +95,108 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
       Rf[k] = c128{beta, 0.0};
       Rf[int64_t(m) + k] = v[0];
     }
-    // left: H[k+1.., j] -= beta v (v^H H[k+1.., j]) for j >= k; each column
-    // is split over P row ranges (P threads per column, partial sums in LDS)
-    {
-      const int ncols = m - k;
-      const int P = max(1, min(4, kEigThreads / ncols));
-      const int col = k + t % ncols, part = t / ncols;
-      const bool act = part < P;
-      const int r0 = act ? (part * len) / P : 0, r1 = act ? ((part + 1) * len) / P : 0;
-      c128 sacc{0.0, 0.0};
-      if (act) {
-#pragma unroll 8
-        for (int i = r0; i < r1; ++i) fma_cacc(sacc, v[i], H[int64_t(k + 1 + i) * m + col]);
-        pd[part * kEigThreads + (col - k)] = sacc;
-      }
-      __syncthreads();
-      if (act) {
-        c128 tot{0.0, 0.0};
-        for (int q = 0; q < P; ++q) tot = tot + pd[q * kEigThreads + (col - k)];
-        tot = beta * tot;
-#pragma unroll 8
-        for (int i = r0; i < r1; ++i) {
-          c128& h = H[int64_t(k + 1 + i) * m + col];
-          h = h - v[i] * tot;
+    const int ncols = m - k;  // columns k .. m-1 (column k + jj)
+    // this lane's entries of v along the columns (v_e,j = v[jj - 1], jj >= 1)
+    c128 vq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int jj = lane + 64 * q;
+      vq[q] = (jj >= 1 && jj < ncols) ? v[jj - 1] : c128{0.0, 0.0};
+    }
+    // sweep 1: x_i = sum_{j>k} H[i][j] v_e,j (all rows), y_j = sum_{i>k}
+    // conj(v_e,i) H[i][j] (columns j >= k)
+    c128 yacc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) yacc[q] = c128{0.0, 0.0};
+    for (int i0 = wv * RPI; i0 < m; i0 += NW * RPI) {
+      c128 a[RPI][NQ];
+#pragma unroll
+      for (int r = 0; r < RPI; ++r) {
+        const int i = i0 + r;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int jj = lane + 64 * q;
+          a[r][q] = (i < m && jj < ncols) ? H[int64_t(i) * m + k + jj] : c128{0.0, 0.0};
         }
       }
-      // columns beyond what one pass of threads covers (ncols > kEigThreads)
-      for (int j = k + kEigThreads + t; j < m && P == 1; j += kEigThreads) {
-        c128 sa{0.0, 0.0};
-#pragma unroll 8
-        for (int i = 0; i < len; ++i) fma_cacc(sa, v[i], H[int64_t(k + 1 + i) * m + j]);
-        sa = beta * sa;
-#pragma unroll 8
-        for (int i = 0; i < len; ++i) {
-          c128& h = H[int64_t(k + 1 + i) * m + j];
-          h = h - v[i] * sa;
+#pragma unroll
+      for (int r = 0; r < RPI; ++r) {
+        const int i = i0 + r;
+        c128 xr{0.0, 0.0};
+        const c128 vi = (i > k && i < m) ? conj(v[i - k - 1]) : c128{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          fma_acc(xr, a[r][q], vq[q]);
+          fma_acc(yacc[q], vi, a[r][q]);
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          xr.re += __shfl_xor(xr.re, o, 64);
+          xr.im += __shfl_xor(xr.im, o, 64);
+        }
+        if (lane == 0 && i < m) xs[i] = xr;
       }
     }
-    __syncthreads();
-    // right: row r of H: row[k+1..] -= beta (row[k+1..] v) v^H; four rows
-    // per wavefront, 16 lanes per row
-    {
-      const int sub = lane & 15, rsel = lane >> 4;
-      for (int r0 = wv * 4; r0 < m; r0 += NW * 4) {
-        const int r = r0 + rsel;
-        const bool ok = r < m;
-        c128* row = H + int64_t(ok ? r : 0) * m;
-        double sr = 0.0, si = 0.0;
-        if (ok)
-          for (int j = sub; j < len; j += 16) {
-            const c128 a = row[k + 1 + j], b = v[j];
-            sr += a.re * b.re - a.im * b.im;
-            si += a.re * b.im + a.im * b.re;
-          }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          sr += __shfl_xor(sr, o, 16);
-          si += __shfl_xor(si, o, 16);
+    for (int q = 0; q < NQ; ++q) {
+      const int jj = lane + 64 * q;
+      if (jj < ncols) yp[wv * m + jj] = yacc[q];
+    }
+    __syncthreads();
+    // y (column sums over the wavefronts' partials) and s = y v_e
+    double pr = 0.0, pi = 0.0;
+    for (int jj = t; jj < ncols; jj += kEigThreads) {
+      c128 y{0.0, 0.0};
+      for (int q = 0; q < NW; ++q) y = y + yp[q * m + jj];
+      ys[jj] = beta * y;
+      if (jj >= 1) {
+        const c128 vj = v[jj - 1];
+        pr += y.re * vj.re - y.im * vj.im;
+        pi += y.re * vj.im + y.im * vj.re;
+      }
+    }
+    const double s_re = block_sum(pr, red), s_im = block_sum(pi, red);
+    // z_i = beta (x_i - beta s v_e,i), over x
+    for (int i = t; i < m; i += kEigThreads) {
+      c128 z = xs[i];
+      if (i > k) z = z - beta * (c128{s_re, s_im} * v[i - k - 1]);
+      xs[i] = beta * z;
+    }
+    __syncthreads();
+    // sweep 2: H[i][j] -= v_e,i (beta y_j) + (beta z_i) conj(v_e,j)
+    c128 yq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int jj = lane + 64 * q;
+      yq[q] = jj < ncols ? ys[jj] : c128{0.0, 0.0};
+      vq[q] = conj(vq[q]);
+    }
+    for (int i0 = wv * RPI; i0 < m; i0 += NW * RPI) {
+      c128 a[RPI][NQ];
+#pragma unroll
+      for (int r = 0; r < RPI; ++r) {
+        const int i = i0 + r;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int jj = lane + 64 * q;
+          a[r][q] = (i < m && jj < ncols) ? H[int64_t(i) * m + k + jj] : c128{0.0, 0.0};
         }
-        const c128 sc = beta * c128{sr, si};
-        if (ok)
-          for (int j = sub; j < len; j += 16) {
-            c128& h = row[k + 1 + j];
-            h = h - sc * conj(v[j]);
-          }
+      }
+#pragma unroll
+      for (int r = 0; r < RPI; ++r) {
+        const int i = i0 + r;
+        if (i >= m) continue;
+        const c128 vi = i > k ? v[i - k - 1] : c128{0.0, 0.0};
+        const c128 zi = xs[i];
+        const c128 nvi{-vi.re, -vi.im}, nzi{-zi.re, -zi.im};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int jj = lane + 64 * q;
+          c128 val = a[r][q];
+          fma_acc(val, nvi, yq[q]);
+          fma_acc(val, nzi, vq[q]);
+          if (jj < ncols) H[int64_t(i) * m + k + jj] = val;
+        }
       }
     }
     __syncthreads();
@@ -456,9 +501,27 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   if (nwin <= 0 || m <= 0) return;
   c128* Z = work;               // m*m per window at stride wsw
   c128* X = work + int64_t(m) * m;
-  // the reflectors go to X, which is free until the eigenvector step
-  hipLaunchKernelGGL(hessenberg_kernel, dim3(nwin), dim3(kEigThreads), (size_t(m) + 4 * kEigThreads) * sizeof(c128), st, H, wsh, m,
-                     X, wsw, wmap);
+  // the reflectors' scalars go to X, which is free until the eigenvector step
+  const size_t hlds = size_t(3 + kEigThreads / 64) * m * sizeof(c128);
+  if (hlds > size_t(150) * 1024) throw DeviceError("hessenberg: basis too large for the LDS");
+  auto hess = [&](auto kern) {
+    if (hlds > size_t(64) * 1024) {
+      static size_t granted = 0;
+      if (hlds > granted) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(hlds));
+        if (e != hipSuccess) throw DeviceError(std::string("hessenberg: LDS attribute: ") + hipGetErrorString(e));
+        granted = hlds;
+      }
+    }
+    hipLaunchKernelGGL(kern, dim3(nwin), dim3(kEigThreads), hlds, st, H, wsh, m, X, wsw, wmap);
+  };
+  if (m <= 8 * 64)
+    hess(hessenberg_kernel<8, 2>);
+  else if (m <= 14 * 64)
+    hess(hessenberg_kernel<14, 1>);
+  else
+    throw DeviceError("hessenberg: basis too large");
   const int zrows = int(std::max<size_t>(1, std::min<size_t>(kZRows, (size_t(150) * 1024) / (size_t(m) * sizeof(c128)))));
   const size_t zlds = size_t(zrows) * m * sizeof(c128);
   if (zlds > size_t(150) * 1024) throw DeviceError("householder_z: basis too large for the LDS");

@@ -83,7 +83,7 @@ def test_stencil_c64_matches_oracle(torch_cuda, shape, B):
     assert np.abs(Y - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("m,batch", [(1, 1), (2, 2), (8, 3), (37, 2), (128, 2), (304, 1)])
+@pytest.mark.parametrize("m,batch", [(1, 1), (2, 2), (8, 3), (37, 2), (128, 2), (304, 1), (600, 1)])
 def test_dense_eig_matches_lapack(torch_cuda, m, batch):
     torch = torch_cuda
     from paper_1606_01139_amd import dense_eig
