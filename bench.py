@@ -121,7 +121,7 @@ def k4_flops(m):
     return 4.0 * (10.0 / 3.0 + 4.0 / 3.0 + 25.0) * m ** 3
 
 
-K4_TRAFFIC_C2 = 6_063_573_013
+K4_TRAFFIC_C2 = 20_963_053_642
 
 
 def auto_basis(nev, block=2):
@@ -166,8 +166,9 @@ def k4_roofline(m, batch, reps=3):
     traffic = K4_TRAFFIC_C2 if (m, batch) == (450, 8) else None
     return {"bound": "alu", "achieved": round(tf, 5), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
-            "kernel": "K4 small eigensolve: hessenberg_kernel + schur_kernel + trevc_kernel + small_gemm_kernel "
-                      "+ colnorm_kernel (one workgroup per window)",
+            "kernel": "K4 small eigensolve: hess_slab_p/u_kernel (Hessenberg, row slabs over several "
+                      "workgroups per window; hessenberg_kernel below m = 192) + householder_z_kernel + "
+                      "schur_kernel + zreplay_kernel + trevc_kernel + small_gemm_kernel + colnorm_kernel",
             "launch": f"{batch} windows x {m}x{m} complex128", "avg_ms": round(avg, 3),
             "algorithmic_flops": fl}
 

@@ -18,6 +18,10 @@ namespace {
 
 constexpr int kEigThreads = 512;
 constexpr int kSB = 8;  // column block of the restart-basis orthonormalisation
+// Bases from this size on take the Hessenberg reduction over several
+// workgroups per matrix (row slabs of about 32 rows, at most kMaxSlabs).
+constexpr int kSlabMinBasis = 192;
+constexpr int kMaxSlabs = 16;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -203,6 +207,198 @@ __global__ __launch_bounds__(kEigThreads) void hessenberg_kernel(c128* Hall, int
     for (int i = k + 2 + t; i < m; i += kEigThreads) H[int64_t(i) * m + k] = v[i - k - 1];
     __syncthreads();
   }
+}
+
+// The same reduction for larger bases, spread over several workgroups per
+// matrix: the rows are cut into slabs, one workgroup each, and every column
+// step is two launches (the launch boundary orders the slabs' accesses).
+//   hess_slab_p: every workgroup forms the reflector from column k itself;
+//     the first slab stores beta, v[0] and v; then each workgroup runs the
+//     first sweep over its rows (x complete for its rows, a partial y).
+//   hess_slab_u: each workgroup sums the partial ys, forms s and z for its
+//     rows and applies the rank-2 update to them, then stores its share of
+//     v below the subdiagonal of column k.
+// Scratch in X beside the reflectors' scalars (rows 0 and 1): v in row 2, x
+// in row 3, the partial ys in rows 4 .. 4 + nslab - 1.  With the grid laid
+// out (window, slab), a window's slabs fall on one XCD when eight windows are
+// batched, so its matrix stays in one L2.
+template <int NQ, int RPI>
+__global__ __launch_bounds__(kEigThreads) void hess_slab_p_kernel(const c128* Hall, int64_t wsh, int m, c128* Rall,
+                                                                  int64_t wsr, int k, int rows,
+                                                                  const int* __restrict__ wmap) {
+  extern __shared__ c128 sm[];  // v[m], then NW x m partial y
+  __shared__ double red[kEigThreads / 64];
+  constexpr int NW = kEigThreads / 64;
+  c128* v = sm;
+  c128* yp = sm + m;
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int sl = int(blockIdx.y);
+  const int r0 = sl * rows, r1 = min(m, r0 + rows);
+  const c128* H = Hall + int64_t(w) * wsh;
+  c128* Rf = Rall + int64_t(w) * wsr;
+  c128* vbuf = Rf + 2 * int64_t(m);
+  c128* xbuf = Rf + 3 * int64_t(m);
+  c128* ypart = Rf + int64_t(4 + sl) * m;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int len = m - k - 1;  // rows k+1 .. m-1
+  double part = 0.0;
+  for (int i = t; i < len; i += kEigThreads) {
+    const c128 x = H[int64_t(k + 1 + i) * m + k];
+    v[i] = x;
+    part += norm2(x);
+  }
+  const double alpha2 = block_sum(part, red);
+  const c128 x0 = v[0];
+  __syncthreads();  // every thread has read v[0] before it is rewritten
+  const double ax0 = cabs(x0);
+  const double alpha = sqrt(alpha2);
+  if (alpha == 0.0 || alpha2 - ax0 * ax0 <= 1e-300 * (alpha2 > 0 ? alpha2 : 1.0)) {
+    if (sl == 0 && t == 0) Rf[k] = c128{0.0, 0.0};  // no reflector: beta = 0
+    return;
+  }
+  const c128 ph = ax0 > 0.0 ? c128{x0.re / ax0, x0.im / ax0} : c128{1.0, 0.0};
+  if (t == 0) v[0] = x0 + alpha * ph;
+  __syncthreads();
+  const double beta = 1.0 / (alpha * (alpha + ax0));  // 2 / |v|^2
+  if (sl == 0) {
+    if (t == 0) {
+      Rf[k] = c128{beta, 0.0};
+      Rf[int64_t(m) + k] = v[0];
+    }
+    for (int i = t; i < len; i += kEigThreads) vbuf[i] = v[i];
+  }
+  const int ncols = m - k;  // columns k .. m-1 (column k + jj)
+  c128 vq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jj = lane + 64 * q;
+    vq[q] = (jj >= 1 && jj < ncols) ? v[jj - 1] : c128{0.0, 0.0};
+  }
+  c128 yacc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) yacc[q] = c128{0.0, 0.0};
+  for (int i0 = r0 + wv * RPI; i0 < r1; i0 += NW * RPI) {
+    c128 a[RPI][NQ];
+#pragma unroll
+    for (int r = 0; r < RPI; ++r) {
+      const int i = i0 + r;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int jj = lane + 64 * q;
+        a[r][q] = (i < r1 && jj < ncols) ? H[int64_t(i) * m + k + jj] : c128{0.0, 0.0};
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPI; ++r) {
+      const int i = i0 + r;
+      c128 xr{0.0, 0.0};
+      const c128 vi = (i > k && i < r1) ? conj(v[i - k - 1]) : c128{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        fma_acc(xr, a[r][q], vq[q]);
+        fma_acc(yacc[q], vi, a[r][q]);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        xr.re += __shfl_xor(xr.re, o, 64);
+        xr.im += __shfl_xor(xr.im, o, 64);
+      }
+      if (lane == 0 && i < r1) xbuf[i] = xr;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jj = lane + 64 * q;
+    if (jj < ncols) yp[wv * m + jj] = yacc[q];
+  }
+  __syncthreads();
+  for (int jj = t; jj < ncols; jj += kEigThreads) {
+    c128 y{0.0, 0.0};
+    for (int q = 0; q < NW; ++q) y = y + yp[q * m + jj];
+    ypart[jj] = y;
+  }
+}
+
+template <int NQ, int RPI>
+__global__ __launch_bounds__(kEigThreads) void hess_slab_u_kernel(c128* Hall, int64_t wsh, int m,
+                                                                  const c128* __restrict__ Rall, int64_t wsr, int k,
+                                                                  int rows, int nslab, const int* __restrict__ wmap) {
+  extern __shared__ c128 sm[];  // v[m], beta y[m], beta z[rows]
+  __shared__ double red[kEigThreads / 64];
+  constexpr int NW = kEigThreads / 64;
+  c128* v = sm;
+  c128* ys = sm + m;
+  c128* zs = sm + 2 * m;
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;  // idle slot (whole workgroup)
+  const int sl = int(blockIdx.y);
+  const int r0 = sl * rows, r1 = min(m, r0 + rows);
+  c128* H = Hall + int64_t(w) * wsh;
+  const c128* Rf = Rall + int64_t(w) * wsr;
+  const double beta = Rf[k].re;
+  if (beta == 0.0) return;  // uniform: no reflector at this column
+  const c128* vbuf = Rf + 2 * int64_t(m);
+  const c128* xbuf = Rf + 3 * int64_t(m);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int len = m - k - 1, ncols = m - k;
+  for (int i = t; i < len; i += kEigThreads) v[i] = vbuf[i];
+  // y (sum of the slabs' partials) and s = y v_e
+  double pr = 0.0, pi = 0.0;
+  for (int jj = t; jj < ncols; jj += kEigThreads) {
+    c128 y{0.0, 0.0};
+    for (int q = 0; q < nslab; ++q) y = y + Rf[int64_t(4 + q) * m + jj];
+    ys[jj] = beta * y;
+    if (jj >= 1) {
+      const c128 vj = vbuf[jj - 1];
+      pr += y.re * vj.re - y.im * vj.im;
+      pi += y.re * vj.im + y.im * vj.re;
+    }
+  }
+  const double s_re = block_sum(pr, red), s_im = block_sum(pi, red);  // also orders v and ys
+  for (int i = r0 + t; i < r1; i += kEigThreads) {
+    c128 z = xbuf[i];
+    if (i > k) z = z - beta * (c128{s_re, s_im} * v[i - k - 1]);
+    zs[i - r0] = beta * z;
+  }
+  __syncthreads();
+  c128 yq[NQ], vq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jj = lane + 64 * q;
+    yq[q] = jj < ncols ? ys[jj] : c128{0.0, 0.0};
+    vq[q] = (jj >= 1 && jj < ncols) ? conj(v[jj - 1]) : c128{0.0, 0.0};
+  }
+  for (int i0 = r0 + wv * RPI; i0 < r1; i0 += NW * RPI) {
+    c128 a[RPI][NQ];
+#pragma unroll
+    for (int r = 0; r < RPI; ++r) {
+      const int i = i0 + r;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int jj = lane + 64 * q;
+        a[r][q] = (i < r1 && jj < ncols) ? H[int64_t(i) * m + k + jj] : c128{0.0, 0.0};
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPI; ++r) {
+      const int i = i0 + r;
+      if (i >= r1) continue;
+      const c128 vi = i > k ? v[i - k - 1] : c128{0.0, 0.0};
+      const c128 zi = zs[i - r0];
+      const c128 nvi{-vi.re, -vi.im}, nzi{-zi.re, -zi.im};
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int jj = lane + 64 * q;
+        c128 val = a[r][q];
+        fma_acc(val, nvi, yq[q]);
+        fma_acc(val, nzi, vq[q]);
+        if (jj < ncols) H[int64_t(i) * m + k + jj] = val;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = max(k + 2, r0) + t; i < r1; i += kEigThreads) H[int64_t(i) * m + k] = v[i - k - 1];
 }
 
 // Z = P_0 P_1 ... P_{m-3} from the reflectors R of hessenberg_kernel, rows
@@ -516,12 +712,42 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
     }
     hipLaunchKernelGGL(kern, dim3(nwin), dim3(kEigThreads), hlds, st, H, wsh, m, X, wsw, wmap);
   };
-  if (m <= 8 * 64)
-    hess(hessenberg_kernel<8, 2>);
-  else if (m <= 14 * 64)
-    hess(hessenberg_kernel<14, 1>);
-  else
-    throw DeviceError("hessenberg: basis too large");
+  if (m > 14 * 64) throw DeviceError("hessenberg: basis too large");
+  if (m < kSlabMinBasis) {
+    if (m <= 8 * 64)
+      hess(hessenberg_kernel<8, 2>);
+    else
+      hess(hessenberg_kernel<14, 1>);
+  } else {
+    // about 32 rows per slab, at most kMaxSlabs slabs
+    int nslab = std::min(kMaxSlabs, (m + 31) / 32);
+    const int rows = (m + nslab - 1) / nslab;
+    nslab = (m + rows - 1) / rows;
+    if (int64_t(4 + nslab) * m > int64_t(m) * m) throw DeviceError("hessenberg: scratch does not fit in X");
+    const size_t plds = size_t(1 + kEigThreads / 64) * m * sizeof(c128);
+    const size_t ulds = size_t(2 * m + rows) * sizeof(c128);
+    if (plds > size_t(150) * 1024) throw DeviceError("hessenberg: basis too large for the LDS");
+    auto slabs = [&](auto pk, auto uk) {
+      if (plds > size_t(64) * 1024) {
+        static size_t granted = 0;
+        if (plds > granted) {
+          const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pk),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(plds));
+          if (e != hipSuccess) throw DeviceError(std::string("hessenberg: LDS attribute: ") + hipGetErrorString(e));
+          granted = plds;
+        }
+      }
+      const dim3 grid{unsigned(nwin), unsigned(nslab), 1u};
+      for (int k = 0; k + 2 < m; ++k) {
+        hipLaunchKernelGGL(pk, grid, dim3(kEigThreads), plds, st, H, wsh, m, X, wsw, k, rows, wmap);
+        hipLaunchKernelGGL(uk, grid, dim3(kEigThreads), ulds, st, H, wsh, m, X, wsw, k, rows, nslab, wmap);
+      }
+    };
+    if (m <= 8 * 64)
+      slabs(hess_slab_p_kernel<8, 2>, hess_slab_u_kernel<8, 2>);
+    else
+      slabs(hess_slab_p_kernel<14, 1>, hess_slab_u_kernel<14, 1>);
+  }
   const int zrows = int(std::max<size_t>(1, std::min<size_t>(kZRows, (size_t(150) * 1024) / (size_t(m) * sizeof(c128)))));
   const size_t zlds = size_t(zrows) * m * sizeof(c128);
   if (zlds > size_t(150) * 1024) throw DeviceError("householder_z: basis too large for the LDS");
