@@ -126,6 +126,9 @@ struct QRShared {
   double bc[kMaxShift];
   c128 bs[kMaxShift];
   int bp[kMaxShift];
+  // column p of rows p+1 and p+2 after bulge j's right rotation at p: the
+  // two values its next rotation is built from
+  c128 fx[kMaxShift], fy[kMaxShift];
 };
 
 // Single-shift QR on the n x n block B (LDS, row-major) until all its
@@ -485,8 +488,10 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
             x = H[int64_t(lo) * m + lo] - S.shift[t];
             y = H[int64_t(lo + 1) * m + lo];
           } else {
-            x = H[int64_t(p) * m + p - 1];
-            y = H[int64_t(p + 1) * m + p - 1];
+            // H[p][p-1] and H[p+1][p-1], forwarded by the previous step's
+            // right phase (the same values it stored to H)
+            x = S.fx[t];
+            y = S.fy[t];
           }
           double c; c128 s;
           givens(x, y, c, s);
@@ -567,7 +572,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
           // the batch's loads are all in flight before the first is used
           c128 av[kBatch], bv[kBatch];
           c128* ap[kBatch];
-          int pr[kBatch];
+          int pr[kBatch];  // bulge + kMaxShift * (r - p if 1 or 2, else 0); -1: skipped
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
@@ -576,7 +581,8 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
             const int j = in ? ja + idx % nact : ja;
             const int p = in ? S.bp[j] : -1;
             const bool ok = p >= 0 && r <= min(p + 2, ihi);
-            pr[q] = ok ? j : -1;
+            const int fwd = (r - p == 1 || r - p == 2) ? r - p : 0;
+            pr[q] = ok ? j + kMaxShift * fwd : -1;
             ap[q] = ok ? H + int64_t(r) * m + p : H;
             av[q] = ap[q][0];
             bv[q] = ap[q][1];
@@ -584,11 +590,14 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
 #pragma unroll
           for (int q = 0; q < kBatch; ++q) {
             if (pr[q] < 0) continue;
-            const int j = pr[q];
+            const int j = pr[q] % kMaxShift, fwd = pr[q] / kMaxShift;
             const double c = S.bc[j];
             const c128 sj = S.bs[j];
-            ap[q][0] = c * av[q] + conj(sj) * bv[q];
+            const c128 n0 = c * av[q] + conj(sj) * bv[q];
+            ap[q][0] = n0;
             ap[q][1] = c * bv[q] - sj * av[q];
+            if (fwd == 1) S.fx[j] = n0;
+            else if (fwd == 2) S.fy[j] = n0;
           }
         }
       }
