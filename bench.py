@@ -121,7 +121,7 @@ def k4_flops(m):
     return 4.0 * (10.0 / 3.0 + 4.0 / 3.0 + 25.0) * m ** 3
 
 
-K4_TRAFFIC_C2 = 20_963_053_642
+K4_TRAFFIC_C2 = 20_964_223_232
 
 
 def auto_basis(nev, block=2):
