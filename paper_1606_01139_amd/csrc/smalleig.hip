@@ -19,9 +19,17 @@ namespace {
 constexpr int kEigThreads = 512;
 constexpr int kSB = 8;  // column block of the restart-basis orthonormalisation
 // Bases from this size on take the Hessenberg reduction over several
-// workgroups per matrix (row slabs of about 32 rows, at most kMaxSlabs).
+// workgroups per matrix (row slabs of about kSlabRows rows, at most
+// kMaxSlabs).
 constexpr int kSlabMinBasis = 192;
-constexpr int kMaxSlabs = 16;
+#ifndef TSG_HESS_SLAB_ROWS
+#define TSG_HESS_SLAB_ROWS 32
+#endif
+#ifndef TSG_HESS_MAX_SLABS
+#define TSG_HESS_MAX_SLABS 16
+#endif
+constexpr int kSlabRows = TSG_HESS_SLAB_ROWS;
+constexpr int kMaxSlabs = TSG_HESS_MAX_SLABS;
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -719,8 +727,8 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
     else
       hess(hessenberg_kernel<14, 1>);
   } else {
-    // about 32 rows per slab, at most kMaxSlabs slabs
-    int nslab = std::min(kMaxSlabs, (m + 31) / 32);
+    // about kSlabRows rows per slab, at most kMaxSlabs slabs
+    int nslab = std::min(kMaxSlabs, (m + kSlabRows - 1) / kSlabRows);
     const int rows = (m + nslab - 1) / nslab;
     nslab = (m + rows - 1) / rows;
     if (int64_t(4 + nslab) * m > int64_t(m) * m) throw DeviceError("hessenberg: scratch does not fit in X");
