@@ -277,11 +277,12 @@ tsg_status tsg_apply_operator(tsg_ctx* ctx, const void* X, void* Y, int32_t ncol
 
 /* Dense eigen-decomposition of `batch` general complex m x m matrices (the
  * small Rayleigh-Ritz problem inside each window iteration).  H: device,
- * batch row-major m x m complex128 matrices, overwritten; theta: device,
- * batch*m complex128 eigenvalues; Y: device, batch row-major m x m, unit
- * 2-norm eigenvector columns; info: device, batch int32 (0 = converged).
- * hip_stream as in tsg_build_operator.  Errors: TSG_EINVAL, TSG_ENOMEM,
- * TSG_EDEVICE. */
+ * batch row-major m x m complex128 matrices, 1 <= m <= 896, overwritten;
+ * theta: device, batch*m complex128 eigenvalues; Y: device, batch row-major
+ * m x m, unit 2-norm eigenvector columns; info: device, batch int32
+ * (0 = converged).
+ * hip_stream as in tsg_build_operator.  Errors: TSG_EINVAL (null pointer,
+ * m or batch out of range; nothing launched), TSG_ENOMEM, TSG_EDEVICE. */
 tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info, void* hip_stream);
 
 /* Message for the last failed call on ctx (or for the last failed call

@@ -1345,6 +1345,7 @@ int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, doubl
 void dense_eig(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st) {
   if (!H || !theta || !Y || !info) throw InvalidArg("null device pointer");
   if (m < 1 || batch < 1) throw InvalidArg("need m >= 1 and batch >= 1");
+  if (m > kMaxDenseBasis) throw InvalidArg("m exceeds the largest supported matrix (896)");
   DevArr<c128> work;
   work.alloc(size_t(smalleig_workspace(m)) * batch);
   smalleig(static_cast<c128*>(H), int64_t(m) * m, m, static_cast<c128*>(theta), m, static_cast<c128*>(Y),

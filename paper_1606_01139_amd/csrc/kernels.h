@@ -125,9 +125,12 @@ void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, in
 
 // ---------------------------------------------------------------- K4
 // Eigen-decomposition of general complex m x m matrices, one workgroup per
-// window.  H (row-major, ld m) is overwritten; theta gets the eigenvalues and
-// Y (row-major m x m) the unit-2-norm right eigenvectors (columns).
-// work must hold smalleig_workspace(m) c128 per window.
+// window for the sequential parts.  H (row-major, ld m) is overwritten; theta
+// gets the eigenvalues and Y (row-major m x m) the unit-2-norm right
+// eigenvectors (columns).  work must hold smalleig_workspace(m) c128 per
+// window.  m is at most kMaxDenseBasis (a Hessenberg row must fit the
+// registers of one wavefront, 14 values per lane).
+constexpr int kMaxDenseBasis = 14 * 64;
 void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, int64_t wsy, c128* work,
               int64_t wsw, int* info, int nwin, hipStream_t st, const int* wmap = nullptr);
 int64_t smalleig_workspace(int m);

@@ -720,7 +720,7 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
     }
     hipLaunchKernelGGL(kern, dim3(nwin), dim3(kEigThreads), hlds, st, H, wsh, m, X, wsw, wmap);
   };
-  if (m > 14 * 64) throw DeviceError("hessenberg: basis too large");
+  if (m > kMaxDenseBasis) throw DeviceError("hessenberg: basis too large");
   if (m < kSlabMinBasis) {
     if (m <= 8 * 64)
       hess(hessenberg_kernel<8, 2>);

@@ -116,6 +116,20 @@ def test_dense_eig_matches_lapack(torch_cuda, m, batch):
         np.testing.assert_allclose(np.linalg.norm(Y[b], axis=0), 1.0, atol=1e-12)
 
 
+def test_dense_eig_rejects_basis_above_maximum(torch_cuda):
+    # A Hessenberg row must fit one wavefront's registers (14 values per
+    # lane, m <= 896); a larger m is refused on the host before any launch.
+    torch = torch_cuda
+    from paper_1606_01139_amd import TsgError, dense_eig
+    from paper_1606_01139_amd.binding import STATUS_NAMES
+    print("dense_eig m=897 (rejected on the host)", flush=True)
+    H = torch.zeros((1, 897, 897), dtype=torch.complex128, device="cuda")
+    with pytest.raises(TsgError) as err:
+        dense_eig(H)
+    assert STATUS_NAMES[err.value.status] == "TSG_EINVAL"
+    assert "896" in str(err.value)
+
+
 def test_dense_eig_log_flush_path_is_identical(torch_cuda, monkeypatch):
     # The Schur chase logs its rotations and a second kernel applies them to
     # the Schur vectors; when the log is full the chase applies it itself.
