@@ -18,8 +18,9 @@ namespace tsg {
 
 namespace {
 
-constexpr int kGT = 32;   // gram tile (rows and columns of C)
-constexpr int kGK = 32;   // grid rows of X, Y staged per step
+constexpr int kGT = 64;   // gram tile (rows and columns of C)
+constexpr int kGK = 16;   // grid rows of X, Y staged per step
+constexpr int kGR = kGT / 16;  // outputs per thread along each tile axis
 
 inline int gram_chunks(int64_t N, int r, int s, int nwin) {
   const int64_t tiles = int64_t((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT) * nwin;
@@ -58,11 +59,15 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __res
   const int i0 = ti * kGT, j0 = tj * kGT;
   X += int64_t(w) * wsx;
   Y += int64_t(w) * wsy;
-  c128 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = c128{0.0, 0.0};
+  // thread (tx, ty) owns C[i0 + ty + 16 a][j0 + tx + 16 b]: per staged row,
+  // kGR + kGR LDS reads feed kGR * kGR complex multiply-adds
+  c128 acc[kGR][kGR];
+#pragma unroll
+  for (int a = 0; a < kGR; ++a)
+#pragma unroll
+    for (int b = 0; b < kGR; ++b) acc[a][b] = c128{0.0, 0.0};
   for (int64_t nb = n0; nb < n1; nb += kGK) {
-    // stage kGK rows of 32 columns of X and Y; consecutive threads read
+    // stage kGK rows of kGT columns of X and Y; consecutive threads read
     // consecutive rows of one column
     for (int e = t; e < kGK * kGT; e += 256) {
       const int cc = e / kGK, rr = e % kGK;
@@ -76,21 +81,26 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __res
       Ys[rr][cc] = yv;
     }
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
     for (int k = 0; k < kGK; ++k) {
-      c128 x0 = Xs[k][2 * ty], x1 = Xs[k][2 * ty + 1];
-      c128 y0 = Ys[k][2 * tx], y1 = Ys[k][2 * tx + 1];
-      fma_cacc(acc[0][0], x0, y0);
-      fma_cacc(acc[0][1], x0, y1);
-      fma_cacc(acc[1][0], x1, y0);
-      fma_cacc(acc[1][1], x1, y1);
+      c128 xv[kGR], yv[kGR];
+#pragma unroll
+      for (int a = 0; a < kGR; ++a) xv[a] = Xs[k][ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < kGR; ++b) yv[b] = Ys[k][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < kGR; ++a)
+#pragma unroll
+        for (int b = 0; b < kGR; ++b) fma_cacc(acc[a][b], xv[a], yv[b]);
     }
     __syncthreads();
   }
   c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int i = i0 + 2 * ty + a, j = j0 + 2 * tx + b;
+#pragma unroll
+  for (int a = 0; a < kGR; ++a)
+#pragma unroll
+    for (int b = 0; b < kGR; ++b) {
+      const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
       if (i < r && j < s) Pw[int64_t(i) * s + j] = acc[a][b];
     }
 }
