@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kEigThreads = 512;
 constexpr int kSB = 8;  // column block of the restart-basis orthonormalisation
+constexpr int kSelThreads = 512;  // threads of select_restart_kernel (a power of two)
 // Bases from this size on take the Hessenberg reduction over several
 // workgroups per matrix (row slabs of about kSlabRows rows, at most
 // kMaxSlabs).
@@ -567,7 +568,7 @@ __device__ inline double sel_key(c128 th, double sigma, int mode) {
   return cabs(c128{th.re - sigma, th.im});  // nearest the shift
 }
 
-__global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, int64_t wst, const c128* Yall,
+__global__ __launch_bounds__(kSelThreads) void select_restart_kernel(const c128* thall, int64_t wst, const c128* Yall,
                                                              int64_t wsy, int m, const double* sigma, int mode, int k,
                                                              int nev, c128* outall, int64_t wso, c128* thsel,
                                                              int64_t wss, const int* __restrict__ wmap) {
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
   int* order = reinterpret_cast<int*>(smraw);                       // m
   c128* coef = reinterpret_cast<c128*>(smraw + ((m * sizeof(int) + 15) / 16) * 16);  // k * kSB
   c128* Wb = coef + size_t(k > 0 ? k : 1) * kSB;                                      // m * kSB
-  __shared__ double red[256];
+  __shared__ double red[kSelThreads];
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
   const c128* th = thall + int64_t(w) * wst;
@@ -584,7 +585,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
   const int ld = k + nev;
   const double sg = sigma ? sigma[w] : 0.0;
   const int t = threadIdx.x;
-  for (int i = t; i < m; i += 256) {
+  for (int i = t; i < m; i += kSelThreads) {
     const double ki = sel_key(th[i], sg, mode);
     int rank = 0;
     for (int j = 0; j < m; ++j) {
@@ -597,25 +598,25 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
   }
   __syncthreads();
   // nearest nev eigenvectors and their values
-  for (int e = t; e < m * nev; e += 256) {
+  for (int e = t; e < m * nev; e += kSelThreads) {
     const int i = e / nev, q = e % nev;
     out[int64_t(i) * ld + k + q] = Y[int64_t(i) * m + order[q]];
   }
-  for (int q = t; q < nev; q += 256) thsel[int64_t(w) * wss + q] = th[order[q]];
+  for (int q = t; q < nev; q += kSelThreads) thsel[int64_t(w) * wss + q] = th[order[q]];
   // orthonormal basis of the first k selected eigenvectors: blocks of kSB
   // columns staged in LDS, each made orthogonal to the columns before it by
   // two passes of block classical Gram-Schmidt, then orthonormalised inside
   // the block by two passes of classical Gram-Schmidt column by column
   for (int q0 = 0; q0 < k; q0 += kSB) {
     const int nb = min(kSB, k - q0);
-    for (int e = t; e < m * kSB; e += 256) {
+    for (int e = t; e < m * kSB; e += kSelThreads) {
       const int i = e / kSB, j = e % kSB;
       Wb[e] = j < nb ? Y[int64_t(i) * m + order[q0 + j]] : c128{0.0, 0.0};
     }
     __syncthreads();
     for (int pass = 0; pass < 2 && q0 > 0; ++pass) {
       // C = out[:, :q0]^H W  (q0 x nb)
-      for (int e = t; e < q0 * nb; e += 256) {
+      for (int e = t; e < q0 * nb; e += kSelThreads) {
         const int p = e % q0, j = e / q0;
         // eight partial sums keep eight loads in flight
         c128 sp[8];
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
       }
       __syncthreads();
       // W -= out[:, :q0] C, one thread per row
-      for (int i = t; i < m; i += 256) {
+      for (int i = t; i < m; i += kSelThreads) {
         c128 acc[kSB];
 #pragma unroll
         for (int j = 0; j < kSB; ++j) acc[j] = c128{0.0, 0.0};
@@ -667,7 +668,7 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
           coef[t] = s;
         }
         __syncthreads();
-        for (int i = t; i < m; i += 256) {
+        for (int i = t; i < m; i += kSelThreads) {
           c128 v = Wb[i * kSB + q];
           for (int p = 0; p < q; ++p) v = v - Wb[i * kSB + p] * coef[p];
           Wb[i * kSB + q] = v;
@@ -675,20 +676,20 @@ __global__ __launch_bounds__(256) void select_restart_kernel(const c128* thall, 
         __syncthreads();
       }
       double part = 0.0;
-      for (int i = t; i < m; i += 256) part += norm2(Wb[i * kSB + q]);
+      for (int i = t; i < m; i += kSelThreads) part += norm2(Wb[i * kSB + q]);
       red[t] = part;
       __syncthreads();
-      for (int o = 128; o > 0; o >>= 1) {
+      for (int o = kSelThreads / 2; o > 0; o >>= 1) {
         if (t < o) red[t] += red[t + o];
         __syncthreads();
       }
       const double nrm = sqrt(red[0]);
       __syncthreads();
       const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = t; i < m; i += 256) Wb[i * kSB + q] = f * Wb[i * kSB + q];
+      for (int i = t; i < m; i += kSelThreads) Wb[i * kSB + q] = f * Wb[i * kSB + q];
       __syncthreads();
     }
-    for (int e = t; e < m * nb; e += 256) {
+    for (int e = t; e < m * nb; e += kSelThreads) {
       const int i = e / nb, j = e % nb;
       out[int64_t(i) * ld + q0 + j] = Wb[i * kSB + j];
     }
@@ -795,7 +796,7 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
   if (nwin <= 0) return;
   const size_t smem = ((m * sizeof(int) + 15) / 16) * 16 + size_t(std::max(k, 1) + m) * kSB * sizeof(c128);
   // beyond the default 64 KiB the kernel must be allowed more dynamic LDS
-  // (its static part is 2 KiB of the 160 KiB)
+  // (its static part is 4 KiB of the 160 KiB)
   if (smem > size_t(150) * 1024) throw DeviceError("select_restart: basis too large for the LDS");
   if (smem > size_t(64) * 1024) {
     static size_t granted = 0;
@@ -806,7 +807,7 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
       granted = smem;
     }
   }
-  hipLaunchKernelGGL(select_restart_kernel, dim3(nwin), dim3(256), smem, st, theta, wst, Y, wsy, m, sigma, mode, k,
+  hipLaunchKernelGGL(select_restart_kernel, dim3(nwin), dim3(kSelThreads), smem, st, theta, wst, Y, wsy, m, sigma, mode, k,
                      nev, out, wso, theta_sel, wss, wmap);
 }
 
