@@ -278,7 +278,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): windows are independent and "
-              "would be dealt across GPUs, but this build measures the one-GPU share", file=sys.stderr)
+              "would be dealt across GPUs, but this benchmark measures the one-GPU share", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1606_01139_amd import default_opts, FP64, FP32_BULK
