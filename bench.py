@@ -208,56 +208,171 @@ def stencil_roofline(nx, ny, nz, ncols, dtype, reps=30):
             "algorithmic_bytes": bytes_alg}
 
 
-def cpu_baseline(w, shift, nev=10):
-    """The oracle (ARPACK 'SM' on the shifted operator, FP64, CPU) on a bounded
-    sample of the same workload: nev eigenpairs nearest the first window's
-    shift, timed on the host cores."""
-    from oracle import operator as op, eigen
-    g = w.grid
-    ab = w.absorber.as_tuple()
-    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
-    A = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
-    t0 = time.perf_counter()
-    e, U = eigen.window_arpack(A, shift, nev)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(nev / dt, 4), "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nev} eigenpairs nearest the first planned window's shift {shift:.4f} Ha on the "
-                      f"{g.nx}x{g.ny}x{g.nz} grid, ARPACK SM on the shifted operator (scipy, FP64), "
-                      f"{dt:.1f} s; this is the workload's easiest window (bound states), the oracle's time "
-                      f"per pair grows steeply for the interior windows; cores = the threads BLAS may use, "
-                      f"the sparse products run on one"}
+CPU_SAMPLE_NEV = 10
+CPU_LOWEST_NEV = 40
 
 
-def timed_steps(w, opts, args, label):
+def _cpu_worker(conn, config):
+    """Child process (started before the parent touches the GPU): builds the
+    oracle's operator of `config`, then for each job (kind, shift, nev,
+    threads) times the oracle with BLAS limited to `threads` threads on
+    either the nev eigenpairs of lowest real part ("lowest": ARPACK 'SR', the
+    exterior end where the partitioned interval starts) or the nev nearest
+    `shift` ("window": ARPACK 'SM' on the shifted operator), and sends back
+    (status, seconds, pairs)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        from oracle import operator as op, eigen
+        from synth.workloads import workload
+        w = workload(config)
+        g = w.grid
+        gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
+        A = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    except Exception as exc:
+        conn.send(("error", repr(exc), 0))
+        return
+    while True:
+        job = conn.recv()
+        if job is None:
+            return
+        kind, shift, nev, threads = job
+        try:
+            with threadpool_limits(limits=threads):
+                t0 = time.perf_counter()
+                if kind == "lowest":
+                    e = eigen.lowest_real(A, nev)
+                else:
+                    e, _ = eigen.window_arpack(A, shift, nev)
+                dt = time.perf_counter() - t0
+            conn.send(("ok", dt, len(e)))
+        except Exception as exc:  # reported in the JSON line
+            conn.send(("error", repr(exc), 0))
+
+
+class CpuSample:
+    """The oracle timed on the host cores in a child process started before
+    the GPU is touched.  Its single-thread run overlaps the GPU steps (it
+    needs one core; the GPU steps need one host thread)."""
+
+    def __init__(self, config):
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        self.conn, child = ctx.Pipe()
+        self.proc = ctx.Process(target=_cpu_worker, args=(child, config), daemon=True)
+        self.proc.start()
+        self.t_job = None
+
+    def start(self, kind, shift, nev, threads):
+        self.job = (kind, shift, nev, threads)
+        self.t_job = time.perf_counter()
+        try:
+            self.conn.send(self.job)
+        except (BrokenPipeError, OSError):
+            pass  # the worker ended early; result() reports what it sent
+
+    def result(self, deadline):
+        """Result of the started job, waiting until `deadline` (perf_counter
+        seconds) at most; an unfinished run ends the worker."""
+        kind, shift, nev, threads = self.job
+        if self.conn.poll(max(deadline - time.perf_counter(), 0.0)):
+            kind, dt, n = self.conn.recv()
+            if kind == "ok":
+                return {"seconds": round(dt, 2), "eigenpairs": n, "value": round(n / dt, 4), "threads": threads}
+            return {"error": dt, "threads": threads}
+        waited = time.perf_counter() - self.t_job
+        self.close()
+        return {"unfinished_after_s": round(waited, 1), "threads": threads,
+                "value_upper_bound": round(nev / waited, 4)}
+
+    def close(self):
+        if self.proc.is_alive():
+            try:
+                self.conn.send(None)
+            except Exception:
+                pass
+            self.proc.join(2)
+        if self.proc.is_alive():
+            self.proc.kill()
+            self.proc.join(5)
+
+
+def cpu_baseline_line(single, multi, window, config, nev, shift):
+    """cpu_baseline object: the single-thread run (primary), the all-core
+    run, and the interior-window attempt (when it ran)."""
+    prim = single or {}
+    val = prim.get("value", prim.get("value_upper_bound"))
+    out = {"value": val, "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
+           "sample": f"the {nev} eigenpairs of lowest real part of the {config} operator (the bottom of the same "
+                     f"combined set the GPU step returns), by the oracle's ARPACK 'SR' (scipy, FP64), BLAS limited to "
+                     f"one thread; interior windows cost the oracle far more per pair (see interior_window)"}
+    if "unfinished_after_s" in prim:
+        out["sample"] += f"; not finished after {prim['unfinished_after_s']} s, so value is an upper bound"
+    if "error" in prim:
+        out["sample"] += f"; the run failed: {prim['error']}"
+    out["single_thread"] = single
+    out["all_cores"] = multi
+    if window is not None:
+        window = dict(window)
+        window["what"] = (f"{CPU_SAMPLE_NEV} eigenpairs nearest {shift:.4f} Ha (the median planned window), ARPACK "
+                          f"'SM' on the shifted operator, one thread, run beside the GPU steps")
+    out["interior_window"] = window
+    return out
+
+
+def run_budgeted(w, opts, args, label, deadline_warm, deadline_timed):
+    """Warm-up steps while fewer than args.warmup have run and the next one
+    (estimated by the last) ends before deadline_warm; then timed steps while
+    fewer than args.steps have run and the next ends before deadline_timed
+    (at least one).  Returns (seconds, converged pairs, steps timed, warm-up
+    steps run, last step's results)."""
     import torch
     p, nev = w.n_windows, w.nev_per_window
     n_r = p * nev
-    for i in range(args.warmup):
+    est = None
+    nwarm = 0
+    while nwarm < args.warmup:
+        if est is not None and time.perf_counter() + est > deadline_warm:
+            break
+        t0 = time.perf_counter()
         r = run_step(w, n_r, p, opts, args.max_windows or None, args.plan, args.fill_rounds)
         torch.cuda.synchronize()
-        log(f"{label} warmup {i} done, n={r[1]}")
+        est = time.perf_counter() - t0
+        nwarm += 1
+        log(f"{label} warm-up step {nwarm} done in {est:.1f} s, n={r[1]}")
         r[0].close()
+        if est is not None and time.perf_counter() + est > deadline_warm:
+            break
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total = 0
+    steps = 0
     last = None
-    for i in range(args.steps):
+    while steps < max(args.steps, 1):
+        if steps > 0 and time.perf_counter() + (time.perf_counter() - t0) / steps > deadline_timed:
+            break
         r = run_step(w, n_r, p, opts, args.max_windows or None, args.plan, args.fill_rounds)
         total += r[1]
+        steps += 1
         if last is not None:
             last[0].close()
         last = r
-        log(f"{label} step {i}: {time.perf_counter() - t0:.2f} s cumulative, n={r[1]}")
+        torch.cuda.synchronize()
+        log(f"{label} timed step {steps}: {time.perf_counter() - t0:.2f} s cumulative, n={r[1]}")
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, total, last
+    return time.perf_counter() - t0, total, steps, nwarm, last
 
 
 def main():
+    t_launch = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=1,
+                    help="timed steps at most; steps that would end past the wall budget are not started")
+    ap.add_argument("--warmup", type=int, default=0, help="warm-up steps at most, under the same budget")
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="wall-clock seconds from start by which the JSON line is printed (steps are sized to it)")
+    ap.add_argument("--timed-budget", type=float, default=75.0,
+                    help="seconds of timed steps at most (at least one step is timed)")
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "bulk"])
     ap.add_argument("--compare-bulk", action="store_true",
@@ -280,6 +395,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): windows are independent and "
               "would be dealt across GPUs, but this benchmark measures the one-GPU share", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not (args.no_cpu_baseline or args.k4_only or args.config == "c3"):
+        cpu = CpuSample(args.config)  # before this process touches the GPU
     import torch
     from paper_1606_01139_amd import default_opts, FP64, FP32_BULK
     from synth.workloads import workload
@@ -316,26 +434,44 @@ def main():
         return o
 
     opts = make_opts(prec)
-    dt, total, last = timed_steps(w, opts, args, args.precision)
-    oper, n, holes, status, wins, erange, stats, T = last
-    ms = dt / args.steps * 1e3
     nev = w.nev_per_window
     b = opts.block
     m = opts.basis or auto_basis(nev, b)
-    log("timing the small eigensolve and the stencil")
-    roof = k4_roofline(m, len(wins))
-    sdt = "c128" if prec == FP64 else "c64"
     g = w.grid
-    stencil = [stencil_roofline(g.nx, g.ny, g.nz, b * len(wins), sdt),
+    # kernel rooflines first: they take seconds and must be in the line
+    log("timing the small eigensolve and the stencil")
+    roof = k4_roofline(m, w.n_windows)
+    sdt = "c128" if prec == FP64 else "c64"
+    stencil = [stencil_roofline(g.nx, g.ny, g.nz, b * w.n_windows, sdt),
                stencil_roofline(64, 64, 160, 64, "c64"), stencil_roofline(64, 64, 160, 64, "c128")]
+    # the oracle's single-thread sample runs beside the GPU steps, on a
+    # window of the same plan (the median planned shift)
+    cpu_shift = None
+    if cpu is not None:
+        from paper_1606_01139_amd import Operator, PLAN_SEMICLASSICAL
+        o0 = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+        wins0, _ = o0.plan_windows(w.n_windows * nev, w.n_windows, PLAN_SEMICLASSICAL, opts)
+        o0.close()
+        cpu_shift = sorted(s for s, _ in wins0)[len(wins0) // 2]
+        cpu.start("lowest", 0.0, CPU_LOWEST_NEV, 1)
+    deadline = t_launch + args.budget
+    # the other-precision comparison and the oracle's all-core run need room after the timed steps
+    reserve = 60.0 if cpu is not None else 0.0
+    share = 0.5 if args.compare_bulk else 1.0
+    t_now = time.perf_counter()
+    gpu_window = max(deadline - reserve - t_now, 0.0) * share
+    deadline_warm = t_now + min(0.3 * gpu_window, 0.5 * args.timed_budget)
+    deadline_timed = min(t_now + gpu_window, deadline_warm + args.timed_budget)
+    dt, total, steps, nwarm, last = run_budgeted(w, opts, args, args.precision, deadline_warm, deadline_timed)
+    oper, n, holes, status, wins, erange, stats, T = last
     out = {
         "metric": "converged eigenpairs/s at rel. residual 1e-8",
         "value": round(total / dt, 3),
         "unit": "eigenpairs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 2),
+        "steps": steps,
+        "warmup": nwarm,
+        "ms_per_step": round(dt / steps * 1e3, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -347,27 +483,46 @@ def main():
                    "hole_filling": oper.fill,
                    "status": int(status), "e_range": [round(x, 6) for x in erange],
                    "planner": args.plan, "plan_seconds_last_step": round(oper.plan_seconds, 3),
-                   "block": b, "basis": m, "groups": opts.groups},
+                   "block": b, "basis": m, "groups": opts.groups,
+                   "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "budget_s": args.budget},
         "roofline": roof,
         "stencil": stencil,
         "windows": [{"shift": round(s.shift, 6), "nev": s.nev, "n_conv": s.n_conv, "restarts": s.restarts,
                      "restarts_bulk": s.restarts_bulk, "matvecs": s.matvecs,
                      "max_backward_error": s.max_backward_error} for s in stats],
     }
-    shift0 = wins[0][0]
     oper.close()
     if args.compare_bulk:
         other = FP32_BULK if prec == FP64 else FP64
-        dt2, total2, last2 = timed_steps(w, make_opts(other), args, "other precision")
+        t_now = time.perf_counter()
+        left = max(deadline - reserve - t_now, 0.0)
+        dt2, total2, steps2, _, last2 = run_budgeted(w, make_opts(other), args, "other precision",
+                                                     t_now + 0.3 * left, t_now + left)
         last2[0].close()
-        t64, tb = (dt, dt2) if prec == FP64 else (dt2, dt)
-        out["fp32_bulk_vs_fp64"] = {"fp64_s_per_step": round(t64 / args.steps, 2),
-                                    "bulk_s_per_step": round(tb / args.steps, 2),
-                                    "speedup": round(t64 / tb, 3),
-                                    "other_unique_converged": last2[1]}
-    if not args.no_cpu_baseline:
-        log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w, shift0)
+        t64, tb = (dt / steps, dt2 / steps2) if prec == FP64 else (dt2 / steps2, dt / steps)
+        out["fp32_bulk_vs_fp64"] = {"fp64_s_per_step": round(t64, 2), "bulk_s_per_step": round(tb, 2),
+                                    "speedup": round(t64 / tb, 3), "other_unique_converged": last2[1],
+                                    "other_steps": steps2}
+    if cpu is not None:
+        log("waiting for the oracle's single-thread sample")
+        single = cpu.result(deadline - 0.5 * reserve)
+        multi = window = None
+        if "value" in single:
+            ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+            threads = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS", ncpu))))
+            if single["seconds"] < deadline - time.perf_counter() - 10.0:
+                log(f"timing the oracle's all-core sample ({threads} threads)")
+                cpu.start("lowest", 0.0, CPU_LOWEST_NEV, threads)
+                multi = cpu.result(deadline - 5.0)
+            left = deadline - time.perf_counter() - 5.0
+            if "value" in (multi or {}) and left > 20.0:
+                log(f"the oracle on an interior window for {left:.0f} s at most")
+                cpu.start("window", cpu_shift, CPU_SAMPLE_NEV, 1)
+                window = cpu.result(deadline - 3.0)
+        cpu.close()
+        out["cpu_baseline"] = cpu_baseline_line(single, multi, window, args.config, CPU_LOWEST_NEV, cpu_shift)
+    out["wall_s"] = round(time.perf_counter() - t_launch, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -104,6 +104,11 @@ typedef struct {
   int64_t matvecs;          /* single-vector operator applications */
   double max_backward_error;
   int32_t restarts_bulk;    /* FP32-bulk: restarts spent in the complex64 phase */
+  int32_t breakdowns;       /* block steps whose new block A P lay in the span of the basis (to within
+                               1e-12 ||A||_G in FP64, 1e-6 in complex64) and was replaced by a fresh
+                               random block orthonormal to the basis */
+  int32_t cnorm_failures;   /* converged pairs dropped because u^T u vanished (|u^T u| < 1e-10 ||u||^2):
+                               such a vector cannot be c-normalised (bi-orthogonality of Section 1 fails) */
 } tsg_window_stats;
 
 /* Fills *opts with the defaults listed in tsg_opts. */
@@ -150,7 +155,9 @@ tsg_status tsg_plan_windows(tsg_ctx* ctx, int32_t n_r, int32_t p, int32_t mode, 
  * appends it to the context's list of partitions (a continuation run in the
  * sense of Section 2).  *n_conv gets the number converged: a partition keeps
  * only the pairs whose backward error is at most opts->tol.
- * Errors: TSG_EINVAL, TSG_ENOCONV (converged subset kept), TSG_EDEVICE. */
+ * Errors: TSG_EINVAL, TSG_ENOCONV (converged subset kept), TSG_EBREAKDOWN (a
+ * converged pair had u^T u = 0 and was dropped, see tsg_window_stats; takes
+ * precedence over TSG_ENOCONV), TSG_EDEVICE. */
 tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opts, int32_t* n_conv);
 
 /* Clears the partition list, solves all p windows together (one batched

@@ -104,18 +104,6 @@ def window_arpack(A_sparse: sp.spmatrix, sigma: float, nev: int, guard: int = 8,
     return eps[idx], U[:, idx]
 
 
-def extremal_real(A, which: str, dense: bool):
-    """Eigenvalue with smallest ('SR') or largest ('LR') real part (Section 2.2:
-    the two exterior eigenvalues that bound the partitioned interval)."""
-    if dense:
-        eps = np.linalg.eigvals(A)
-        o = order_real(eps)
-        return complex(eps[o[0]] if which == "SR" else eps[o[-1]])
-    w = sla.eigs(A, k=1, which=which, tol=1e-13, ncv=40, maxiter=200000,
-                 return_eigenvectors=False)
-    return complex(w[0])
-
-
 def lowest_real(A_sparse: sp.spmatrix, k: int, tol: float = 1e-13) -> np.ndarray:
     """The k eigenvalues of smallest real part (Section 2.2: the exterior end of
     the spectrum where the partitioned interval starts), by ARPACK 'SR' with

@@ -57,7 +57,8 @@ class TsgOpts(C.Structure):
 
 class TsgWindowStats(C.Structure):
     _fields_ = [("shift", C.c_double), ("nev", C.c_int32), ("n_conv", C.c_int32), ("restarts", C.c_int32),
-                ("matvecs", C.c_int64), ("max_backward_error", C.c_double), ("restarts_bulk", C.c_int32)]
+                ("matvecs", C.c_int64), ("max_backward_error", C.c_double), ("restarts_bulk", C.c_int32),
+                ("breakdowns", C.c_int32), ("cnorm_failures", C.c_int32)]
 
 
 class TsgError(RuntimeError):
@@ -165,6 +166,8 @@ class WindowStats:
     matvecs: int
     max_backward_error: float
     restarts_bulk: int
+    breakdowns: int = 0
+    cnorm_failures: int = 0
 
 
 class Operator:
@@ -231,7 +234,7 @@ class Operator:
         holes = (C.c_uint8 * max(p - 1, 1))()
         s = self.lib.tsg_solve_all_partitions(self.ctx, arr, p, C.byref(opts) if opts else None, C.byref(n),
                                               holes)
-        status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
+        status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV, TSG_EBREAKDOWN) if allow_noconv else ())
         return n.value, [bool(holes[i]) for i in range(p - 1)], status
 
     def fill_holes(self, e_min: float, n_cap: int, max_rounds: int, opts: Optional[TsgOpts] = None,
@@ -289,7 +292,7 @@ class Operator:
         s = self.lib.tsg_get_stats(self.ctx, j, C.byref(st))
         _check(self.lib, self.ctx, s)
         return WindowStats(st.shift, st.nev, st.n_conv, st.restarts, st.matvecs, st.max_backward_error,
-                           st.restarts_bulk)
+                           st.restarts_bulk, st.breakdowns, st.cnorm_failures)
 
     def transmission(self, energies: Sequence[float]) -> np.ndarray:
         E = np.ascontiguousarray(energies, dtype=np.float64)

@@ -8,11 +8,15 @@
 //   d eps_k = u_k^T dA u_k  (first-order perturbation of Eq. (5)'s kind),
 //   d u_k   = sum_{j != k} u_j (u_j^T dA u_k) / (eps_k - eps_j),
 // and dL = 2 Re sum_k mu_k^T dA u_k + (explicit Gamma terms), where
-//   mu_k = a_k u_k + sum_{j in S, j != k} u_j C_jk / (eps_k - eps_j) + lambda_k,
-//   a_k  = sum_e w_e g_k^2 (W conj(g))_k,  W = M^R o M^L,
+//   mu_k = sum_{j in S} u_j B_jk + lambda_k.
+// Summed over the computed set the in-set eigenvector terms telescope with
+// the eigenvalue terms: the pair (j, k) contributes through
+// (g_k - g_j)/(eps_k - eps_j) = g_j g_k, so the in-set part of dG is
+// G dA G and needs no eigenvalue difference (finite at degeneracy):
+//   B = (P + P^T)/2,  P_jk = sum_e w_e g_j g_k sum_l conj(g_l) M^R_jl M^L_kl.
+// The out-of-set part:
 //   z_k  = Gamma_R conj(U) (K^R)^T e_k + Gamma_L conj(U) (K^L)^T e_k,
 //   K^R  = Q o M^L, K^L = Q o M^R, Q_kl = sum_e w_e g_k conj(g_l),
-//   C    = U^T Z,
 //   lambda_k solves (eps_k - A) lambda_k = (I - U U^T) z_k in the
 //   complement of the computed set (projected COCR, all k at once).
 // The explicit dependence of T on Gamma_X gives
@@ -45,26 +49,78 @@ __global__ void kmat_kernel(const c128* G, int n, int nE, const double* w, const
   KLt[int64_t(l) * n + k] = q * MR[e];
 }
 
-// a_k = sum_e w_e g_k^2 sum_l W_kl conj(g_l)
-__global__ void akern(const c128* G, int n, int nE, const double* w, const c128* W, c128* a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  c128 acc{0.0, 0.0};
-  for (int t = 0; t < nE; ++t) {
-    c128 s{0.0, 0.0};
-    for (int l = 0; l < n; ++l) fma_acc(s, W[int64_t(k) * n + l], conj(G[int64_t(l) * nE + t]));
-    const c128 g = G[int64_t(k) * nE + t];
-    acc = acc + (w[t] * (g * g)) * s;
+// P_jk = sum_e w_e g_j(e) g_k(e) sum_l conj(g_l(e)) MR_jl ML_kl: a product
+// whose contraction index runs over (energy, l), with the factors formed
+// while the MR and ML tiles are staged in LDS.  Tiles of 32 x 32 outputs,
+// 256 threads, 2 x 2 outputs per thread.
+constexpr int kPT = 32, kPL = 16;
+__global__ __launch_bounds__(256) void pmat_kernel(const c128* __restrict__ G, int n, int nE,
+                                                   const double* __restrict__ w, const c128* __restrict__ MR,
+                                                   const c128* __restrict__ ML, c128* __restrict__ P) {
+  __shared__ c128 a[kPL][kPT + 1];  // conj(g_l) MR_jl, [l][j]
+  __shared__ c128 b[kPL][kPT + 1];  // ML_kl, [l][k]
+  __shared__ c128 gj[kPT], gk[kPT];
+  const int j0 = blockIdx.y * kPT, k0 = blockIdx.x * kPT;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // outputs (j0 + 2ty + p, k0 + 2tx + q)
+  c128 acc[2][2] = {};
+  for (int e = 0; e < nE; ++e) {
+    __syncthreads();
+    if (threadIdx.x < kPT) {
+      const int j = j0 + threadIdx.x;
+      gj[threadIdx.x] = j < n ? G[int64_t(j) * nE + e] : c128{0.0, 0.0};
+    } else if (threadIdx.x < 2 * kPT) {
+      const int k = k0 + threadIdx.x - kPT;
+      gk[threadIdx.x - kPT] = k < n ? G[int64_t(k) * nE + e] : c128{0.0, 0.0};
+    }
+    c128 t[2][2] = {};
+    for (int l0 = 0; l0 < n; l0 += kPL) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < kPL * kPT; i += 256) {
+        const int li = i % kPL, ri = i / kPL;
+        const int l = l0 + li;
+        const int j = j0 + ri, k = k0 + ri;
+        c128 av{0.0, 0.0}, bv{0.0, 0.0};
+        if (l < n) {
+          const c128 gl = conj(G[int64_t(l) * nE + e]);
+          if (j < n) av = gl * MR[int64_t(j) * n + l];
+          if (k < n) bv = ML[int64_t(k) * n + l];
+        }
+        a[li][ri] = av;
+        b[li][ri] = bv;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int li = 0; li < kPL; ++li) {
+        const c128 a0 = a[li][2 * ty], a1 = a[li][2 * ty + 1];
+        const c128 b0 = b[li][2 * tx], b1 = b[li][2 * tx + 1];
+        fma_acc(t[0][0], a0, b0); fma_acc(t[0][1], a0, b1);
+        fma_acc(t[1][0], a1, b0); fma_acc(t[1][1], a1, b1);
+      }
+    }
+    const double we = w[e];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const c128 s = we * (gj[2 * ty + p] * gk[2 * tx + q]);
+        fma_acc(acc[p][q], s, t[p][q]);
+      }
   }
-  a[k] = acc;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = j0 + 2 * ty + p, k = k0 + 2 * tx + q;
+      if (j < n && k < n) P[int64_t(j) * n + k] = acc[p][q];
+    }
 }
 
-// B_jk = a_k (j == k), C_jk / (eps_k - eps_j) otherwise
-__global__ void bmat_kernel(const c128* C, const c128* a, const c128* eps, int n, c128* B) {
+// B = (P + P^T) / 2
+__global__ void symmetrize_kernel(const c128* P, int n, c128* B) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= int64_t(n) * n) return;
   const int j = int(e / n), k = int(e % n);
-  B[e] = (j == k) ? a[k] : cdiv(C[e], eps[k] - eps[j]);
+  B[e] = 0.5 * (P[e] + P[int64_t(k) * n + j]);
 }
 
 __global__ void conj_kernel(const c128* X, c128* Y, int64_t total) {
@@ -214,11 +270,11 @@ void adj_kmats(const c128* G, int n, int nE, const double* w, const c128* MR, co
                hipStream_t st) {
   hipLaunchKernelGGL(kmat_kernel, dim3(blocks(int64_t(n) * n)), dim3(256), 0, st, G, n, nE, w, MR, ML, KRt, KLt);
 }
-void adj_avec(const c128* G, int n, int nE, const double* w, const c128* W, c128* a, hipStream_t st) {
-  hipLaunchKernelGGL(akern, dim3(blocks(n, 64)), dim3(64), 0, st, G, n, nE, w, W, a);
-}
-void adj_bmat(const c128* C, const c128* a, const c128* eps, int n, c128* B, hipStream_t st) {
-  hipLaunchKernelGGL(bmat_kernel, dim3(blocks(int64_t(n) * n)), dim3(256), 0, st, C, a, eps, n, B);
+void adj_inset(const c128* G, int n, int nE, const double* w, const c128* MR, const c128* ML, c128* P, c128* B,
+               hipStream_t st) {
+  const unsigned t = unsigned((n + kPT - 1) / kPT);
+  hipLaunchKernelGGL(pmat_kernel, dim3(t, t), dim3(256), 0, st, G, n, nE, w, MR, ML, P);
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks(int64_t(n) * n)), dim3(256), 0, st, P, n, B);
 }
 void adj_conj(const c128* X, c128* Y, int64_t total, hipStream_t st) {
   hipLaunchKernelGGL(conj_kernel, dim3(blocks(total)), dim3(256), 0, st, X, Y, total);

@@ -39,6 +39,24 @@ tsg_status guarded(tsg_ctx* ctx, F&& f) {
   return s;
 }
 
+// Status of a solve that stored partitions [first, end) of ctx: a dropped
+// pair whose u^T u vanished (TSG_EBREAKDOWN) takes precedence over a window
+// that did not converge (TSG_ENOCONV).
+tsg_status solve_status(tsg_ctx* ctx, size_t first, bool converged) {
+  for (size_t j = first; j < ctx->parts.size(); ++j)
+    if (ctx->parts[j].stats.cnorm_failures > 0) {
+      ctx->err = "a converged pair had u^T u = 0 and could not be c-normalised; it was dropped";
+      g_last_error = ctx->err;
+      return TSG_EBREAKDOWN;
+    }
+  if (!converged) {
+    ctx->err = "a window did not converge within max_restarts; the converged subset is kept";
+    g_last_error = ctx->err;
+    return TSG_ENOCONV;
+  }
+  return TSG_OK;
+}
+
 tsg_status fail(tsg_ctx* ctx, tsg_status s, const std::string& msg) {
   g_last_error = msg;
   if (ctx) ctx->err = msg;
@@ -133,14 +151,10 @@ tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opt
   return guarded(ctx, [&]() {
     tsg_opts o;
     if (opts) o = *opts; else tsg_default_opts(&o);
+    const size_t first = ctx->parts.size();
     const bool ok = tsg::solve_windows(ctx, {tsg::WindowSpec{win.shift, win.nev}}, o);
     if (n_conv) *n_conv = ctx->parts.back().stats.n_conv;
-    if (!ok) {
-      ctx->err = "window did not converge within max_restarts";
-      g_last_error = ctx->err;
-      return TSG_ENOCONV;
-    }
-    return TSG_OK;
+    return solve_status(ctx, first, ok);
   });
 }
 
@@ -170,12 +184,7 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
     if (n_unique) *n_unique = ctx->nc;
     if (hole_flags)
       for (size_t i = 0; i < ctx->holes.size(); ++i) hole_flags[i] = ctx->holes[i];
-    if (!ok) {
-      ctx->err = "a window did not converge within max_restarts";
-      g_last_error = ctx->err;
-      return TSG_ENOCONV;
-    }
-    return TSG_OK;
+    return solve_status(ctx, 0, ok);
   });
 }
 
@@ -190,12 +199,7 @@ tsg_status tsg_fill_holes(tsg_ctx* ctx, double e_min, int32_t n_cap, int32_t max
     if (rounds) *rounds = r.rounds;
     if (n_unique) *n_unique = ctx->nc;
     if (holes_left) *holes_left = r.holes_left;
-    if (!r.converged) {
-      ctx->err = "an inserted partition did not converge within max_restarts";
-      g_last_error = ctx->err;
-      return TSG_ENOCONV;
-    }
-    return TSG_OK;
+    return solve_status(ctx, 0, r.converged);
   });
 }
 
@@ -221,12 +225,16 @@ tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window*
       if (n_unique) n_unique[s] = cs[s]->nc;
       all = all && ok[s];
     }
-    if (!all) {
-      ctx[0]->err = "a window did not converge within max_restarts";
-      g_last_error = ctx[0]->err;
-      return TSG_ENOCONV;
+    tsg_status st = TSG_OK;
+    for (int s = 0; s < n_sys && st != TSG_EBREAKDOWN; ++s) {
+      const tsg_status q = solve_status(cs[s], 0, ok[s]);
+      if (q != TSG_OK) {
+        st = q;
+        ctx[0]->err = cs[s]->err;
+      }
     }
-    return TSG_OK;
+    (void)all;
+    return st;
   });
 }
 

@@ -451,6 +451,111 @@ __global__ void random_kernel(cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, u
   X[int64_t(w) * wsx + int64_t(j) * ldx + n] = cplx<T>{T(2.0 * u - 1.0), T(0)};
 }
 
+// Breakdown of a block step: the new block W (b columns) has lost rank
+// against the basis (its Cholesky pivot fell below the floor, flags[w] set),
+// i.e. the Krylov space of the window has (numerically) become invariant.
+// One workgroup per window replaces W with a counter-based random block,
+// made orthogonal to the first J basis columns (and to the earlier columns
+// of W) by two classical Gram-Schmidt passes in groups of 8 columns and
+// then normalised; Rinv[w] becomes the identity so that the rowmix that
+// follows leaves W as it is, and count[w] counts the event.
+constexpr int kReseedThreads = 1024;
+constexpr int kReseedGroup = 8;
+
+__device__ inline double reseed_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < kReseedThreads / 64; ++q) s += red[q];
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kReseedThreads) void reseed_kernel(const cplx<T>* V, int64_t ldv, int64_t wsv, int J,
+                                                                cplx<T>* W, int64_t ldw, int64_t wsw, int b, Rows rows,
+                                                                const int* __restrict__ flags, int* count, c128* Rinv,
+                                                                int64_t wsr, uint64_t seed,
+                                                                const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0 || flags[w] == 0) return;
+  __shared__ double red[kReseedThreads / 64];
+  __shared__ c128 dots[kReseedGroup];
+  const int64_t N = rows.of(w);
+  const cplx<T>* Vw = V + int64_t(w) * wsv;
+  cplx<T>* Ww = W + int64_t(w) * wsw;
+  const uint64_t ev = uint64_t(count[w]);
+  for (int q = 0; q < b; ++q) {
+    cplx<T>* x = Ww + int64_t(q) * ldw;
+    for (int64_t n = threadIdx.x; n < N; n += kReseedThreads) {
+      const uint64_t h = mix64(seed ^ mix64((uint64_t(w) << 40) ^ (ev << 20) ^ uint64_t(q) ^ 0xA5A5ull) ^
+                               mix64(uint64_t(n) + 0x2545F491ull));
+      const double u = double(h >> 11) * (1.0 / 9007199254740992.0);
+      x[n] = cplx<T>{T(2.0 * u - 1.0), T(0)};
+    }
+    __syncthreads();
+    const int ncol = J + q;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i0 = 0; i0 < ncol; i0 += kReseedGroup) {
+        const int g = min(kReseedGroup, ncol - i0);
+        c128 acc[kReseedGroup];
+#pragma unroll
+        for (int t = 0; t < kReseedGroup; ++t) acc[t] = c128{0.0, 0.0};
+        for (int64_t n = threadIdx.x; n < N; n += kReseedThreads) {
+          const cplx<T> xv = x[n];
+          const c128 xd{double(xv.re), double(xv.im)};
+#pragma unroll
+          for (int t = 0; t < kReseedGroup; ++t) {
+            if (t < g) {
+              const int i = i0 + t;
+              const cplx<T> cv = i < J ? Vw[int64_t(i) * ldv + n] : Ww[int64_t(i - J) * ldw + n];
+              fma_cacc(acc[t], c128{double(cv.re), double(cv.im)}, xd);
+            }
+          }
+        }
+        for (int t = 0; t < g; ++t) {
+          const double re = reseed_sum(acc[t].re, red);
+          const double im = reseed_sum(acc[t].im, red);
+          if (threadIdx.x == 0) dots[t] = c128{re, im};
+        }
+        __syncthreads();
+        for (int64_t n = threadIdx.x; n < N; n += kReseedThreads) {
+          const cplx<T> xv = x[n];
+          c128 xd{double(xv.re), double(xv.im)};
+          for (int t = 0; t < g; ++t) {
+            const int i = i0 + t;
+            const cplx<T> cv = i < J ? Vw[int64_t(i) * ldv + n] : Ww[int64_t(i - J) * ldw + n];
+            const c128 c{double(cv.re), double(cv.im)};
+            const c128 d = dots[t];
+            xd.re -= d.re * c.re - d.im * c.im;
+            xd.im -= d.re * c.im + d.im * c.re;
+          }
+          x[n] = cplx<T>{T(xd.re), T(xd.im)};
+        }
+        __syncthreads();
+      }
+    }
+    double s = 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += kReseedThreads) {
+      const cplx<T> xv = x[n];
+      s += double(xv.re) * double(xv.re) + double(xv.im) * double(xv.im);
+    }
+    s = reseed_sum(s, red);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += kReseedThreads) {
+      const cplx<T> xv = x[n];
+      x[n] = cplx<T>{T(inv * double(xv.re)), T(inv * double(xv.im))};
+    }
+    __syncthreads();
+  }
+  c128* Ri = Rinv + int64_t(w) * wsr;
+  for (int e = threadIdx.x; e < b * b; e += kReseedThreads)
+    Ri[e] = c128{(e / b == e % b) ? 1.0 : 0.0, 0.0};
+  if (threadIdx.x == 0) count[w] += 1;
+}
+
 template <typename TX, typename TY>
 __global__ void copy_kernel(const cplx<TX>* X, int64_t ldx, int64_t wsx, cplx<TY>* Y, int64_t ldy, int64_t wsy,
                             Rows rows, const int* __restrict__ wmap) {
@@ -479,9 +584,10 @@ __global__ void scale_kernel(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* s
 
 // One workgroup per window; thread 0 factors G = R^H R (b small) and then
 // the workgroup forms R^{-1} column by column.  A pivot that is not
-// positive relative to the trace flags a rank-deficient block.
+// positive relative to the trace, or not above abs_floor[w] (when given),
+// flags a rank-deficient block.
 __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags,
-                                    const int* __restrict__ wmap) {
+                                    const int* __restrict__ wmap, const double* __restrict__ abs_floor) {
   extern __shared__ c128 L[];  // b*b: R (upper), row-major
   const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
   if (w < 0) return;  // idle slot (whole workgroup)
@@ -495,7 +601,8 @@ __global__ void cholesky_inv_kernel(const c128* G, int64_t wsg, int b, c128* Rin
     bad = 0;
     double tr = 0.0;
     for (int i = 0; i < b; ++i) tr += L[i * b + i].re;
-    const double floor = 1e-26 * (tr > 0 ? tr : 1.0);
+    double floor = 1e-26 * (tr > 0 ? tr : 1.0);
+    if (abs_floor) floor = fmax(floor, abs_floor[w]);
     for (int k = 0; k < b; ++k) {
       double d = L[k * b + k].re;
       for (int p = 0; p < k; ++p) d -= norm2(L[p * b + k]);
@@ -846,11 +953,24 @@ template void rowmix<float>(cplx<float>*, int64_t, int64_t, const c128*, int64_t
                             const int*);
 
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
-                  const int* wmap) {
+                  const int* wmap, const double* abs_floor) {
   if (nwin <= 0) return;
   hipLaunchKernelGGL(cholesky_inv_kernel, dim3(nwin), dim3(64), size_t(b) * b * sizeof(c128), st, G, wsg, b, Rinv,
-                     wsr, flags, wmap);
+                     wsr, flags, wmap, abs_floor);
 }
+
+template <typename T>
+void reseed_block(const cplx<T>* V, int64_t ldv, int64_t wsv, int J, cplx<T>* W, int64_t ldw, int64_t wsw, int b,
+                  Rows rows, const int* flags, int* count, c128* Rinv, int64_t wsr, uint64_t seed, int nwin,
+                  hipStream_t st, const int* wmap) {
+  if (nwin <= 0 || b <= 0) return;
+  hipLaunchKernelGGL((reseed_kernel<T>), dim3(nwin), dim3(kReseedThreads), 0, st, V, ldv, wsv, J, W, ldw, wsw, b,
+                     rows, flags, count, Rinv, wsr, seed, wmap);
+}
+template void reseed_block<double>(const cplx<double>*, int64_t, int64_t, int, cplx<double>*, int64_t, int64_t, int,
+                                   Rows, const int*, int*, c128*, int64_t, uint64_t, int, hipStream_t, const int*);
+template void reseed_block<float>(const cplx<float>*, int64_t, int64_t, int, cplx<float>*, int64_t, int64_t, int,
+                                  Rows, const int*, int*, c128*, int64_t, uint64_t, int, hipStream_t, const int*);
 
 #define TSG_INST_T(T)                                                                                              \
   template void gemm_cols<T>(const cplx<T>*, int64_t, int64_t, const c128*, int64_t, int64_t, cplx<T>*, int64_t,  \

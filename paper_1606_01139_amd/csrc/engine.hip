@@ -164,12 +164,13 @@ struct SolveStream {
 // holds A times the wanted Ritz vectors.  Ft is a b-column temporary.
 template <typename T> struct Batch {
   int nw = 0, m = 0, k = 0, b = 0, nv = 0;
+  uint64_t seed = 0;
   int64_t ldN = 0;
   Rows rows;
   DevArr<cplx<T>> V, AV, Vr, AR, Ft;
   DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, Mx, part;
-  DevArr<double> res, sig, nb, na;
-  DevArr<int> flags, info, wmap, wmap2, sel;
+  DevArr<double> res, sig, nb, na, bfloor;
+  DevArr<int> flags, info, wmap, wmap2, sel, nbreak;
 
   void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
     nw = nw_; ldN = S.ldN; rows = S.rows_arg(); m = m_; k = k_; b = b_; nv = nv_;
@@ -195,6 +196,7 @@ template <typename T> struct Batch {
     sig.alloc(size_t(nw));
     flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
     wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * b); na.alloc(size_t(nw) * b);
+    bfloor.alloc(size_t(nw)); nbreak.alloc(size_t(nw));
   }
   int64_t ws() const { return ldN * (m + b); }
   int64_t wsc() const { return int64_t(m + b) * 2 * b; }
@@ -266,7 +268,12 @@ void expand_step(const Systems& S, Batch<T>& B, int j) {
   rowmix<T>(P, ldN, wsV, B.Mx.p, int64_t(4) * b * b, B.rows, 2 * b, nw, st, wm);
   gram<T, T>(W, ldN, wsV, W, ldN, wsV, B.rows, b, b, B.G.p, b, int64_t(b) * b, nw, B.part.p, int64_t(B.part.n), st,
              wm);
-  cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, nw, st, wm);
+  // a pivot below the floor (a fixed fraction of ||A||) means A P lies in
+  // the span of the basis: that window's block is replaced by a fresh random
+  // block orthonormal to the basis (breakdown of the Krylov sequence)
+  cholesky_inv(B.G.p, int64_t(b) * b, b, B.Rinv.p, int64_t(b) * b, B.flags.p, nw, st, wm, B.bfloor.p);
+  reseed_block<T>(B.V.p, ldN, wsV, j + b, W, ldN, wsV, b, B.rows, B.flags.p, B.nbreak.p, B.Rinv.p, int64_t(b) * b,
+                  B.seed ^ 0x6A09E667F3BCC908ull, nw, st, wm);
   rowmix<T>(W, ldN, wsV, B.Rinv.p, int64_t(b) * b, B.rows, b, nw, st, wm);
 }
 
@@ -274,6 +281,7 @@ struct WinOut {
   bool done = false;
   bool converged = false;
   int restarts = 0;
+  int breakdowns = 0;       // block steps whose new block lost rank and was replaced
   int64_t matvecs = 0;
   std::vector<c128> theta;   // selection order
   std::vector<double> rho;
@@ -314,6 +322,16 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
   std::vector<double> shifts(nw);
   for (int w = 0; w < nw; ++w) shifts[w] = wins[w].shift;
   check(hipMemcpyAsync(B.sig.p, shifts.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st), "shifts");
+  // breakdown floor on the squared norm of a new block column after
+  // orthogonalisation: (eta ||A||)^2, eta well above the rounding level of
+  // the storage precision
+  const double eta = sizeof(T) == 4 ? 1e-6 : 1e-12;
+  std::vector<double> floors(nw);
+  for (int w = 0; w < nw; ++w) floors[w] = (eta * normA[w]) * (eta * normA[w]);
+  check(hipMemcpyAsync(B.bfloor.p, floors.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st), "floors");
+  check(hipMemsetAsync(B.nbreak.p, 0, sizeof(int) * nw, st), "nbreak");
+  B.seed = seed;
+  std::vector<int> hbreak(nw, 0);
   out.assign(nw, WinOut{});
   const int* wm = B.wmap.p;
   const Rows rows = B.rows;
@@ -390,12 +408,17 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
     check(hipMemcpyAsync(hres.data(), B.res.p, sizeof(double) * 2 * nv * nw, hipMemcpyDeviceToHost, st), "res");
     check(hipMemcpyAsync(hth.data(), B.thsel.p, sizeof(c128) * nv * nw, hipMemcpyDeviceToHost, st), "theta");
     check(hipMemcpyAsync(hinfo.data(), B.info.p, sizeof(int) * nw, hipMemcpyDeviceToHost, st), "info");
+    check(hipMemcpyAsync(hbreak.data(), B.nbreak.p, sizeof(int) * nw, hipMemcpyDeviceToHost, st), "nbreak");
     check(hipStreamSynchronize(st), "sync");
     std::swap(B.V, B.Vr);
     std::vector<int> still;
     for (int w : active) {
       WinOut& o = out[w];
       o.restarts = cyc + 1;
+      if (hbreak[w] > o.breakdowns && trace_on())
+        std::fprintf(stderr, "[tsg] cycle %d window %d: %d block breakdown(s), fresh random block(s)\n", cyc, w,
+                     hbreak[w] - o.breakdowns);
+      o.breakdowns = hbreak[w];
       const int nev = wins[w].nev;
       o.theta.assign(hth.begin() + size_t(w) * nv, hth.begin() + size_t(w) * nv + nev);
       o.rho.resize(nev);
@@ -477,7 +500,7 @@ void choose_sizes(int64_t N, int nvmax, const tsg_opts& o, int& m, int& k, int& 
 // real part.  Returns the partition, which keeps only the pairs whose
 // backward error is at most tol (all of them when the iteration converged).
 Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr<c128>&& U, int nev,
-                        const WinOut& o, int restarts_bulk, double tol) {
+                        const WinOut& o, int restarts_bulk, int breakdowns_bulk, double tol) {
   const int64_t N = c->N;
   Systems S;
   one_system(S, c, st);
@@ -526,11 +549,15 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
     rho[i] = std::isfinite(r) ? r : 1e300;
     maxrho = std::max(maxrho, rho[i]);
   }
-  // gather the kept pairs as sorted, c-normalised columns
+  // gather the kept pairs as sorted, c-normalised columns; a converged
+  // vector whose u^T u vanishes cannot be c-normalised and is dropped
   std::vector<const c128*> srcs;
   std::vector<c128> scs;
+  int cfail = 0;
   for (int i = 0; i < nev; ++i) {
     if (!(rho[ord[i]] <= tol)) continue;
+    const c128 uu = hd[2 * ord[i] + 1];
+    if (!(cabs(uu) >= 1e-10 * hr[2 * ord[i] + 1])) { ++cfail; continue; }
     srcs.push_back(U.p + int64_t(ord[i]) * N);
     scs.push_back(sc[ord[i]]);
     P.eps.push_back(thc[ord[i]]);
@@ -553,6 +580,8 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
   P.stats.matvecs = o.matvecs + nev;
   P.stats.max_backward_error = maxrho;
   P.stats.restarts_bulk = restarts_bulk;
+  P.stats.breakdowns = o.breakdowns + breakdowns_bulk;
+  P.stats.cnorm_failures = cfail;
   return P;
 }
 
@@ -585,7 +614,7 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
   for (int w = 0; w < nw; ++w) normA[w] = S.of(w)->normA;
   std::vector<DevArr<c128>> results(nw);
   std::vector<WinOut> outs;
-  std::vector<int> bulk_restarts(nw, 0);
+  std::vector<int> bulk_restarts(nw, 0), bulk_breaks(nw, 0);
   std::vector<int64_t> bulk_mv(nw, 0);
   auto save_fp64 = [&](Batch<double>& Bd) {
     return [&](int w) {
@@ -614,7 +643,11 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
                              Bf.Vr.p + size_t(w) * Bf.ws() + size_t(m) * ldN, sizeof(c64) * ldN * b,
                              hipMemcpyDeviceToDevice, st), "handoff");
       }, use_graphs, 100.0 * btol);
-      for (int w = 0; w < nw; ++w) { bulk_restarts[w] = fo[w].restarts; bulk_mv[w] = fo[w].matvecs; }
+      for (int w = 0; w < nw; ++w) {
+        bulk_restarts[w] = fo[w].restarts;
+        bulk_mv[w] = fo[w].matvecs;
+        bulk_breaks[w] = fo[w].breakdowns;
+      }
     }
     Batch<double> Bd;
     Bd.alloc(nw, S, m, k, b, nvmax);
@@ -632,7 +665,7 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
   for (int w = 0; w < nw; ++w) {
     outs[w].matvecs += bulk_mv[w];
     Partition P = finish_window(S.of(w), st, wins[w], std::move(results[w]), wins[w].nev, outs[w], bulk_restarts[w],
-                                o.tol);
+                                bulk_breaks[w], o.tol);
     conv[w] = outs[w].converged && P.stats.n_conv == wins[w].nev;
     parts.push_back(std::move(P));
   }
@@ -1227,15 +1260,14 @@ int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, doubl
   const size_t nn = size_t(n) * n, Nn = size_t(N) * n;
   const Rows rows{N, nullptr};
   DevArr<double> dE, dw, dVd, dGL, dGR, prof, dab, sums, cpart;
-  DevArr<c128> G, KRt, KLt, a, Ub, YR, YL, Z, C, B, MU, X, R, MRv, P, MP, Ct, rho, alpha, beta, gpart;
+  DevArr<c128> G, KRt, KLt, Ub, YR, YL, Z, C, B, MU, X, R, MRv, P, MP, Ct, rho, alpha, beta, gpart;
   DevArr<int> done;
   dE.alloc(nE); dw.alloc(nE);
   check(hipMemcpyAsync(dE.p, E, sizeof(double) * nE, hipMemcpyHostToDevice, st), "E");
   check(hipMemcpyAsync(dw.p, w, sizeof(double) * nE, hipMemcpyHostToDevice, st), "w");
-  G.alloc(size_t(n) * nE); KRt.alloc(nn); KLt.alloc(nn); a.alloc(n);
+  G.alloc(size_t(n) * nE); KRt.alloc(nn); KLt.alloc(nn);
   adj_gmat(c->epsd.p, n, dE.p, nE, G.p, st);
   adj_kmats(G.p, n, nE, dw.p, c->MR.p, c->ML.p, KRt.p, KLt.p, st);
-  adj_avec(G.p, n, nE, dw.p, c->Wt.p, a.p, st);
   // Y^X = conj(U) (K^X)^T; explicit Gamma terms D_X = Re rowsum(U o Y^X)
   Ub.alloc(Nn); YR.alloc(Nn); YL.alloc(Nn); Z.alloc(Nn);
   adj_conj(c->Uc.p, Ub.p, int64_t(Nn), st);
@@ -1248,13 +1280,14 @@ int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, doubl
   adj_rowdot(c->Uc.p, YR.p, N, n, 1.0, false, dGR.p, st);
   adj_rowdot(c->Uc.p, YL.p, N, n, 1.0, false, dGL.p, st);
   adj_zcombine(YR.p, YL.p, c->gR.p, c->gL.p, N, n, plane, Z.p, st);
-  // in-set part: mu = U B, B = diag(a) + C_jk / (eps_k - eps_j), C = U^T Z
+  // in-set part: mu = U B with B = (P + P^T)/2 (no eigenvalue differences)
   int64_t pw = std::max<int64_t>(gram_workspace(N, n, n, 1), 1);
   gpart.alloc(size_t(pw));
   C.alloc(nn); B.alloc(nn); MU.alloc(Nn); Ct.alloc(nn);
-  gram<double, double>(Ub.p, N, 0, Z.p, N, 0, rows, n, n, C.p, n, 0, 1, gpart.p, pw, st);
-  adj_bmat(C.p, a.p, c->epsd.p, n, B.p, st);
+  adj_inset(G.p, n, nE, dw.p, c->MR.p, c->ML.p, Ct.p, B.p, st);
   gemm_cols<double>(c->Uc.p, N, 0, B.p, n, 0, MU.p, N, 0, rows, n, n, 0.0, 1, st);
+  // C = U^T Z for the right-hand sides of the out-of-set solves
+  gram<double, double>(Ub.p, N, 0, Z.p, N, 0, rows, n, n, C.p, n, 0, 1, gpart.p, pw, st);
   // out-of-set part: (eps_k - A) x_k = P z_k with P = I - U U^T, solved by
   // COCR on the projected operator P (eps_k - A) P (complex symmetric, as
   // P^T = P), all k together

@@ -119,9 +119,18 @@ void rowmix(cplx<T>* Y, int64_t ldy, int64_t wsy, const c128* M, int64_t wsm, Ro
             hipStream_t st, const int* wmap = nullptr);
 
 // Small per-window kernels on b x b Gram matrices (one workgroup per window):
-// G = R^H R (Cholesky), writes Rinv (upper triangular) and a breakdown flag.
+// G = R^H R (Cholesky), writes Rinv (upper triangular) and flags[w] = 1 when
+// a pivot falls below 1e-26 trace(G) or below abs_floor[w] (when given),
+// else 0.
 void cholesky_inv(const c128* G, int64_t wsg, int b, c128* Rinv, int64_t wsr, int* flags, int nwin, hipStream_t st,
-                  const int* wmap = nullptr);
+                  const int* wmap = nullptr, const double* abs_floor = nullptr);
+// For windows with flags[w] set: W (b contiguous columns) is replaced by a
+// random block orthonormal to V[:, 0:J) and within itself, Rinv[w] is set to
+// the identity and count[w] is incremented (breakdown of the block step).
+template <typename T>
+void reseed_block(const cplx<T>* V, int64_t ldv, int64_t wsv, int J, cplx<T>* W, int64_t ldw, int64_t wsw, int b,
+                  Rows rows, const int* flags, int* count, c128* Rinv, int64_t wsr, uint64_t seed, int nwin,
+                  hipStream_t st, const int* wmap = nullptr);
 
 // ---------------------------------------------------------------- K4
 // Eigen-decomposition of general complex m x m matrices, one workgroup per
@@ -175,8 +184,10 @@ void gather_columns(c128* dst, int64_t ldd, const c128* const* srcs, const c128*
 void adj_gmat(const c128* eps, int n, const double* E, int nE, c128* G, hipStream_t st);
 void adj_kmats(const c128* G, int n, int nE, const double* w, const c128* MR, const c128* ML, c128* KRt, c128* KLt,
                hipStream_t st);
-void adj_avec(const c128* G, int n, int nE, const double* w, const c128* W, c128* a, hipStream_t st);
-void adj_bmat(const c128* C, const c128* a, const c128* eps, int n, c128* B, hipStream_t st);
+// In-set part of the adjoint: B = (P + P^T)/2 with
+// P_jk = sum_e w_e g_j g_k sum_l conj(g_l) MR_jl ML_kl (P is scratch, n x n).
+void adj_inset(const c128* G, int n, int nE, const double* w, const c128* MR, const c128* ML, c128* P, c128* B,
+               hipStream_t st);
 void adj_conj(const c128* X, c128* Y, int64_t total, hipStream_t st);
 void adj_zcombine(const c128* YR, const c128* YL, const double* gR, const double* gL, int64_t N, int n,
                   int64_t plane, c128* Z, hipStream_t st);

@@ -88,3 +88,53 @@ def test_autograd_matches_finite_differences(torch_cuda):
     dv[r] = step
     fd = (loss(V.detach() + dv, par.detach()) - loss(V.detach() - dv, par.detach())) / (2 * step)
     assert abs(V.grad[r].item() - fd) <= 1e-4 * max(abs(fd), 1e-3), (V.grad[r].item(), fd)
+
+
+def test_vjp_finite_on_degenerate_pairs(torch_cuda):
+    """An x-y symmetric box (nx = ny, V = 0, absorbers in z) has exactly
+    twofold eigenvalues.  The in-set part of the gradient is G dA G and has
+    no eigenvalue differences, so it must stay finite and match the oracle's
+    exact gradient when whole degenerate pairs are in the computed set.  The
+    oracle's eigenbasis is bi-orthogonalised inside each pair by its
+    Algorithm 2 (unconjugated Gram-Schmidt of near-equal eigenvalues)."""
+    from oracle import eigen, gradient, operator as op, partition
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import Absorber, Grid
+    print("vjp on a degenerate system", flush=True)
+    g = Grid(6, 6, 10)
+    ab = Absorber.ends(g).as_tuple()
+    V = np.zeros(g.n)
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    A = op.assemble_dense(g.nx, g.ny, g.nz, g.h, V, gL, gR)
+    nrm = op.gershgorin_norm(g.h, V, (gL + gR).max())
+    ea, Ua = eigen.dense_spectrum(A)
+    full = partition.combine([(ea, Ua)], nrm)
+    assert len(full.eps) == g.n
+    assert np.abs(full.U.T @ full.U - np.eye(g.n)).max() < 1e-8
+    # at least two exact pairs among the lowest eigenvalues
+    d = np.abs(np.diff(full.eps[:14]))
+    assert (d < 1e-10).sum() >= 2
+    # a window below the spectrum whose nearest set ends in a gap, so that it
+    # holds whole pairs
+    sigma = float(full.eps[0].real) - 1.0
+    order = eigen.order_nearest(full.eps, sigma)
+    dist = np.abs(full.eps[order] - sigma)
+    nev = next(k for k in range(8, 20) if dist[k] - dist[k - 1] > 1e-3)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, V, ab)
+    oper.solve_all_partitions([(sigma, nev)], default_opts(tol=1e-11))
+    eps = oper.eigenvalues()
+    assert len(eps) == nev
+    in_set = np.zeros(g.n, bool)
+    for e in eps:
+        in_set |= np.abs(full.eps - e) < 1e-8
+    assert in_set.sum() == nev and set(np.flatnonzero(in_set)) == set(order[:nev])
+    E = np.linspace(eps.real.min() - 0.05, eps.real.max() + 0.05, 6)
+    wts = np.random.default_rng(5).uniform(0.5, 1.5, len(E))
+    dV, dab = oper.transmission_vjp(E, wts)
+    assert np.all(np.isfinite(dV)) and np.all(np.isfinite(dab))
+    dg = gradient.absorber_param_derivs(g.nx, g.ny, g.nz, g.h, ab)
+    ref = gradient.gradient_full_basis(full.eps, full.U, in_set, gL, gR, dg, E, wts)
+    scale = np.abs(ref["V"]).max()
+    assert np.abs(dV - ref["V"]).max() <= 1e-6 * scale, np.abs(dV - ref["V"]).max() / scale
+    np.testing.assert_allclose(dab, ref["abs"], rtol=1e-6, atol=1e-6 * np.abs(ref["abs"]).max())
+    oper.close()

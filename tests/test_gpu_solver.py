@@ -308,3 +308,70 @@ def test_c2_full_size_sampled_parity(c2_solved):
     Tref = transport.transmission_spectral(eps, Uall, gL, gR, E)
     assert np.abs(T - Tref).max() <= 1e-6
     assert (T >= -1e-10).all()
+
+
+def test_restart_cap_reports_noconv_and_keeps_converged_subset(torch_cuda):
+    """max_restarts = 1 stops every window after its first cycle: the solve
+    returns TSG_ENOCONV and each partition keeps only its pairs at backward
+    error <= tol, which are exact eigenpairs of the oracle's operator."""
+    from oracle import eigen
+    from paper_1606_01139_amd import Operator, default_opts, TSG_ENOCONV
+    from synth.workloads import workload
+    print("restart cap -> ENOCONV", flush=True)
+    w = workload("c1")
+    g = w.grid
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    shifts = [0.5 * (ea[0].real + ea[19].real), 0.5 * (ea[20].real + ea[39].real)]
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    n, holes, status = oper.solve_all_partitions([(s, 20) for s in shifts], default_opts(max_restarts=1),
+                                                 allow_noconv=True)
+    assert status == TSG_ENOCONV
+    kept = 0
+    for j, s in enumerate(shifts):
+        st = oper.stats(j)
+        assert st.restarts == 1 and st.n_conv < st.nev
+        eps, Ud = oper.partition(j)
+        assert len(eps) == st.n_conv
+        kept += st.n_conv
+        U = Ud.cpu().numpy()
+        for k in range(len(eps)):
+            r = A @ U[:, k] - eps[k] * U[:, k]
+            assert np.linalg.norm(r) / (nrm * np.linalg.norm(U[:, k])) <= 1e-8
+            assert np.min(np.abs(ea - eps[k]) / np.maximum(np.abs(ea), 1.0)) <= 1e-10
+    assert n <= kept
+    oper.close()
+
+
+def test_invariant_krylov_space_breakdown_is_restarted(torch_cuda):
+    """A 4 x 4 x 4 cube with V = 0 and no absorbers has eigenvalues of
+    multiplicity 1, 3 and 6 (sums of three 1-D eigenvalues), so the Krylov
+    space of a block of 2 vectors is invariant at dimension <= 36 < 64 and a
+    basis of 60 must break down.  Each breakdown is replaced by a fresh random
+    block orthonormal to the basis; the window must still find every
+    eigenvalue with its multiplicity (oracle: dense spectrum)."""
+    from oracle import eigen, operator as op
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import Grid
+    print("breakdown on a 4x4x4 cube", flush=True)
+    g = Grid(4, 4, 4)
+    ab = (0.0, 2.0, 0.0, 0.0, 2.0, 1.5)
+    V = np.zeros(g.n)
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    A = op.assemble_dense(g.nx, g.ny, g.nz, g.h, V, gL, gR)
+    ea = np.sort(np.linalg.eigvalsh(A.real))
+    sigma = float(ea[0]) - 1.0
+    # a count that ends between two distinct eigenvalues
+    nev = next(k for k in range(7, 20) if ea[k] - ea[k - 1] > 1e-6)
+    mult = np.diff(np.flatnonzero(np.r_[True, np.diff(ea[:nev]) > 1e-8, True]))
+    assert mult.max() >= 3
+    oper = Operator(g.nx, g.ny, g.nz, g.h, V, ab)
+    nconv = oper.solve_partition(sigma, nev, default_opts(basis=60, keep=30, tol=1e-10))
+    st = oper.stats(0)
+    assert st.breakdowns >= 1, st
+    assert nconv == nev
+    eps, Ud = oper.partition(0)
+    np.testing.assert_allclose(np.sort(eps.real), ea[:nev], atol=1e-10 * max(1.0, abs(ea[nev - 1])))
+    assert np.abs(eps.imag).max() <= 1e-10
+    U = Ud.cpu().numpy()
+    assert np.linalg.matrix_rank(U, tol=1e-6) == nev
+    oper.close()

@@ -370,3 +370,74 @@ def test_hole_filling_closes_gaps_brute_force():
     want = np.sort_complex(ea[(ea.real >= lo) & (ea.real <= hi)])
     np.testing.assert_allclose(np.sort_complex(comb.eps), want, atol=1e-12)
     np.testing.assert_allclose(comb.U.T @ comb.U, np.eye(len(comb.eps)), atol=1e-8)
+
+
+# ---------------------------------------------------------------- pins of helpers
+def test_backward_error_worked_value():
+    """A = diag(1, 2), u = (1, 1), theta = 3/2: r = (-1/2, 1/2), so
+    ||r|| / (||A|| ||u||) = (1/sqrt 2) / (2 sqrt 2) = 1/4 with ||A|| = 2; an
+    exact eigenpair gives 0."""
+    A = np.diag([1.0, 2.0]).astype(complex)
+    u = np.array([1.0, 1.0], dtype=complex)
+    assert abs(eigen.backward_error(A, u, 1.5, 2.0) - 0.25) < 1e-15
+    assert eigen.backward_error(A, np.array([0.0, 3.0j]), 2.0, 2.0) == 0.0
+    # scaling u or ||A|| scales as stated
+    assert abs(eigen.backward_error(A, 7.0 * u, 1.5, 4.0) - 0.125) < 1e-15
+
+
+@pytest.mark.parametrize("n_r,p,want", [(10, 3, [4, 3, 3]), (400, 8, [50] * 8), (7, 7, [1] * 7),
+                                        (9, 4, [3, 2, 2, 2]), (5, 1, [5]), (3, 5, [1, 1, 1, 0, 0])])
+def test_equal_counts_worked_values(n_r, p, want):
+    """n_r pairs dealt to p partitions as evenly as integers allow: the
+    counts sum to n_r, differ by at most one, and the larger ones come
+    first (worked by hand)."""
+    got = partition.equal_counts(n_r, p)
+    assert got == want
+    assert sum(got) == n_r and max(got) - min(got) <= 1
+
+
+@pytest.mark.parametrize("e_min,n_r,p,box", [(-2.65, 400, 8, (15.5, 15.5, 31.5)), (-1.0, 40, 2, (4.5, 4.5, 9.5)),
+                                             (0.3, 100, 5, (10.0, 10.0, 10.0))])
+def test_sample_shifts_cover_the_free_particle_region(e_min, n_r, p, box):
+    """Density sampling's shifts (a reading: the paper asks for a few pairs at
+    several sample points) must be max(2p, 8) evenly spaced points, each in
+    the middle of its slice of [E_min, top], where `top` lies above the
+    energy at which the free-particle (Weyl) count of the box reaches n_r,
+    so that the samples reach the region the n_r pairs occupy."""
+    s = partition.sample_shifts(e_min, n_r, p, box)
+    S = max(2 * p, 8)
+    assert len(s) == S
+    d = np.diff(s)
+    assert np.allclose(d, d[0], rtol=1e-12, atol=0) and d[0] > 0
+    top = s[-1] + d[0] / 2
+    assert abs((s[0] - d[0] / 2) - e_min) < 1e-12
+    vol = box[0] * box[1] * box[2]
+    # Weyl: N(E) = vol (2E)^(3/2) / (6 pi^2) free states below E
+    e_weyl = 0.5 * (6 * math.pi ** 2 * n_r / vol) ** (2.0 / 3.0)
+    assert top > e_weyl
+    assert top > e_min
+
+
+def test_absorber_profile_width_is_the_standard_deviation():
+    """Gaussian absorbers with amplitude a and width w read as the peak and
+    the standard deviation: Gamma_L(0) = a, Gamma_L(w) = a e^(-1/2)
+    (e.g. 0.5 Ha and 2 bohr give 0.5 e^(-1/2) at z = 2 bohr), the half
+    maximum sits at w sqrt(2 ln 2), and the mass over the half line is
+    a w sqrt(pi/2).  Gamma_R is the mirror image about z_R."""
+    h, nz = 0.5, 41
+    zR = (nz - 1) * h
+    gL, gR = op.absorber_profiles(nz, h, (0.5, 2.0, 0.0, 0.25, 3.0, zR))
+    assert abs(gL[0] - 0.5) < 1e-15 and abs(gL[4] - 0.5 * math.exp(-0.5)) < 1e-15
+    assert abs(gR[-1] - 0.25) < 1e-15 and abs(gR[-1 - 6] - 0.25 * math.exp(-0.5)) < 1e-15
+    # fine grid: FWHM and half-line mass
+    hf = 1e-3
+    z = np.arange(0, 40.0, hf)
+    gf, _ = op.absorber_profiles(len(z), hf, (0.5, 2.0, 0.0, 0.0, 1.0, 0.0))
+    zhalf = z[np.argmin(np.abs(gf - 0.25))]
+    assert abs(zhalf - 2.0 * math.sqrt(2 * math.log(2))) < 2e-3
+    mass = np.trapezoid(gf, z)
+    assert abs(mass - 0.5 * 2.0 * math.sqrt(math.pi / 2)) < 1e-6
+    # the fields repeat the z profile over each xy plane (x fastest)
+    GL, GR = op.gamma_fields(3, 2, nz, h, (0.5, 2.0, 0.0, 0.25, 3.0, zR))
+    assert GL.shape == (3 * 2 * nz,) and np.all(GL[:6] == gL[0]) and np.all(GL[6:12] == gL[1])
+    assert np.all(GR[-6:] == gR[-1])
