@@ -292,6 +292,21 @@ tsg_status tsg_apply_operator(tsg_ctx* ctx, const void* X, void* Y, int32_t ncol
  * m or batch out of range; nothing launched), TSG_ENOMEM, TSG_EDEVICE. */
 tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info, void* hip_stream);
 
+/* tsg_dense_eig for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but the workspace lives in a
+ * fixed 64 MiB device array that each GPU holds from its first call until
+ * the process ends, so the call allocates nothing.  It returns as soon as the
+ * work is enqueued on hip_stream (no synchronisation); the outputs are
+ * complete when that stream reaches this point.  Every call on one GPU shares
+ * the array: calls that overlap on one GPU (other streams or threads) race.
+ * Limit: batch * (2 m^2 + rotation log(m)) complex128 values must fit in the
+ * 64 MiB (m = 450: 2 matrices; m = 300: 3; m = 128: 6; m = 64: 9).
+ * Errors: TSG_EINVAL (null pointer, m out of range, or more than fits in the
+ * scratch; nothing launched), TSG_EDEVICE. */
+tsg_status tsg_dense_eig_noalloc(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info,
+                                 void* hip_stream);
+
 /* Message for the last failed call on ctx (or for the last failed call
  * without a context when ctx is NULL).  Never NULL. */
 const char* tsg_last_error(const tsg_ctx* ctx);

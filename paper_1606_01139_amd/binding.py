@@ -29,7 +29,7 @@ EXPORTS = [
     "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
     "tsg_solve_all_partitions", "tsg_fill_holes", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
     "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_transmission_vjp", "tsg_apply_operator",
-    "tsg_dense_eig",
+    "tsg_dense_eig", "tsg_dense_eig_noalloc",
     "tsg_last_error", "tsg_destroy",
 ]
 
@@ -101,6 +101,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_transmission_vjp.argtypes = [vp, dp, i32, dp, dp, dp]
     lib.tsg_apply_operator.argtypes = [vp, vp, vp, i32, i64, i32]
     lib.tsg_dense_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.tsg_dense_eig_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.tsg_last_error.argtypes = [vp]
     lib.tsg_last_error.restype = C.c_char_p
     lib.tsg_destroy.argtypes = [vp]
@@ -351,3 +352,23 @@ def dense_eig(H, stream=None):
                           C.c_void_p(Y.data_ptr()), C.c_void_p(info.data_ptr()), C.c_void_p(st) if st else None)
     _check(lib, None, s)
     return theta, Y, info
+
+
+def dense_eig_noalloc(H, theta, Y, info, stream=None):
+    """tsg_dense_eig_noalloc: the batched dense eigen-decomposition into
+    caller-provided outputs with the library's fixed device scratch (no
+    allocation, no synchronisation).  H (batch, m, m) complex128 is
+    overwritten; theta (batch, m), Y (batch, m, m) complex128 and info
+    (batch,) int32 are outputs."""
+    import torch
+    lib = load()
+    assert H.is_cuda and H.dtype == torch.complex128 and H.dim() == 3 and H.is_contiguous()
+    b, m, _ = H.shape
+    assert theta.shape == (b, m) and theta.dtype == torch.complex128 and theta.is_contiguous()
+    assert Y.shape == (b, m, m) and Y.dtype == torch.complex128 and Y.is_contiguous()
+    assert info.shape == (b,) and info.dtype == torch.int32
+    st = _stream_handle(stream)
+    s = lib.tsg_dense_eig_noalloc(C.c_void_p(H.data_ptr()), m, b, C.c_void_p(theta.data_ptr()),
+                                  C.c_void_p(Y.data_ptr()), C.c_void_p(info.data_ptr()),
+                                  C.c_void_p(st) if st else None)
+    _check(lib, None, s)

@@ -317,6 +317,16 @@ tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y
   });
 }
 
+tsg_status tsg_dense_eig_noalloc(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info,
+                                 void* hip_stream) {
+  std::string why;
+  if (!device_ok(why)) return fail(nullptr, TSG_EDEVICE, why);
+  return guarded(nullptr, [&]() {
+    tsg::dense_eig_noalloc(H, m, batch, theta, Y, info, static_cast<hipStream_t>(hip_stream));
+    return TSG_OK;
+  });
+}
+
 const char* tsg_last_error(const tsg_ctx* ctx) {
   if (ctx && !ctx->err.empty()) return ctx->err.c_str();
   return g_last_error.c_str();

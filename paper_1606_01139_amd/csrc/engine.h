@@ -133,5 +133,9 @@ void transmission(tsg_ctx* c, const double* E, int nE, double* T);
 // throws NotConverged.
 int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, double* dV, double* dabs);
 void dense_eig(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st);
+// The same with its workspace in the fixed per-device scratch (noalloc.hip):
+// allocates nothing and returns without synchronising.
+void dense_eig_noalloc(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st);
+int64_t noalloc_scratch_bytes();
 
 }  // namespace tsg
