@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--basis", type=int, default=0)
     ap.add_argument("--keep", type=int, default=0)
     ap.add_argument("--groups", type=int, default=0, help="window groups iterating concurrently (0: library default)")
+    ap.add_argument("--extraction", default="ritz", choices=["ritz", "harmonic"],
+                    help="Ritz or harmonic Ritz pairs for the window shifts")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--k4-only", action="store_true",
                     help="time only the batched small eigensolve at the solve's shape and print its roofline object")
@@ -431,6 +433,7 @@ def main():
             o.keep = args.keep
         if args.groups:
             o.groups = args.groups
+        o.extraction = 1 if args.extraction == "harmonic" else 0
         return o
 
     opts = make_opts(prec)
@@ -483,7 +486,7 @@ def main():
                    "hole_filling": oper.fill,
                    "status": int(status), "e_range": [round(x, 6) for x in erange],
                    "planner": args.plan, "plan_seconds_last_step": round(oper.plan_seconds, 3),
-                   "block": b, "basis": m, "groups": opts.groups,
+                   "block": b, "basis": m, "groups": opts.groups, "extraction": args.extraction,
                    "steps_requested": args.steps, "warmup_requested": args.warmup,
                    "budget_s": args.budget},
         "roofline": roof,

@@ -50,6 +50,7 @@ enum { TSG_FP64 = 0, TSG_FP32_BULK = 1 };                 /* tsg_opts.precision 
 enum { TSG_PLAN_ALG1 = 0, TSG_PLAN_EQUAL = 1, TSG_PLAN_SAMPLED = 2, TSG_PLAN_SEMICLASSICAL = 3 }; /* tsg_plan_windows mode */
 enum { TSG_SELECT_NEAREST = 0, TSG_SELECT_SMALLEST_REAL = 1, TSG_SELECT_LARGEST_REAL = 2 };
 enum { TSG_C128 = 0, TSG_C64 = 1 };                       /* element types of device blocks */
+enum { TSG_EXTRACT_RITZ = 0, TSG_EXTRACT_HARMONIC = 1 };   /* tsg_opts.extraction */
 
 typedef struct tsg_ctx tsg_ctx;
 
@@ -93,6 +94,11 @@ typedef struct {
                            iteration on its own internal stream and host thread, so that the groups'
                            small eigensolves and expansion steps can overlap (default 1: one batch,
                            the faster choice measured on MI355X) */
+  int32_t extraction;   /* TSG_EXTRACT_RITZ (default): Ritz pairs of V^H A V nearest the shift;
+                           TSG_EXTRACT_HARMONIC: harmonic Ritz pairs for the shift (the pairs
+                           (sigma + nu, V y) with ((A - sigma) V)^H ((A - sigma) V y - nu V y) = 0, the
+                           cheap variant of the mixed inversion Section 2 proposes for interior
+                           windows), ordered by |nu| and estimated by their Rayleigh quotients */
 } tsg_opts;
 
 /* Per-window solver statistics of the last solve. */

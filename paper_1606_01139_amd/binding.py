@@ -23,6 +23,7 @@ FP64, FP32_BULK = 0, 1
 PLAN_ALG1, PLAN_EQUAL, PLAN_SAMPLED, PLAN_SEMICLASSICAL = 0, 1, 2, 3
 SELECT_NEAREST, SELECT_SMALLEST_REAL, SELECT_LARGEST_REAL = 0, 1, 2
 C128, C64 = 0, 1
+EXTRACT_RITZ, EXTRACT_HARMONIC = 0, 1
 
 # Every symbol include/transec_gpu.h declares.
 EXPORTS = [
@@ -52,7 +53,7 @@ class TsgOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("basis", C.c_int32),
                 ("keep", C.c_int32), ("max_restarts", C.c_int32), ("seed", C.c_uint64),
                 ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double),
-                ("graphs", C.c_int32), ("groups", C.c_int32)]
+                ("graphs", C.c_int32), ("groups", C.c_int32), ("extraction", C.c_int32)]
 
 
 class TsgWindowStats(C.Structure):

@@ -101,6 +101,7 @@ void tsg_default_opts(tsg_opts* o) {
   o->bulk_tol = 1e-5;
   o->graphs = 1;
   o->groups = 1;
+  o->extraction = TSG_EXTRACT_RITZ;
 }
 
 tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab, void* hip_stream,

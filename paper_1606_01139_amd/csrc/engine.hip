@@ -165,6 +165,8 @@ struct SolveStream {
 template <typename T> struct Batch {
   int nw = 0, m = 0, k = 0, b = 0, nv = 0;
   uint64_t seed = 0;
+  bool harmonic = false;
+  DevArr<c128> Hs, Lh, Xh, XG;  // harmonic extraction: saved H, LU and solution scratch, restart update
   int64_t ldN = 0;
   Rows rows;
   DevArr<cplx<T>> V, AV, Vr, AR, Ft;
@@ -197,6 +199,11 @@ template <typename T> struct Batch {
     flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
     wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * b); na.alloc(size_t(nw) * b);
     bfloor.alloc(size_t(nw)); nbreak.alloc(size_t(nw));
+  }
+  void alloc_harmonic() {
+    harmonic = true;
+    Hs.alloc(size_t(m) * m * nw); Lh.alloc(size_t(m) * m * nw); Xh.alloc(size_t(m) * b * nw);
+    XG.alloc(size_t(m) * b * nw);
   }
   int64_t ws() const { return ldN * (m + b); }
   int64_t wsc() const { return int64_t(m + b) * 2 * b; }
@@ -359,6 +366,13 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
         orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
       } else {
         copy_block<T, T>(B.Vr.p + m * ldN, ldN, wsV, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
+        if (B.harmonic) {
+          // harmonic vectors have their residuals along F - V X G: continue
+          // from that block (the old basis is still intact in Vr)
+          gemm_cols<T>(B.Vr.p, ldN, wsV, B.XG.p, b, int64_t(m) * b, B.V.p + k * ldN, ldN, wsV, rows, m, b, 1.0, nw,
+                       st, wm, -1.0);
+          orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
+        }
       }
     }
     for (int j = jstart; j < m; j += b) expand_step<T>(S, B, j);
@@ -366,10 +380,20 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
     stencil<T>(S, B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, m, nw, wm);
     gram<T, T>(B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, rows, m, m, B.H.p, m, int64_t(m) * m, nw, B.part.p,
                int64_t(B.part.n), st, wm);
+    if (B.harmonic) {
+      // harmonic Ritz pairs: eigenpairs of H + (H - sigma)^{-H} E (F^H F) E^T,
+      // F^H F being the Gram of the block the last step left pending
+      check(hipMemcpyAsync(B.Hs.p, B.H.p, sizeof(c128) * size_t(m) * m * nw, hipMemcpyDeviceToDevice, st), "Hs");
+      harmonic_update(B.H.p, int64_t(m) * m, m, b, B.sig.p, B.G.p, B.Rinv.p, int64_t(b) * b, B.Lh.p, int64_t(m) * m,
+                      B.Xh.p, int64_t(m) * b, B.XG.p, nw, st, wm);
+    }
     smalleig(B.H.p, int64_t(m) * m, m, B.theta.p, m, B.Ys.p, int64_t(m) * m, B.work.p, smalleig_workspace(m),
              B.info.p, nw, st, wm);
     select_restart(B.theta.p, m, B.Ys.p, int64_t(m) * m, m, B.sig.p, mode, k, nv, B.Ysel.p, int64_t(m) * (k + nv),
                    B.thsel.p, nv, nw, st, wm);
+    if (B.harmonic)  // eigenvalue estimates of the wanted harmonic vectors
+      rayleigh_quotients(B.Hs.p, int64_t(m) * m, m, B.Ysel.p, int64_t(m) * (k + nv), k + nv, k, nv, B.thsel.p, nv, nw,
+                         st, wm);
     // rotation [V Q_k | V Y_nev], then A times the wanted Ritz vectors
     gemm_cols<T>(B.V.p, ldN, wsV, B.Ysel.p, k + nv, int64_t(m) * (k + nv), B.Vr.p, ldN, wsV, rows, m, k + nv, 0.0,
                  nw, st, wm);
@@ -601,6 +625,11 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
   if (o.max_restarts < 1) throw InvalidArg("max_restarts must be >= 1");
   if (o.precision != TSG_FP64 && o.precision != TSG_FP32_BULK) throw InvalidArg("unknown precision");
   if (o.select < 0 || o.select > 2) throw InvalidArg("unknown selection");
+  if (o.extraction != TSG_EXTRACT_RITZ && o.extraction != TSG_EXTRACT_HARMONIC)
+    throw InvalidArg("unknown extraction");
+  if (o.extraction == TSG_EXTRACT_HARMONIC && o.select != TSG_SELECT_NEAREST)
+    throw InvalidArg("harmonic extraction targets the shift: it needs TSG_SELECT_NEAREST");
+  const bool harmonic = o.extraction == TSG_EXTRACT_HARMONIC;
   int m, k, b;
   choose_sizes(S.Nmin, nvmax, o, m, k, b);
   if (int64_t(m) >= S.Nmin) throw InvalidArg("grid too small for the basis size");
@@ -632,6 +661,7 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
     {
       Batch<float> Bf;
       Bf.alloc(nw, S, m, k, b, nvmax);
+      if (harmonic) Bf.alloc_harmonic();
       std::vector<WinOut> fo;
       const double btol = std::max(o.bulk_tol > 0 ? o.bulk_tol : 1e-5, o.tol);
       iterate<float>(S, Bf, wins, normA, o.select, btol, o.max_restarts, o.seed, nullptr, fo, [&](int w) {
@@ -651,11 +681,13 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
     }
     Batch<double> Bd;
     Bd.alloc(nw, S, m, k, b, nvmax);
+    if (harmonic) Bd.alloc_harmonic();
     iterate<double>(S, Bd, wins, normA, o.select, itol, o.max_restarts, o.seed + 1, hand.p, outs, save_fp64(Bd),
                     use_graphs, 0.0, true);
   } else {
     Batch<double> Bd;
     Bd.alloc(nw, S, m, k, b, nvmax);
+    if (harmonic) Bd.alloc_harmonic();
     iterate<double>(S, Bd, wins, normA, o.select, itol, o.max_restarts, o.seed, nullptr, outs, save_fp64(Bd),
                     use_graphs);
   }
@@ -1060,6 +1092,7 @@ double smallest_real_part(tsg_ctx* c, const tsg_opts& o) {
   oe.basis = 0;
   oe.keep = 0;
   oe.select = TSG_SELECT_SMALLEST_REAL;
+  oe.extraction = TSG_EXTRACT_RITZ;  // an exterior end: ordinary Ritz pairs
   oe.max_restarts = std::max(o.max_restarts, 2000);
   const bool ok = solve_windows(c, {WindowSpec{0.0, 1}}, oe);
   const bool found = ok && !c->parts.back().eps.empty();

@@ -159,6 +159,19 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
                     int mode, int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss,
                     int nwin, hipStream_t st, const int* wmap = nullptr);
 
+// Harmonic Ritz extraction (harmonic.hip): H[w] (m x m) += X G E^T with
+// X = (H - sigma)^{-H} E, E the last b columns of the identity, G = F^H F
+// (b x b, upper Cholesky factor inverse Rinv, same stride wsg); XG (m x b)
+// gets X G Rinv, the basis combination to subtract from the pending block at
+// the restart.  L (m x m) and X (m x b) per window are scratch.
+void harmonic_update(c128* H, int64_t wsh, int m, int b, const double* sigma, const c128* G, const c128* Rinv,
+                     int64_t wsg, c128* L, int64_t wsl, c128* X, int64_t wsx, c128* XG, int nwin, hipStream_t st,
+                     const int* wmap = nullptr);
+// theta[w*wst + i] = y^H H y / y^H y for y = column off + i of Y (row-major
+// m x ld), i < nev.
+void rayleigh_quotients(const c128* H, int64_t wsh, int m, const c128* Y, int64_t wsy, int ld, int off, int nev,
+                        c128* theta, int64_t wst, int nwin, hipStream_t st, const int* wmap = nullptr);
+
 // ---------------------------------------------------------------- K7/K8
 // Transmission: T[e] = Re sum_kl g_k conj(g_l) W_kl, g_k = 1/(E_e - eps_k).
 void transmission_sweep(const c128* W, int n, const c128* eps, const double* E, int nE, double* T,

@@ -56,12 +56,14 @@ def _check_vectors(U, Uref, A, eps, nrm, eps_all):
         assert np.linalg.norm(r) / (nrm * np.linalg.norm(U[:, k])) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_c1_partitioned_solve_and_transmission(torch_cuda, precision):
+@pytest.mark.parametrize("precision,extraction", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_c1_partitioned_solve_and_transmission(torch_cuda, precision, extraction):
+    """c1 against the dense oracle, with Ritz (extraction 0) and harmonic Ritz
+    (extraction 1) pairs: the converged set is the same."""
     from oracle import eigen, partition, transport
     from paper_1606_01139_amd import Operator, default_opts
     from synth.workloads import workload
-    print(f"c1 solve precision={precision}", flush=True)
+    print(f"c1 solve precision={precision} extraction={extraction}", flush=True)
     w = workload("c1")
     g = w.grid
     A, gL, gR, ea, Ua, nrm = _setup(w)
@@ -69,7 +71,8 @@ def test_c1_partitioned_solve_and_transmission(torch_cuda, precision):
     shifts = [0.5 * (ea[0].real + ea[19].real), 0.5 * (ea[20].real + ea[39].real)]
     nev = w.nev_per_window
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
-    n, holes, _ = oper.solve_all_partitions([(s, nev) for s in shifts], default_opts(precision=precision))
+    n, holes, _ = oper.solve_all_partitions([(s, nev) for s in shifts],
+                                            default_opts(precision=precision, extraction=extraction))
     ref = partition.combine([eigen.window_from_spectrum(ea, Ua, s, nev) for s in shifts], nrm)
     eps = oper.eigenvalues()
     _match_sets(eps, ref.eps, 1e-10)
@@ -87,17 +90,18 @@ def test_c1_partitioned_solve_and_transmission(torch_cuda, precision):
     oper.close()
 
 
-def test_single_partition_ragged_grid(torch_cuda):
+@pytest.mark.parametrize("extraction", [0, 1])
+def test_single_partition_ragged_grid(torch_cuda, extraction):
     from oracle import eigen
     from paper_1606_01139_amd import Operator, default_opts
     from synth.workloads import small_workload
     w = small_workload(9, 7, 13, 3, seed=17)
     g = w.grid
-    print("ragged single partition 9x7x13", flush=True)
+    print(f"ragged single partition 9x7x13 extraction={extraction}", flush=True)
     A, gL, gR, ea, Ua, nrm = _setup(w)
     sigma = float(ea[11].real) + 0.01
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
-    nconv = oper.solve_partition(sigma, 7, default_opts(basis=64, keep=32))
+    nconv = oper.solve_partition(sigma, 7, default_opts(basis=64, keep=32, extraction=extraction))
     assert nconv == 7
     eps, Ud = oper.partition(0)
     e_ref, U_ref = eigen.window_from_spectrum(ea, Ua, sigma, 7)
