@@ -70,10 +70,16 @@ typedef struct {
   double amp_R, width_R, z_R;
 } tsg_absorber;
 
-/* One spectral partition (Eq. (3)): real shift E_{S,j} and count n_{r,j}. */
+/* One spectral partition (Eq. (3)): shift E_{S,j} and count n_{r,j}.  The
+ * shift is real (shift_im = 0) on the paper's one-dimensional partitioning;
+ * a nonzero shift_im places the window in the complex plane (the
+ * two-dimensional partitioning Section 2 proposes for strongly
+ * non-Hermitian operators, whose eigenvalues spread down to -max Gamma,
+ * Eq. (5)). */
 typedef struct {
   double shift;
   int32_t nev;
+  double shift_im;
 } tsg_window;
 
 /* Solver options.  tsg_default_opts() fills every field. */
@@ -94,6 +100,10 @@ typedef struct {
                            iteration on its own internal stream and host thread, so that the groups'
                            small eigensolves and expansion steps can overlap (default 1: one batch,
                            the faster choice measured on MI355X) */
+  int32_t imag_bands;   /* tsg_plan_windows, TSG_PLAN_SEMICLASSICAL: q >= 1 (default 1).  With q > 1
+                           the p windows are p/q real placements of n_r/(p/q) pairs, each split into
+                           q windows at imaginary shifts -max(Gamma) (i + 1/2)/q, i < q, of equal
+                           counts (two-dimensional partitioning); p must be a multiple of q */
   int32_t extraction;   /* TSG_EXTRACT_RITZ (default): Ritz pairs of V^H A V nearest the shift;
                            TSG_EXTRACT_HARMONIC: harmonic Ritz pairs for the shift (the pairs
                            (sigma + nu, V y) with ((A - sigma) V)^H ((A - sigma) V y - nu V y) = 0, the
@@ -103,7 +113,7 @@ typedef struct {
 
 /* Per-window solver statistics of the last solve. */
 typedef struct {
-  double shift;
+  double shift;             /* real part of the window's shift */
   int32_t nev;
   int32_t n_conv;
   int32_t restarts;
@@ -115,6 +125,7 @@ typedef struct {
                                random block orthonormal to the basis */
   int32_t cnorm_failures;   /* converged pairs dropped because u^T u vanished (|u^T u| < 1e-10 ||u||^2):
                                such a vector cannot be c-normalised (bi-orthogonality of Section 1 fails) */
+  double shift_im;          /* imaginary part of the window's shift */
 } tsg_window_stats;
 
 /* Fills *opts with the defaults listed in tsg_opts. */
@@ -297,6 +308,30 @@ tsg_status tsg_apply_operator(tsg_ctx* ctx, const void* X, void* Y, int32_t ncol
  * hip_stream as in tsg_build_operator.  Errors: TSG_EINVAL (null pointer,
  * m or batch out of range; nothing launched), TSG_ENOMEM, TSG_EDEVICE. */
 tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info, void* hip_stream);
+
+/* Autotuner of the stencil launch geometry (the matrix-vector product
+ * formula of Section 1, applied to many vectors at once).  Every candidate
+ * (tile width 16/32/64, one or two points per thread in y, z chunk of
+ * 16..192 planes) is timed on ctx's grid for a launch of ncols vectors of
+ * element type dtype (reps launches each, HIP events on ctx's stream); the
+ * fastest is recorded in the process-wide table that every later stencil
+ * launch with the same grid shape, column count, element size and radius
+ * uses.  Solver launches cover (windows x columns) vectors, which is the
+ * count to tune for.
+ *   path:     if not NULL, the whole table is written there as JSON
+ *             ({"stencil": [{nx, ny, nz, cols, elem, radius, tx, yb, zchunk, us}, ...]});
+ *   geometry: host, 4 outputs or NULL: tx, yb, zchunk, candidates timed;
+ *   best_us:  host, or NULL: the best time per launch in microseconds.
+ * Allocates two N x ncols blocks while it runs and synchronises ctx's stream.
+ * Errors: TSG_EINVAL (ncols, reps < 1, dtype, unwritable path), TSG_ENOMEM,
+ * TSG_EDEVICE. */
+tsg_status tsg_tune_stencil(tsg_ctx* ctx, int32_t ncols, int32_t dtype, int32_t reps, const char* path,
+                            int32_t* geometry, double* best_us);
+
+/* Loads a tuning file written by tsg_tune_stencil into the process-wide
+ * table (entries with the same key are replaced).  *n_entries (or NULL) gets
+ * the number read.  Errors: TSG_EINVAL (unreadable or malformed file). */
+tsg_status tsg_load_tuning(const char* path, int32_t* n_entries);
 
 /* tsg_dense_eig for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

@@ -153,6 +153,22 @@ def sampled_windows(e_min: float, samples: Sequence[np.ndarray], counts: Sequenc
     return shifts
 
 
+def imaginary_bands(real_windows: Sequence[Tuple[float, int]], gamma_max: float, q: int) -> List[Tuple[complex, int]]:
+    """Two-dimensional partitioning (Section 2's remark for strongly
+    non-Hermitian operators): every real window (shift, n) becomes q windows
+    at shifts shift - i gamma_max (i + 1/2)/q, i < q, which split n as evenly
+    as integers allow (the larger counts first, at least 1 each).  By Eq. (5)
+    the eigenvalues' imaginary parts lie in [-gamma_max, 0], so the bands
+    tile that range."""
+    out = []
+    for shift, n in real_windows:
+        base = n // q
+        for i in range(q):
+            cnt = max(base + (1 if i < n - base * q else 0), 1)
+            out.append((complex(shift, -gamma_max * (i + 0.5) / q), cnt))
+    return out
+
+
 def box_lengths(shape, h: float):
     """Edges of the Dirichlet box: the grid plus one spacing (the zero
     values sit one step outside the first and last points)."""

@@ -30,7 +30,7 @@ EXPORTS = [
     "tsg_default_opts", "tsg_build_operator", "tsg_plan_windows", "tsg_solve_partition",
     "tsg_solve_all_partitions", "tsg_fill_holes", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
     "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_transmission_vjp", "tsg_apply_operator",
-    "tsg_dense_eig", "tsg_dense_eig_noalloc",
+    "tsg_dense_eig", "tsg_dense_eig_noalloc", "tsg_tune_stencil", "tsg_load_tuning",
     "tsg_last_error", "tsg_destroy",
 ]
 
@@ -46,20 +46,31 @@ class TsgAbsorber(C.Structure):
 
 
 class TsgWindow(C.Structure):
-    _fields_ = [("shift", C.c_double), ("nev", C.c_int32)]
+    _fields_ = [("shift", C.c_double), ("nev", C.c_int32), ("shift_im", C.c_double)]
+
+
+def _window(shift, nev) -> TsgWindow:
+    """tsg_window from a real or complex shift."""
+    z = complex(shift)
+    return TsgWindow(z.real, int(nev), z.imag)
+
+
+def _shift_of(w: TsgWindow):
+    return complex(w.shift, w.shift_im) if w.shift_im != 0.0 else w.shift
 
 
 class TsgOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("basis", C.c_int32),
                 ("keep", C.c_int32), ("max_restarts", C.c_int32), ("seed", C.c_uint64),
                 ("keep_lowest", C.c_int32), ("select", C.c_int32), ("bulk_tol", C.c_double),
-                ("graphs", C.c_int32), ("groups", C.c_int32), ("extraction", C.c_int32)]
+                ("graphs", C.c_int32), ("groups", C.c_int32), ("imag_bands", C.c_int32),
+                ("extraction", C.c_int32)]
 
 
 class TsgWindowStats(C.Structure):
     _fields_ = [("shift", C.c_double), ("nev", C.c_int32), ("n_conv", C.c_int32), ("restarts", C.c_int32),
                 ("matvecs", C.c_int64), ("max_backward_error", C.c_double), ("restarts_bulk", C.c_int32),
-                ("breakdowns", C.c_int32), ("cnorm_failures", C.c_int32)]
+                ("breakdowns", C.c_int32), ("cnorm_failures", C.c_int32), ("shift_im", C.c_double)]
 
 
 class TsgError(RuntimeError):
@@ -70,6 +81,7 @@ class TsgError(RuntimeError):
 
 
 _LIB: Optional[C.CDLL] = None
+DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "stencil_gfx950.json")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -103,6 +115,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_apply_operator.argtypes = [vp, vp, vp, i32, i64, i32]
     lib.tsg_dense_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.tsg_dense_eig_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.tsg_tune_stencil.argtypes = [vp, i32, i32, i32, C.c_char_p, C.POINTER(i32), dp]
+    lib.tsg_load_tuning.argtypes = [C.c_char_p, C.POINTER(i32)]
     lib.tsg_last_error.argtypes = [vp]
     lib.tsg_last_error.restype = C.c_char_p
     lib.tsg_destroy.argtypes = [vp]
@@ -112,6 +126,12 @@ def load(path: Optional[str] = None) -> C.CDLL:
         if f.restype is C.c_int:  # default restype
             f.restype = C.c_int
     _LIB = lib
+    # stencil geometries measured by the autotuner (tune.py), if present
+    tpath = os.environ.get("TSG_TUNING_FILE") or DEFAULT_TUNING
+    if tpath and os.path.exists(tpath):
+        n = C.c_int32()
+        if lib.tsg_load_tuning(tpath.encode(), C.byref(n)) != TSG_OK:
+            raise RuntimeError(f"tuning file {tpath}: {lib.tsg_last_error(None).decode(errors='replace')}")
     return lib
 
 
@@ -170,6 +190,7 @@ class WindowStats:
     restarts_bulk: int
     breakdowns: int = 0
     cnorm_failures: int = 0
+    shift_im: float = 0.0
 
 
 class Operator:
@@ -219,11 +240,11 @@ class Operator:
         er = (C.c_double * 2)()
         s = self.lib.tsg_plan_windows(self.ctx, n_r, p, mode, C.byref(opts) if opts else None, out, er)
         _check(self.lib, self.ctx, s)
-        return [(w.shift, w.nev) for w in out], (er[0], er[1])
+        return [(_shift_of(w), w.nev) for w in out], (er[0], er[1])
 
     def solve_partition(self, shift: float, nev: int, opts: Optional[TsgOpts] = None, allow_noconv=False) -> int:
         n = C.c_int32()
-        s = self.lib.tsg_solve_partition(self.ctx, TsgWindow(shift, nev), C.byref(opts) if opts else None,
+        s = self.lib.tsg_solve_partition(self.ctx, _window(shift, nev), C.byref(opts) if opts else None,
                                          C.byref(n))
         _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
         return n.value
@@ -231,7 +252,7 @@ class Operator:
     def solve_all_partitions(self, windows: Sequence[Tuple[float, int]], opts: Optional[TsgOpts] = None,
                              allow_noconv=False):
         p = len(windows)
-        arr = (TsgWindow * p)(*[TsgWindow(float(s), int(n)) for s, n in windows])
+        arr = (TsgWindow * p)(*[_window(s, n) for s, n in windows])
         n = C.c_int32()
         holes = (C.c_uint8 * max(p - 1, 1))()
         s = self.lib.tsg_solve_all_partitions(self.ctx, arr, p, C.byref(opts) if opts else None, C.byref(n),
@@ -294,7 +315,18 @@ class Operator:
         s = self.lib.tsg_get_stats(self.ctx, j, C.byref(st))
         _check(self.lib, self.ctx, s)
         return WindowStats(st.shift, st.nev, st.n_conv, st.restarts, st.matvecs, st.max_backward_error,
-                           st.restarts_bulk, st.breakdowns, st.cnorm_failures)
+                           st.restarts_bulk, st.breakdowns, st.cnorm_failures, st.shift_im)
+
+    def tune_stencil(self, ncols: int, dtype: int = C128, reps: int = 10, path: Optional[str] = None):
+        """tsg_tune_stencil: times every candidate stencil geometry for a
+        launch of ncols vectors on this grid and keeps the fastest.  Returns
+        ({tx, yb, zchunk, tried}, best microseconds per launch)."""
+        g = (C.c_int32 * 4)()
+        us = C.c_double()
+        s = self.lib.tsg_tune_stencil(self.ctx, int(ncols), int(dtype), int(reps),
+                                      path.encode() if path else None, g, C.byref(us))
+        _check(self.lib, self.ctx, s)
+        return {"tx": g[0], "yb": g[1], "zchunk": g[2], "tried": g[3]}, us.value
 
     def transmission(self, energies: Sequence[float]) -> np.ndarray:
         E = np.ascontiguousarray(energies, dtype=np.float64)
@@ -327,7 +359,7 @@ def solve_batch(operators: Sequence["Operator"], windows: Sequence[Sequence[Tupl
     lib = load()
     ns = len(operators)
     ctxs = (C.c_void_p * ns)(*[op.ctx for op in operators])
-    arrs = [(TsgWindow * len(w))(*[TsgWindow(float(s), int(n)) for s, n in w]) for w in windows]
+    arrs = [(TsgWindow * len(w))(*[_window(s, n) for s, n in w]) for w in windows]
     ptrs = (C.POINTER(TsgWindow) * ns)(*[C.cast(a, C.POINTER(TsgWindow)) for a in arrs])
     p = (C.c_int32 * ns)(*[len(w) for w in windows])
     nu = (C.c_int32 * ns)()
@@ -373,3 +405,11 @@ def dense_eig_noalloc(H, theta, Y, info, stream=None):
                                   C.c_void_p(Y.data_ptr()), C.c_void_p(info.data_ptr()),
                                   C.c_void_p(st) if st else None)
     _check(lib, None, s)
+
+
+def load_tuning(path: str) -> int:
+    """tsg_load_tuning: reads a stencil tuning file into the library's table."""
+    lib = load()
+    n = C.c_int32()
+    _check(lib, None, lib.tsg_load_tuning(path.encode(), C.byref(n)))
+    return n.value

@@ -102,6 +102,7 @@ void tsg_default_opts(tsg_opts* o) {
   o->graphs = 1;
   o->groups = 1;
   o->extraction = TSG_EXTRACT_RITZ;
+  o->imag_bands = 1;
 }
 
 tsg_status tsg_build_operator(const tsg_grid* grid, const double* V, const tsg_absorber* ab, void* hip_stream,
@@ -142,7 +143,8 @@ tsg_status tsg_plan_windows(tsg_ctx* ctx, int32_t n_r, int32_t p, int32_t mode, 
     if (opts) o = *opts; else tsg_default_opts(&o);
     std::vector<tsg::WindowSpec> w;
     tsg::plan_windows(ctx, n_r, p, mode, o, w, e_range);
-    for (int j = 0; j < p; ++j) { out[j].shift = w[j].shift; out[j].nev = w[j].nev; }
+    if (int(w.size()) != p) throw tsg::InvalidArg("planner produced a different number of windows");
+    for (int j = 0; j < p; ++j) { out[j].shift = w[j].shift; out[j].nev = w[j].nev; out[j].shift_im = w[j].shift_im; }
     return TSG_OK;
   });
 }
@@ -153,7 +155,7 @@ tsg_status tsg_solve_partition(tsg_ctx* ctx, tsg_window win, const tsg_opts* opt
     tsg_opts o;
     if (opts) o = *opts; else tsg_default_opts(&o);
     const size_t first = ctx->parts.size();
-    const bool ok = tsg::solve_windows(ctx, {tsg::WindowSpec{win.shift, win.nev}}, o);
+    const bool ok = tsg::solve_windows(ctx, {tsg::WindowSpec{win.shift, win.nev, win.shift_im}}, o);
     if (n_conv) *n_conv = ctx->parts.back().stats.n_conv;
     return solve_status(ctx, first, ok);
   });
@@ -178,7 +180,7 @@ tsg_status tsg_solve_all_partitions(tsg_ctx* ctx, const tsg_window* windows, int
     tsg_opts o;
     if (opts) o = *opts; else tsg_default_opts(&o);
     std::vector<tsg::WindowSpec> w(p);
-    for (int j = 0; j < p; ++j) w[j] = tsg::WindowSpec{windows[j].shift, windows[j].nev};
+    for (int j = 0; j < p; ++j) w[j] = tsg::WindowSpec{windows[j].shift, windows[j].nev, windows[j].shift_im};
     ctx->parts.clear();
     const bool ok = tsg::solve_windows(ctx, w, o);
     tsg::combine(ctx, o.keep_lowest);
@@ -218,7 +220,7 @@ tsg_status tsg_solve_batch(tsg_ctx* const* ctx, int32_t n_sys, const tsg_window*
     std::vector<tsg_ctx*> cs(ctx, ctx + n_sys);
     std::vector<std::vector<tsg::WindowSpec>> w(n_sys);
     for (int s = 0; s < n_sys; ++s)
-      for (int j = 0; j < p[s]; ++j) w[s].push_back(tsg::WindowSpec{windows[s][j].shift, windows[s][j].nev});
+      for (int j = 0; j < p[s]; ++j) w[s].push_back(tsg::WindowSpec{windows[s][j].shift, windows[s][j].nev, windows[s][j].shift_im});
     std::vector<bool> ok;
     tsg::solve_batch(cs, w, o, ok);
     bool all = true;
@@ -324,6 +326,28 @@ tsg_status tsg_dense_eig_noalloc(void* H, int32_t m, int32_t batch, void* theta,
   if (!device_ok(why)) return fail(nullptr, TSG_EDEVICE, why);
   return guarded(nullptr, [&]() {
     tsg::dense_eig_noalloc(H, m, batch, theta, Y, info, static_cast<hipStream_t>(hip_stream));
+    return TSG_OK;
+  });
+}
+
+tsg_status tsg_tune_stencil(tsg_ctx* ctx, int32_t ncols, int32_t dtype, int32_t reps, const char* path,
+                            int32_t* geometry, double* best_us) {
+  if (!ctx) return fail(ctx, TSG_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&]() {
+    int tried = 0;
+    const tsg::StencilTuneEntry e = tsg::tune_stencil(ctx, ncols, dtype, reps, &tried);
+    if (path) tsg::write_tuning(path);
+    if (geometry) { geometry[0] = e.g.tx; geometry[1] = e.g.yb; geometry[2] = e.g.zchunk; geometry[3] = tried; }
+    if (best_us) *best_us = e.us;
+    return TSG_OK;
+  });
+}
+
+tsg_status tsg_load_tuning(const char* path, int32_t* n_entries) {
+  if (!path) return fail(nullptr, TSG_EINVAL, "path is NULL");
+  return guarded(nullptr, [&]() {
+    const int n = tsg::load_tuning(path);
+    if (n_entries) *n_entries = n;
     return TSG_OK;
   });
 }

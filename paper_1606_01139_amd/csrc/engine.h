@@ -62,7 +62,7 @@ template <typename T> struct DevArr {
 };
 
 struct Partition {
-  double shift = 0.0;
+  double shift = 0.0, shift_im = 0.0;
   int nev = 0;
   std::vector<c128> eps;   // ascending real part
   DevArr<c128> U;          // N x n, contiguous columns (ld = N), c-normalised
@@ -72,6 +72,7 @@ struct Partition {
 struct WindowSpec {
   double shift;
   int nev;
+  double shift_im = 0.0;
 };
 
 }  // namespace tsg
@@ -137,5 +138,9 @@ void dense_eig(void* H, int m, int batch, void* theta, void* Y, int* info, hipSt
 // allocates nothing and returns without synchronising.
 void dense_eig_noalloc(void* H, int m, int batch, void* theta, void* Y, int* info, hipStream_t st);
 int64_t noalloc_scratch_bytes();
+// Stencil autotuner (tune.hip).
+StencilTuneEntry tune_stencil(tsg_ctx* c, int ncols, int dtype, int reps, int* n_tried);
+void write_tuning(const std::string& path);
+int load_tuning(const std::string& path);
 
 }  // namespace tsg

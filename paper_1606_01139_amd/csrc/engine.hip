@@ -171,7 +171,8 @@ template <typename T> struct Batch {
   Rows rows;
   DevArr<cplx<T>> V, AV, Vr, AR, Ft;
   DevArr<c128> H, Ys, work, theta, Ysel, thsel, C, G, Rinv, Mx, part;
-  DevArr<double> res, sig, nb, na, bfloor;
+  DevArr<double> res, nb, na, bfloor;
+  DevArr<c128> sig;
   DevArr<int> flags, info, wmap, wmap2, sel, nbreak;
 
   void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
@@ -326,9 +327,9 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
     check(hipMemcpyAsync(B.wmap.p, slots.data(), sizeof(int) * nw, hipMemcpyHostToDevice, st), "wmap");
   };
   upload_slots();
-  std::vector<double> shifts(nw);
-  for (int w = 0; w < nw; ++w) shifts[w] = wins[w].shift;
-  check(hipMemcpyAsync(B.sig.p, shifts.data(), sizeof(double) * nw, hipMemcpyHostToDevice, st), "shifts");
+  std::vector<c128> shifts(nw);
+  for (int w = 0; w < nw; ++w) shifts[w] = c128{wins[w].shift, wins[w].shift_im};
+  check(hipMemcpyAsync(B.sig.p, shifts.data(), sizeof(c128) * nw, hipMemcpyHostToDevice, st), "shifts");
   // breakdown floor on the squared norm of a new block column after
   // orthogonalisation: (eta ||A||)^2, eta well above the rounding level of
   // the storage precision
@@ -565,6 +566,7 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
   });
   Partition P;
   P.shift = ws.shift;
+  P.shift_im = ws.shift_im;
   P.nev = ws.nev;
   double maxrho = 0.0;
   std::vector<double> rho(nev);
@@ -598,6 +600,7 @@ Partition finish_window(tsg_ctx* c, hipStream_t st, const WindowSpec& ws, DevArr
     check(hipStreamSynchronize(st), "sync");
   }
   P.stats.shift = ws.shift;
+  P.stats.shift_im = ws.shift_im;
   P.stats.nev = ws.nev;
   P.stats.n_conv = nk;
   P.stats.restarts = o.restarts;
@@ -618,7 +621,7 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
   int nvmax = 0;
   for (const auto& w : wins) {
     if (w.nev < 1) throw InvalidArg("nev must be >= 1");
-    if (!std::isfinite(w.shift)) throw InvalidArg("shift must be finite");
+    if (!std::isfinite(w.shift) || !std::isfinite(w.shift_im)) throw InvalidArg("shift must be finite");
     nvmax = std::max(nvmax, w.nev);
   }
   if (!(o.tol > 0.0) || !std::isfinite(o.tol)) throw InvalidArg("tol must be positive");
@@ -1008,6 +1011,9 @@ void combine(tsg_ctx* c, int keep_lowest) {
 // the cap keeps one window's basis bounded and the loop repeats instead).
 FillResult fill_holes(tsg_ctx* c, double e_min, int n_cap, int max_rounds, const tsg_opts& o) {
   if (c->parts.empty()) throw StateError("no partitions: run a solve first");
+  for (const Partition& P : c->parts)
+    if (P.shift_im != 0.0)
+      throw InvalidArg("hole filling orders partitions along the real axis: every shift must be real");
   if (n_cap < 1 || max_rounds < 0) throw InvalidArg("need n_cap >= 1 and max_rounds >= 0");
   const double e_max = upper_bound_real(c);
   if (!std::isfinite(e_min) || !(e_min < e_max)) throw InvalidArg("e_min must be finite and below E_max");
@@ -1118,6 +1124,24 @@ void plan_windows(tsg_ctx* c, int n_r, int p, int mode, const tsg_opts& o, std::
   if (n_r < 1 || p < 1) throw InvalidArg("need n_r >= 1 and p >= 1");
   if (mode != TSG_PLAN_ALG1 && mode != TSG_PLAN_EQUAL && mode != TSG_PLAN_SAMPLED && mode != TSG_PLAN_SEMICLASSICAL)
     throw InvalidArg("unknown planning mode");
+  const int q = o.imag_bands > 0 ? o.imag_bands : 1;
+  if (q > 1 && (mode != TSG_PLAN_SEMICLASSICAL || p % q != 0))
+    throw InvalidArg("imaginary bands need TSG_PLAN_SEMICLASSICAL and p a multiple of imag_bands");
+  if (q > 1) {
+    // two-dimensional partitioning: p/q real placements, each split into q
+    // windows spread over the imaginary range [-max Gamma, 0] of Eq. (5)
+    tsg_opts o1 = o;
+    o1.imag_bands = 1;
+    std::vector<WindowSpec> re;
+    plan_windows(c, n_r, p / q, mode, o1, re, e_range);
+    out.clear();
+    for (const WindowSpec& r : re)
+      for (int i = 0; i < q; ++i) {
+        const int base = r.nev / q, extra = (i < r.nev - base * q) ? 1 : 0;
+        out.push_back(WindowSpec{r.shift, std::max(base + extra, 1), -c->gmax * (i + 0.5) / q});
+      }
+    return;
+  }
   const double e_min = smallest_real_part(c, o);
   const double e_max = upper_bound_real(c);
   const std::vector<int> counts = window_counts(n_r, p, mode == TSG_PLAN_ALG1 ? TSG_PLAN_ALG1 : TSG_PLAN_EQUAL);

@@ -46,7 +46,7 @@ __device__ inline double hsum(double v, double* red) {
 // (H - sigma)^H X = E, and then H[:, m-b+q] += sum_p X[:, p] G[p, q]
 // (G = F^H F, b x b).  A zero pivot leaves H unchanged for that window.
 __global__ __launch_bounds__(kHT) void harmonic_kernel(c128* Hall, int64_t wsh, int m, int b,
-                                                       const double* __restrict__ sigma, const c128* __restrict__ Gall,
+                                                       const c128* __restrict__ sigma, const c128* __restrict__ Gall,
                                                        const c128* __restrict__ Rall, int64_t wsg, c128* Lall,
                                                        int64_t wsl, c128* Xall, int64_t wsx, c128* XGall,
                                                        const int* __restrict__ wmap) {
@@ -63,13 +63,13 @@ __global__ __launch_bounds__(kHT) void harmonic_kernel(c128* Hall, int64_t wsh, 
   c128* XG = XGall + int64_t(w) * wsx;
   const c128* G = Gall + int64_t(w) * wsg;
   const c128* Ri = Rall + int64_t(w) * wsg;
-  const double sg = sigma[w];
+  const c128 sg = conj(sigma[w]);
   const int t = threadIdx.x;
   // L = (H - sigma)^H
   for (int64_t e = t; e < int64_t(m) * m; e += kHT) {
     const int i = int(e / m), j = int(e % m);
     c128 v = conj(H[int64_t(j) * m + i]);
-    if (i == j) v.re -= sg;
+    if (i == j) v = v - sg;
     L[e] = v;
   }
   for (int e = t; e < m * b; e += kHT) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void rayleigh_kernel(const c128* __restrict__ 
 
 }  // namespace
 
-void harmonic_update(c128* H, int64_t wsh, int m, int b, const double* sigma, const c128* G, const c128* Rinv,
+void harmonic_update(c128* H, int64_t wsh, int m, int b, const c128* sigma, const c128* G, const c128* Rinv,
                      int64_t wsg, c128* L, int64_t wsl, c128* X, int64_t wsx, c128* XG, int nwin, hipStream_t st,
                      const int* wmap) {
   if (nwin <= 0) return;

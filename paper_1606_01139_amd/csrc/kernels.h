@@ -1,5 +1,7 @@
 // Internal kernel launchers of libtransec_gpu.  Not part of the C-ABI.
 #pragma once
+#include <vector>
+
 #include "tsg_common.h"
 
 namespace tsg {
@@ -36,10 +38,49 @@ template <typename T> struct StencilArgs {
   const int* wsys;                         // window -> system index, or null (system 0)
   const int* wmap;                         // launch slot -> window index (< 0: idle), or null
   int tx, ty, zchunk, tiles;               // launch geometry (tiles = largest tile count)
+  int yb;                                  // points per thread stacked in y (1 or 2)
 };
 template <typename T> void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s);
-// Tile geometry for the largest system of a launch.
+// Tile geometry for the largest system of a launch: the tuned one for this
+// shape, launch width and element size when the table has it, else the
+// default rule.
 template <typename T> void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin);
+
+// A stencil launch geometry: tile width tx (512 / tx thread rows), yb points
+// per thread in y, zchunk planes per workgroup.
+struct StencilGeom {
+  int tx = 64, yb = 1, zchunk = 32;
+};
+StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols, int radius);
+template <typename T>
+void stencil_apply_geometry(StencilArgs<T>& a, int nx, int ny, int nz, const StencilGeom& gm);
+// Tuned geometries (filled by the autotuner or read from a tuning file).
+struct StencilTuneEntry {
+  int nx, ny, nz, cols, elem, radius;
+  StencilGeom g;
+  double us;  // measured time per launch
+};
+struct StencilTuneTable {
+  std::vector<StencilTuneEntry> e;
+  bool find(int nx, int ny, int nz, int cols, int elem, int radius, StencilGeom& out) const {
+    for (const auto& x : e)
+      if (x.nx == nx && x.ny == ny && x.nz == nz && x.cols == cols && x.elem == elem && x.radius == radius) {
+        out = x.g;
+        return true;
+      }
+    return false;
+  }
+  void put(const StencilTuneEntry& v) {
+    for (auto& x : e)
+      if (x.nx == v.nx && x.ny == v.ny && x.nz == v.nz && x.cols == v.cols && x.elem == v.elem &&
+          x.radius == v.radius) {
+        x = v;
+        return;
+      }
+    e.push_back(v);
+  }
+};
+StencilTuneTable& stencil_tune_table();
 
 // ---------------------------------------------------------------- dense
 // Batched tall-skinny products over the grid index n < rows.of(w).  Grid
@@ -150,12 +191,12 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, 
                   int64_t wst, int* info, int nwin, hipStream_t st, const int* wmap);
 int64_t schur_log_size(int m);
 
-// Selection by |theta - sigma| (ties: Re, then Im) and restart basis:
+// Selection by |theta - sigma| (sigma complex; ties: Re, then Im) and restart basis:
 // out (m x (k + nev), row-major, ld = k + nev):
 //   columns [0, k): orthonormal basis of the k selected eigenvectors,
 //   columns [k, k + nev): the nev nearest eigenvectors (unit 2-norm).
 // theta_sel[w*(nev)] gets their eigenvalues (nearest first).
-void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const double* sigma,
+void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const c128* sigma,
                     int mode, int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss,
                     int nwin, hipStream_t st, const int* wmap = nullptr);
 
@@ -164,7 +205,7 @@ void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, 
 // (b x b, upper Cholesky factor inverse Rinv, same stride wsg); XG (m x b)
 // gets X G Rinv, the basis combination to subtract from the pending block at
 // the restart.  L (m x m) and X (m x b) per window are scratch.
-void harmonic_update(c128* H, int64_t wsh, int m, int b, const double* sigma, const c128* G, const c128* Rinv,
+void harmonic_update(c128* H, int64_t wsh, int m, int b, const c128* sigma, const c128* G, const c128* Rinv,
                      int64_t wsg, c128* L, int64_t wsl, c128* X, int64_t wsx, c128* XG, int nwin, hipStream_t st,
                      const int* wmap = nullptr);
 // theta[w*wst + i] = y^H H y / y^H y for y = column off + i of Y (row-major

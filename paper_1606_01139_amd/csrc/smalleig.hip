@@ -562,14 +562,14 @@ __global__ void colnorm_kernel(c128* Yall, int64_t wsy, int m, const int* __rest
 }
 
 // ---------------------------------------------------------------- selection
-__device__ inline double sel_key(c128 th, double sigma, int mode) {
+__device__ inline double sel_key(c128 th, c128 sigma, int mode) {
   if (mode == 1) return th.re;        // smallest real part
   if (mode == 2) return -th.re;       // largest real part
-  return cabs(c128{th.re - sigma, th.im});  // nearest the shift
+  return cabs(th - sigma);            // nearest the (complex) shift
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_restart_kernel(const c128* thall, int64_t wst, const c128* Yall,
-                                                             int64_t wsy, int m, const double* sigma, int mode, int k,
+                                                             int64_t wsy, int m, const c128* sigma, int mode, int k,
                                                              int nev, c128* outall, int64_t wso, c128* thsel,
                                                              int64_t wss, const int* __restrict__ wmap) {
   extern __shared__ unsigned char smraw[];
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kSelThreads) void select_restart_kernel(const c128*
   const c128* Y = Yall + int64_t(w) * wsy;
   c128* out = outall + int64_t(w) * wso;
   const int ld = k + nev;
-  const double sg = sigma ? sigma[w] : 0.0;
+  const c128 sg = sigma ? sigma[w] : c128{0.0, 0.0};
   const int t = threadIdx.x;
   for (int i = t; i < m; i += kSelThreads) {
     const double ki = sel_key(th[i], sg, mode);
@@ -790,7 +790,7 @@ void smalleig(c128* H, int64_t wsh, int m, c128* theta, int64_t wst, c128* Y, in
   hipLaunchKernelGGL(colnorm_kernel, dim3((m + 63) / 64, nwin), dim3(64), 0, st, Y, wsy, m, wmap);
 }
 
-void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const double* sigma, int mode,
+void select_restart(const c128* theta, int64_t wst, const c128* Y, int64_t wsy, int m, const c128* sigma, int mode,
                     int k, int nev, c128* out, int64_t wso, c128* theta_sel, int64_t wss, int nwin, hipStream_t st,
                     const int* wmap) {
   if (nwin <= 0) return;

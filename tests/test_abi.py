@@ -85,3 +85,26 @@ def test_no_device_reports_edevice(pkg):
     with pytest.raises(pkg.TsgError) as e:
         pkg.Operator(4, 4, 4, 0.5, np.zeros(64), [0.5, 2.0, 0.0, 0.5, 2.0, 1.5])
     assert e.value.status == 5  # TSG_EDEVICE: no CPU fallback exists
+
+
+def test_tuning_file_round_trip_and_rejections(pkg, tmp_path):
+    """tsg_load_tuning parses the autotuner's JSON on the host (no device
+    needed) and refuses malformed or invalid entries."""
+    from paper_1606_01139_amd.binding import load_tuning, TsgError, TSG_EINVAL
+    good = tmp_path / "t.json"
+    good.write_text('{"stencil": [\n {"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 16, "radius": 6, "tx": 32, '
+                    '"yb": 2, "zchunk": 16, "us": 1.5},\n {"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 8, '
+                    '"radius": 6, "tx": 16, "yb": 1, "zchunk": 9, "us": 1.0}]}\n')
+    assert load_tuning(str(good)) == 2
+    bad = tmp_path / "b.json"
+    bad.write_text('{"stencil": [{"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 16, "radius": 6, "tx": 48, '
+                   '"yb": 1, "zchunk": 16, "us": 1.0}]}')
+    with pytest.raises(TsgError) as e:
+        load_tuning(str(bad))
+    assert e.value.status == TSG_EINVAL
+    worse = tmp_path / "w.json"
+    worse.write_text('{"stencil": [{"nx": 7}]}')
+    with pytest.raises(TsgError):
+        load_tuning(str(worse))
+    with pytest.raises(TsgError):
+        load_tuning(str(tmp_path / "missing.json"))

@@ -83,6 +83,66 @@ def test_stencil_c64_matches_oracle(torch_cuda, shape, B):
     assert np.abs(Y - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
+# every geometry the autotuner may pick: tile widths 16/32/64, one or two
+# points per thread in y, z chunks shorter and longer than the grid, on
+# ragged tiles in x and y
+@pytest.mark.parametrize("tx,yb,zc", [(16, 1, 16), (16, 2, 24), (32, 2, 5), (64, 2, 48), (32, 1, 192), (64, 1, 7)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_stencil_tuned_geometries_match_oracle(torch_cuda, tmp_path, tx, yb, zc, dtype):
+    torch = torch_cuda
+    from oracle import operator as op
+    from paper_1606_01139_amd import Operator
+    from paper_1606_01139_amd.binding import load_tuning
+    nx, ny, nz, B = 37, 29, 21, 3
+    print(f"stencil geometry tx={tx} yb={yb} zchunk={zc} {dtype}", flush=True)
+    elem = 16 if dtype == "c128" else 8
+    f = tmp_path / "tune.json"
+    f.write_text('{"stencil": [{"nx": %d, "ny": %d, "nz": %d, "cols": %d, "elem": %d, "radius": 6, "tx": %d, '
+                 '"yb": %d, "zchunk": %d, "us": 0}]}' % (nx, ny, nz, B, elem, tx, yb, zc))
+    assert load_tuning(str(f)) == 1
+    V, ab, gL, gR = _fields(nx, ny, nz, 8)
+    N = nx * ny * nz
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((N, B)) + 1j * rng.standard_normal((N, B))
+    if dtype == "c64":
+        X = X.astype(np.complex64)
+    ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X.astype(np.complex128), 6)
+    oper = Operator(nx, ny, nz, 0.5, V, ab)
+    Xd = _to_dev(torch, X, 0)
+    Yd = _to_dev(torch, np.zeros_like(X), 0)
+    oper.apply(Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().T.astype(np.complex128)
+    tol = 1e-13 if dtype == "c128" else 1e-6
+    assert np.abs(Y - ref).max() <= tol * np.abs(ref).max()
+    oper.close()
+
+
+def test_stencil_autotuner_picks_a_candidate_and_keeps_parity(torch_cuda, tmp_path):
+    torch = torch_cuda
+    from oracle import operator as op
+    from paper_1606_01139_amd import Operator
+    from paper_1606_01139_amd.binding import load_tuning
+    nx, ny, nz, B = 20, 24, 40, 4
+    print("stencil autotuner", flush=True)
+    V, ab, gL, gR = _fields(nx, ny, nz, 11)
+    oper = Operator(nx, ny, nz, 0.5, V, ab)
+    out = tmp_path / "tuned.json"
+    geo, us = oper.tune_stencil(B, 0, 3, str(out))
+    assert geo["tx"] in (16, 32, 64) and geo["yb"] in (1, 2) and 1 <= geo["zchunk"] <= nz and geo["tried"] > 10
+    assert us > 0
+    assert load_tuning(str(out)) >= 1
+    N = nx * ny * nz
+    X = np.random.default_rng(12).standard_normal((N, B)) + 0.5j
+    ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X, 6)
+    Xd = _to_dev(torch, X, 0)
+    Yd = _to_dev(torch, np.zeros_like(X), 0)
+    oper.apply(Xd, Yd)
+    torch.cuda.synchronize()
+    assert np.abs(Yd.cpu().numpy().T - ref).max() <= 1e-13 * np.abs(ref).max()
+    oper.close()
+
+
 @pytest.mark.parametrize("m,batch", [(1, 1), (2, 2), (8, 3), (37, 2), (128, 2), (304, 1), (600, 1)])
 def test_dense_eig_matches_lapack(torch_cuda, m, batch):
     torch = torch_cuda

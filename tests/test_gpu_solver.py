@@ -251,48 +251,107 @@ def test_hole_filling_matches_oracle(torch_cuda):
     oper.close()
 
 
-@pytest.fixture(scope="module")
-def c2_solved(torch_cuda):
-    # the bench's configuration: c2, semiclassical windows, 8 x 50, FP64
+def _c2_reference():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2_reference.json")) as f:
+        return json.load(f)
+
+
+def _match_one_to_one(got, ref, tol_rel):
+    """Every reference eigenvalue has its own computed one within tol_rel
+    max(|eps|, 1 Ha) (matched by nearest distance; the order of equal real
+    parts is not unique)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert len(got) == len(ref), (len(got), len(ref))
+    used = np.zeros(len(got), bool)
+    worst = 0.0
+    for e in ref:
+        d = np.abs(got - e)
+        d[used] = np.inf
+        k = int(np.argmin(d))
+        used[k] = True
+        worst = max(worst, d[k] / max(abs(e), 1.0))
+    assert worst <= tol_rel, worst
+    return worst
+
+
+@pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "fp32bulk"])
+def c2_solved(torch_cuda, request):
+    # the bench's configuration: c2, semiclassical windows, 8 x 50, hole
+    # filling (4 rounds, inserted counts capped at 50)
     from paper_1606_01139_amd import Operator, default_opts, PLAN_SEMICLASSICAL
     from synth.workloads import workload
-    print("c2 full-size solve (about a minute)", flush=True)
+    precision = request.param
+    print(f"c2 full-size solve precision={precision} (about a minute)", flush=True)
     w = workload("c2")
     g = w.grid
     oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
-    opts = default_opts(tol=1e-8)
+    opts = default_opts(tol=1e-8, precision=precision)
     wins, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
     n, holes, status = oper.solve_all_partitions(wins, opts)
     assert status == 0
-    # Algorithm 1's repeat loop, as the bench runs it
     added, rounds, n, left, status = oper.fill_holes(erange[0], w.nev_per_window, 4, opts)
     print(f"c2: {n} unique, {added} partitions inserted in {rounds} rounds, {left} flags left", flush=True)
     assert status == 0 and left == 0
     for j in range(len(wins) + added):
         st = oper.stats(j)
         assert st.n_conv == st.nev and st.max_backward_error <= 1e-8
-    yield w, oper, wins
+    yield w, oper, wins, erange, (added, rounds)
     oper.close()
 
 
-def test_c2_full_size_sampled_parity(c2_solved):
-    # Sampled outputs at the full c2 size, each computed independently by the
-    # oracle: the lowest eigenvalues (ARPACK 'SR'), backward errors and
-    # c-products of sampled vectors with the oracle's sparse operator, and
-    # T(E) at sampled energies.
+def test_c2_full_set_matches_oracle_reference(c2_solved):
+    """The whole c2 result in the bench's configuration against the oracle's
+    stored result (tests/golden/c2_reference.json, written by
+    make_c2_fixture.py from oracle/ only): the plan, the partitions
+    Algorithm 1's repeat loop inserts, every partition's eigenvalues, the
+    combined set element by element at 1e-10 relative, and T(E) at the 200
+    stored energies to 1e-6 absolute."""
+    w, oper, wins, erange, (added, rounds) = c2_solved
+    ref = _c2_reference()
+    assert abs(erange[0] - ref["e_min"]) <= 1e-10 * abs(ref["e_min"])
+    assert abs(erange[1] - ref["e_max"]) <= 1e-12 * ref["e_max"]
+    assert [c for _, c in wins] == [p["nev"] for p in ref["planned"]]
+    np.testing.assert_allclose([s for s, _ in wins], [p["shift"] for p in ref["planned"]], rtol=0, atol=1e-8)
+    assert added == len(ref["inserted"]) and rounds == ref["rounds"]
+    # partitions after the loop, ordered by shift
+    assert len(ref["windows"]) == len(wins) + added
+    for j, rw in enumerate(ref["windows"]):
+        st = oper.stats(j)
+        assert st.nev == rw["nev"] and abs(st.shift - rw["shift"]) <= 1e-8, (j, st.shift, rw["shift"])
+        e, _ = oper.partition(j)
+        _match_one_to_one(e, np.array(rw["re"]) + 1j * np.array(rw["im"]), 1e-10)
+    eps = oper.eigenvalues()
+    comb = np.array(ref["combined"]["re"]) + 1j * np.array(ref["combined"]["im"])
+    worst = _match_one_to_one(eps, comb, 1e-10)
+    print(f"combined set: {len(eps)} pairs, worst relative difference {worst:.2e}", flush=True)
+    # T(E) from two valid eigenbases: each side's vectors are fixed only to
+    # what backward error 1e-8 determines (about rho ||A|| / gap, gaps of
+    # 1e-3 Ha here) and T is quadratic in them, while T itself reaches about
+    # 70; so the comparison is relative, 1e-5 max(1, |T|) (measured: 7.7e-7
+    # in FP64, 1.6e-6 in FP32-bulk).  The T kernels themselves are checked
+    # at 1e-6 absolute on the GPU's own pairs in test_c2_full_size_vectors.
+    T = oper.transmission(np.array(ref["energies"]))
+    Tref = np.array(ref["transmission"])
+    rel = np.abs(T - Tref) / np.maximum(1.0, np.abs(Tref))
+    print(f"T(E): worst relative difference {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-5
+    assert (T >= -1e-10).all()
+
+
+def test_c2_full_size_vectors(c2_solved):
+    # Eigenvectors at the full c2 size against the oracle's sparse operator:
+    # the lowest eigenvalues (ARPACK 'SR'), backward errors and c-products of
+    # sampled vectors, and T(E) from the oracle's formula on the GPU's pairs.
     from oracle import operator as op, eigen, transport
-    w, oper, wins = c2_solved
+    w, oper, wins, erange, _ = c2_solved
     g = w.grid
     gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
     A = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR).tocsr()
     nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
     eps = oper.eigenvalues()
-    # (1) the 10 lowest eigenvalues: the first window reaches the bottom end
-    e_ref = eigen.lowest_real(A, 10)
-    for e in e_ref:
-        d = np.min(np.abs(eps - e))
-        assert d <= 1e-10 * max(abs(e), 1.0), (e, d)
-    # (2) backward errors and c-normalisation of 24 sampled eigenvectors
     Uall = oper.eigenvectors().cpu().numpy()
     rng = np.random.default_rng(0)
     idx = rng.choice(len(eps), size=min(24, len(eps)), replace=False)
@@ -302,16 +361,12 @@ def test_c2_full_size_sampled_parity(c2_solved):
         r = A @ u - eps[k] * u
         assert np.linalg.norm(r) / (nrm * np.linalg.norm(u)) <= 1e-8
         assert abs(u @ u - 1.0) <= 1e-10
-    # (3) c-orthogonality among the sample (distinct eigenvalues)
     G = Us.T @ Us
     assert np.abs(G - np.eye(len(idx))).max() <= 1e-6
-    # (4) T(E) at sampled energies, evaluated by the oracle's formula on the
-    # GPU's eigenpairs (checks the Gamma-weighted grams and the sweep at size)
-    E = np.linspace(eps.real.min(), eps.real.max(), 5)
+    E = np.linspace(eps.real.min(), eps.real.max(), 7)
     T = oper.transmission(E)
     Tref = transport.transmission_spectral(eps, Uall, gL, gR, E)
     assert np.abs(T - Tref).max() <= 1e-6
-    assert (T >= -1e-10).all()
 
 
 def test_restart_cap_reports_noconv_and_keeps_converged_subset(torch_cuda):
@@ -378,4 +433,55 @@ def test_invariant_krylov_space_breakdown_is_restarted(torch_cuda):
     assert np.abs(eps.imag).max() <= 1e-10
     U = Ud.cpu().numpy()
     assert np.linalg.matrix_rank(U, tol=1e-6) == nev
+    oper.close()
+
+
+def test_complex_shift_windows_match_oracle(torch_cuda):
+    """Two-dimensional partitioning on a strongly absorbing system (absorber
+    amplitude 3 Ha, so eigenvalues spread down to Im = -3): windows at
+    complex shifts return the pairs nearest those shifts in the complex plane
+    (dense oracle), combined by Algorithm 2."""
+    from oracle import eigen, operator as op, partition
+    from paper_1606_01139_amd import Operator, default_opts
+    from synth.workloads import small_workload, Absorber
+    print("complex-shift windows", flush=True)
+    w = small_workload(8, 8, 12, 3, seed=9)
+    g = w.grid
+    ab = Absorber.ends(g, amp=3.0).as_tuple()
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    A = op.assemble_dense(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
+    ea, Ua = eigen.dense_spectrum(A)
+    assert ea.imag.min() < -1.0
+    wins = partition.imaginary_bands([(float(ea[6].real), 12), (float(ea[30].real), 12)], float((gL + gR).max()), 2)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, ab)
+    n, holes, _ = oper.solve_all_partitions(wins, default_opts(tol=1e-10))
+    ref = partition.combine([eigen.window_from_spectrum(ea, Ua, s, c) for s, c in wins], nrm)
+    _match_sets(oper.eigenvalues(), ref.eps, 1e-10)
+    for j, (s, c) in enumerate(wins):
+        st = oper.stats(j)
+        assert st.n_conv == c and abs(complex(st.shift, st.shift_im) - s) == 0.0
+        e, _ = oper.partition(j)
+        e_ref, _ = eigen.window_from_spectrum(ea, Ua, s, c)
+        _match_sets(e, e_ref, 1e-10)
+    oper.close()
+
+
+def test_planner_imaginary_bands_match_oracle(torch_cuda):
+    """imag_bands = 2 with the semiclassical planner: the real placements of
+    p/2 windows, each split into two bands at -max Gamma/4 and -3 max Gamma/4
+    (oracle: semiclassical windows, then its band split)."""
+    from oracle import operator as op, partition
+    from paper_1606_01139_amd import Operator, PLAN_SEMICLASSICAL, default_opts
+    from synth.workloads import workload
+    print("planner with imaginary bands", flush=True)
+    w = workload("c1")
+    g = w.grid
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    wins, er = oper.plan_windows(40, 4, PLAN_SEMICLASSICAL, default_opts(imag_bands=2))
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
+    real = partition.semiclassical_windows(w.V, g.h, (g.nx, g.ny, g.nz), er[0], partition.equal_counts(40, 2))
+    ref = partition.imaginary_bands([(s, 20) for s in real], float((gL + gR).max()), 2)
+    assert [c for _, c in wins] == [c for _, c in ref]
+    np.testing.assert_allclose([complex(s) for s, _ in wins], [s for s, _ in ref], rtol=0, atol=1e-9)
     oper.close()

@@ -441,3 +441,28 @@ def test_absorber_profile_width_is_the_standard_deviation():
     GL, GR = op.gamma_fields(3, 2, nz, h, (0.5, 2.0, 0.0, 0.25, 3.0, zR))
     assert GL.shape == (3 * 2 * nz,) and np.all(GL[:6] == gL[0]) and np.all(GL[6:12] == gL[1])
     assert np.all(GR[-6:] == gR[-1])
+
+
+def test_imaginary_bands_worked_values():
+    """Two bands over Im in [-0.5, 0]: centres -1/8 and -3/8 (worked by hand),
+    counts 50 -> 25 + 25 and 7 -> 4 + 3; one band keeps the window on the
+    line Im = -gamma_max/2."""
+    got = partition.imaginary_bands([(0.3, 50), (1.0, 7)], 0.5, 2)
+    assert got == [(complex(0.3, -0.125), 25), (complex(0.3, -0.375), 25),
+                   (complex(1.0, -0.125), 4), (complex(1.0, -0.375), 3)]
+    assert partition.imaginary_bands([(0.3, 5)], 0.5, 1) == [(complex(0.3, -0.25), 5)]
+    three = partition.imaginary_bands([(0.0, 2)], 0.6, 3)
+    assert [c for _, c in three] == [1, 1, 1]
+    assert np.allclose([z.imag for z, _ in three], [-0.1, -0.3, -0.5])
+
+
+def test_complex_window_is_nearest_in_the_plane():
+    """The window of a complex shift is the nev eigenvalues nearest it in the
+    complex plane (Eq. (3) with a complex E_S), checked on a diagonal
+    operator whose eigenvalues are known."""
+    eps = np.array([0.0 - 0.0j, 0.1 - 0.9j, 0.2 - 0.1j, 0.5 - 1.0j, 1.0 - 0.05j])
+    U = np.eye(5, dtype=complex)
+    e, _ = eigen.window_from_spectrum(eps, U, complex(0.3, -0.95), 2)
+    assert set(np.round(e, 12)) == {0.1 - 0.9j, 0.5 - 1.0j}
+    e, _ = eigen.window_from_spectrum(eps, U, 0.3, 2)
+    assert set(np.round(e, 12)) == {0.2 - 0.1j, 0.0 - 0.0j}
