@@ -29,6 +29,10 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args(argv)
     import numpy as np
+    import torch  # the device is set up the way the rest of the package uses it
+    if not torch.cuda.is_available():
+        raise SystemExit("the autotuner needs a GPU")
+    torch.cuda.set_device(0)
     results = []
     for (nx, ny, nz), cols_list, dtypes in SHAPES:
         V = np.linspace(-2.0, 0.0, nx * ny * nz)
