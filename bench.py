@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--basis", type=int, default=0)
     ap.add_argument("--keep", type=int, default=0)
     ap.add_argument("--groups", type=int, default=0, help="window groups iterating concurrently (0: library default)")
+    ap.add_argument("--bulk-tol", type=float, default=0.0,
+                    help="FP32-bulk: backward error at which the complex64 phase hands over (0: library default)")
     ap.add_argument("--extraction", default="ritz", choices=["ritz", "harmonic"],
                     help="Ritz or harmonic Ritz pairs for the window shifts")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -434,6 +436,8 @@ def main():
         if args.groups:
             o.groups = args.groups
         o.extraction = 1 if args.extraction == "harmonic" else 0
+        if args.bulk_tol > 0:
+            o.bulk_tol = args.bulk_tol
         return o
 
     opts = make_opts(prec)

@@ -410,6 +410,13 @@ __global__ __launch_bounds__(256) void cdot_partial_kernel(const cplx<T>* __rest
 
 // F[:, q] = AU[:, sel_q] - theta[sel_q] U[:, sel_q] (explicit residuals of
 // selected Ritz pairs); columns with sel_q < 0 are left unchanged.
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 template <typename T>
 __global__ void resblock_kernel(const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ AU, int64_t ld, int64_t ws,
                                 const c128* __restrict__ theta, int64_t wst, const int* __restrict__ sel, int b,
@@ -421,7 +428,14 @@ __global__ void resblock_kernel(const cplx<T>* __restrict__ U, const cplx<T>* __
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= rows.of(w)) return;
   const int col = sel[w * b + q];
-  if (col < 0) return;
+  if (col < 0) {
+    // no pair for this column (a window with fewer wanted pairs): a
+    // counter-based random vector keeps the block of full rank
+    const uint64_t h = mix64(0xD1B54A32D192ED03ull ^ mix64((uint64_t(w) << 32) ^ uint64_t(q)) ^ mix64(uint64_t(n)));
+    const double u = double(h >> 11) * (1.0 / 9007199254740992.0);
+    F[int64_t(w) * wsf + int64_t(q) * ldf + n] = cplx<T>{T(2.0 * u - 1.0), T(0)};
+    return;
+  }
   const c128 th = theta[int64_t(w) * wst + col];
   const int64_t off = int64_t(w) * ws + int64_t(col) * ld + n;
   const cplx<T> u = U[off], au = AU[off];
@@ -431,13 +445,6 @@ __global__ void resblock_kernel(const cplx<T>* __restrict__ U, const cplx<T>* __
 }
 
 // ------------------------------------------------------------- misc
-__device__ inline uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 template <typename T>
 __global__ void random_kernel(cplx<T>* X, int64_t ldx, int64_t wsx, Rows rows, uint64_t seed,
                               const int* __restrict__ wmap) {

@@ -164,6 +164,7 @@ struct SolveStream {
 // holds A times the wanted Ritz vectors.  Ft is a b-column temporary.
 template <typename T> struct Batch {
   int nw = 0, m = 0, k = 0, b = 0, nv = 0;
+  int bw = 0;  // widest block orthonormalize handles (b, or the residual block of the FP64 polish)
   uint64_t seed = 0;
   bool harmonic = false;
   DevArr<c128> Hs, Lh, Xh, XG;  // harmonic extraction: saved H, LU and solution scratch, restart update
@@ -175,30 +176,32 @@ template <typename T> struct Batch {
   DevArr<c128> sig;
   DevArr<int> flags, info, wmap, wmap2, sel, nbreak;
 
-  void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_) {
+  void alloc(int nw_, const Systems& S, int m_, int k_, int b_, int nv_, int bw_ = 0) {
     nw = nw_; ldN = S.ldN; rows = S.rows_arg(); m = m_; k = k_; b = b_; nv = nv_;
+    bw = std::max(b, bw_);
     const int64_t N = S.Nmax;
     V.alloc(size_t(ws()) * nw); Vr.alloc(size_t(ws()) * nw);
     AV.alloc(size_t(ldN) * m * nw); AR.alloc(size_t(ws()) * nw);
-    Ft.alloc(size_t(ldN) * b * nw);
+    Ft.alloc(size_t(ldN) * bw * nw);
     H.alloc(size_t(m) * m * nw); Ys.alloc(size_t(m) * m * nw);
     work.alloc(size_t(smalleig_workspace(m)) * nw);
     theta.alloc(size_t(m) * nw);
     Ysel.alloc(size_t(m) * (k + nv) * nw);
     thsel.alloc(size_t(nv) * nw);
     C.alloc(size_t(wsc()) * nw);
-    G.alloc(size_t(b) * b * nw);
-    Rinv.alloc(size_t(b) * b * nw);
+    G.alloc(size_t(bw) * bw * nw);
+    Rinv.alloc(size_t(bw) * bw * nw);
     Mx.alloc(size_t(4) * b * b * nw);
     int64_t pw = gram_workspace(N, m, m, nw);
     pw = std::max(pw, gram_workspace(N, m + b, 2 * b, nw));
-    pw = std::max(pw, gram_workspace(N, b, b, nw));
+    pw = std::max(pw, gram_workspace(N, bw, bw, nw));
+    pw = std::max(pw, gram_workspace(N, m, bw, nw));
     pw = std::max(pw, residual_workspace(N, nv, nw));
     part.alloc(size_t(pw));
     res.alloc(size_t(2) * nv * nw);
     sig.alloc(size_t(nw));
-    flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * b);
-    wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * b); na.alloc(size_t(nw) * b);
+    flags.alloc(size_t(nw)); info.alloc(size_t(nw)); wmap.alloc(size_t(nw)); sel.alloc(size_t(nw) * bw);
+    wmap2.alloc(size_t(nw)); nb.alloc(size_t(nw) * bw); na.alloc(size_t(nw) * bw);
     bfloor.alloc(size_t(nw)); nbreak.alloc(size_t(nw));
   }
   void alloc_harmonic() {
@@ -207,15 +210,16 @@ template <typename T> struct Batch {
     XG.alloc(size_t(m) * b * nw);
   }
   int64_t ws() const { return ldN * (m + b); }
-  int64_t wsc() const { return int64_t(m + b) * 2 * b; }
+  int64_t wsc() const { return int64_t(m + b) * std::max(2 * b, bw); }
 };
 
 // dest (ldN x b per window, column stride ldd, window stride wsd) is made
 // orthonormal against the first J basis columns (CGS2) and within itself
 // (Cholesky-QR, twice).
 template <typename T>
-void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, int64_t wsd, int J) {
-  const int b = B.b, nw = B.nw;
+void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, int64_t wsd, int J, int width = 0) {
+  const int b = width > 0 ? width : B.b, nw = B.nw;
+  if (b > B.bw) throw DeviceError("orthonormalize: block wider than the batch's buffers");
   const int* wm = B.wmap.p;
   hipStream_t st = S.st;
   const int64_t ldN = B.ldN;
@@ -227,10 +231,9 @@ void orthonormalize(const Systems& S, Batch<T>& B, cplx<T>* dest, int64_t ldd, i
     col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.nb.p, cpart, ccap, st, wm);
     for (int pass = 0; pass < 2; ++pass) {
       const int* wp = pass == 0 ? wm : B.wmap2.p;
-      gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, int64_t(B.m) * b, nw, B.part.p,
+      gram<T, T>(B.V.p, ldN, B.ws(), dest, ldd, wsd, B.rows, J, b, B.C.p, b, B.wsc(), nw, B.part.p,
                  int64_t(B.part.n), st, wp);
-      gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, int64_t(B.m) * b, dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wp,
-                   -1.0);
+      gemm_cols<T>(B.V.p, ldN, B.ws(), B.C.p, b, B.wsc(), dest, ldd, wsd, B.rows, J, b, 1.0, nw, st, wp, -1.0);
       if (pass == 0) {
         col_sqnorms<T>(dest, ldd, wsd, B.rows, b, nw, B.na.p, cpart, ccap, st, wm);
         dgks_select(B.nb.p, B.na.p, b, nw, wm, B.wmap2.p, st);
@@ -358,13 +361,21 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
   // rotation and residual norms; with `cont`, first the continuation block
   // left pending after the previous cycle's last step (in Davidson mode the
   // residual block of the wanted Ritz pairs instead, orthonormalised)
+  // residual block width of the FP64 polish: the b worst pairs (measured on
+  // c2: feeding all nev residuals each cycle stalls near 1e-6, as the
+  // residual directions crowd out the Krylov steps)
+  const int dw = b;
+  if (dw > B.bw) throw DeviceError("iterate: residual block wider than the batch's buffers");
   auto body = [&](int jstart, bool cont) {
     if (cont) {
       if (davidson) {
-        residual_block<T>(B.V.p + k * ldN, B.AR.p, ldN, wsV, B.thsel.p, nv, B.sel.p, b, B.Ft.p, ldN, ldN * b, rows,
+        // the residuals of dw wanted pairs (all of them when they fit),
+        // orthonormalised, continue the basis; the Krylov steps then extend
+        // it from the last b of them
+        residual_block<T>(B.V.p + k * ldN, B.AR.p, ldN, wsV, B.thsel.p, nv, B.sel.p, dw, B.Ft.p, ldN, ldN * dw, rows,
                           nw, st, wm);
-        copy_block<T, T>(B.Ft.p, ldN, ldN * b, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
-        orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k);
+        copy_block<T, T>(B.Ft.p, ldN, ldN * dw, B.V.p + k * ldN, ldN, wsV, rows, dw, nw, st, wm);
+        orthonormalize<T>(S, B, B.V.p + k * ldN, ldN, wsV, k, dw);
       } else {
         copy_block<T, T>(B.Vr.p + m * ldN, ldN, wsV, B.V.p + k * ldN, ldN, wsV, rows, b, nw, st, wm);
         if (B.harmonic) {
@@ -376,7 +387,9 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
         }
       }
     }
-    for (int j = jstart; j < m; j += b) expand_step<T>(S, B, j);
+    // in Davidson mode the first dw - b columns after the kept ones are final
+    const int jfirst = (cont && davidson) ? jstart + dw - b : jstart;
+    for (int j = jfirst; j < m; j += b) expand_step<T>(S, B, j);
     // Rayleigh-Ritz on the final basis: A V afresh, then H = V^H A V
     stencil<T>(S, B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, m, nw, wm);
     gram<T, T>(B.V.p, ldN, wsV, B.AV.p, ldN, ldN * m, rows, m, m, B.H.p, m, int64_t(m) * m, nw, B.part.p,
@@ -488,12 +501,15 @@ void iterate(const Systems& S, Batch<T>& B, const std::vector<WindowSpec>& wins,
       // after a precision change the kept basis has a residual of full rank,
       // so the next block is built from the explicit residuals of the b
       // wanted Ritz pairs with the largest backward error
-      std::vector<int> hsel(size_t(nw) * b, -1);
+      // the dw pairs with the largest backward errors, ordered so that the
+      // worst come last: the Krylov steps continue from the last b columns
+      std::vector<int> hsel(size_t(nw) * dw, -1);
       for (int w : active) {
         std::vector<int> ord(wins[w].nev);
         std::iota(ord.begin(), ord.end(), 0);
         std::sort(ord.begin(), ord.end(), [&](int a, int c2) { return out[w].rho[a] > out[w].rho[c2]; });
-        for (int q = 0; q < b && q < int(ord.size()); ++q) hsel[size_t(w) * b + q] = ord[q];
+        const int nsel = std::min(dw, int(ord.size()));
+        for (int q = 0; q < nsel; ++q) hsel[size_t(w) * dw + (dw - 1 - q)] = ord[q];
       }
       check(hipMemcpyAsync(B.sel.p, hsel.data(), sizeof(int) * hsel.size(), hipMemcpyHostToDevice, st), "sel");
       check(hipStreamSynchronize(st), "sync");  // hsel is a host temporary
