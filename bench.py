@@ -113,6 +113,83 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_large(args):
+    """The large configurations once, outside the timed-steps contract: c4
+    (plan, solve, hole filling, T(E), then the gradient of the summed T(E)
+    by tsg_transmission_vjp, checked by the exact uniform-shift identity)
+    and c5 on a subset of its planned windows (--window-subset).  Prints one
+    JSON line with timings, per-window statistics and the checks."""
+    import numpy as np
+    import torch
+    from paper_1606_01139_amd import Operator, PLAN_SEMICLASSICAL, default_opts, FP64, FP32_BULK
+    from synth.workloads import workload
+    w = workload(args.config)
+    g = w.grid
+    prec = FP64 if args.precision == "fp64" else FP32_BULK
+    opts = default_opts(precision=prec, tol=1e-8, max_restarts=args.max_restarts)
+    if args.basis:
+        opts.basis = args.basis
+    t0 = time.perf_counter()
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    wins, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    t_plan = time.perf_counter() - t0
+    log(f"{args.config}: planned {len(wins)} windows in {t_plan:.1f} s, E range {erange}")
+    if args.window_subset:
+        idx = [int(x) for x in args.window_subset.split(",")]
+        wins = [wins[i] for i in idx]
+        log(f"solving windows {idx} of the plan: {wins}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n, holes, status = oper.solve_all_partitions(wins, opts, allow_noconv=True)
+    t_solve = time.perf_counter() - t0
+    log(f"solve: {n} unique pairs in {t_solve:.1f} s, status {status}")
+    fill = None
+    if args.fill_rounds and not args.window_subset:
+        t0 = time.perf_counter()
+        added, rounds, n, left, st2 = oper.fill_holes(erange[0], max(k for _, k in wins), args.fill_rounds, opts,
+                                                      allow_noconv=True)
+        fill = {"rounds": rounds, "inserted": added, "holes_left": left, "seconds": round(time.perf_counter() - t0, 2)}
+        status = max(status, st2)
+        log(f"hole filling: {fill}")
+    t_solve_all = t_solve + (fill["seconds"] if fill else 0.0)
+    eps = oper.eigenvalues()
+    E = energy_grid(eps, w.n_energies)
+    t0 = time.perf_counter()
+    T = oper.transmission(E)
+    t_T = time.perf_counter() - t0
+    nparts = len(wins) + (fill["inserted"] if fill else 0)
+    stats = [oper.stats(j) for j in range(nparts)]
+    out = {"config": {"workload": f"{args.config}: {g.nx}x{g.ny}x{g.nz} grid (N={g.n}), {len(w.wells)} wells, "
+                                  f"{w.n_windows} windows x {w.nev_per_window} planned"
+                                  + (f", windows {args.window_subset} solved" if args.window_subset else ""),
+                      "precision": args.precision, "status": int(status), "e_range": [round(x, 6) for x in erange]},
+           "unique_converged_eigenpairs": int(n), "plan_s": round(t_plan, 2), "solve_s": round(t_solve_all, 2),
+           "eigenpairs_per_s": round(n / t_solve_all, 3), "transmission_s": round(t_T, 3),
+           "n_energies": len(E), "T_max": float(np.max(T)), "T_min": float(np.min(T)), "hole_filling": fill,
+           "windows": [{"shift": round(st.shift, 6), "nev": st.nev, "n_conv": st.n_conv, "restarts": st.restarts,
+                        "restarts_bulk": st.restarts_bulk, "max_backward_error": st.max_backward_error,
+                        "breakdowns": st.breakdowns} for st in stats]}
+    if args.vjp:
+        wts = np.ones(len(E))
+        t0 = time.perf_counter()
+        dV, dab = oper.transmission_vjp(E, wts, allow_noconv=True)
+        t_vjp = time.perf_counter() - t0
+        # A uniform shift of V by c moves every eigenvalue by c and keeps the
+        # vectors, so T_S(E) becomes T_S(E - c): the gradient summed over the
+        # grid equals -sum_e w_e dT/dE(E_e), here by central differences in E
+        # on the same eigenpairs (no new solve)
+        d = 1e-6 * max(1.0, float(np.abs(E).max()))
+        dTdE = (oper.transmission(E + d) - oper.transmission(E - d)) / (2 * d)
+        lhs, rhs = float(dV.sum()), float(-(wts * dTdE).sum())
+        out["gradient"] = {"seconds": round(t_vjp, 2), "status": int(oper.vjp_status), "finite": bool(np.all(np.isfinite(dV)) and np.all(np.isfinite(dab))),
+                           "dL_dabs": [float(x) for x in dab], "dL_dV_norm": float(np.linalg.norm(dV)),
+                           "uniform_shift_identity": {"sum_dL_dV": lhs, "minus_sum_dT_dE": rhs,
+                                                      "rel_diff": abs(lhs - rhs) / max(abs(rhs), 1e-300)}}
+        log(f"gradient: {out['gradient']}")
+    oper.close()
+    print(json.dumps(out), flush=True)
+
+
 def k4_flops(m):
     """Algorithmic real flops of one m x m complex eigen-decomposition:
     Householder Hessenberg reduction with accumulation (10/3 + 4/3 m^3) and
@@ -394,13 +471,17 @@ def main():
     ap.add_argument("--k4-only", action="store_true",
                     help="time only the batched small eigensolve at the solve's shape and print its roofline object")
     ap.add_argument("--n-sys", type=int, default=64, help="systems of the ragged batch (config c3)")
+    ap.add_argument("--large", action="store_true",
+                    help="c4/c5 once: plan, solve, T(E) (and --vjp), with per-window statistics")
+    ap.add_argument("--window-subset", default="", help="with --large: comma-separated indices of planned windows")
+    ap.add_argument("--vjp", action="store_true", help="with --large: also the gradient of the summed T(E)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): windows are independent and "
               "would be dealt across GPUs, but this benchmark measures the one-GPU share", file=sys.stderr)
         sys.exit(2)
     cpu = None
-    if not (args.no_cpu_baseline or args.k4_only or args.config == "c3"):
+    if not (args.no_cpu_baseline or args.k4_only or args.large or args.config == "c3"):
         cpu = CpuSample(args.config)  # before this process touches the GPU
     import torch
     from paper_1606_01139_amd import default_opts, FP64, FP32_BULK
@@ -421,6 +502,9 @@ def main():
         return
     if args.config == "c3":
         run_batch(args)
+        return
+    if args.large:
+        run_large(args)
         return
     w = workload(args.config)
     prec = FP64 if args.precision == "fp64" else FP32_BULK

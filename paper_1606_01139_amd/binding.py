@@ -337,9 +337,11 @@ class Operator:
         return T
 
 
-    def transmission_vjp(self, energies: Sequence[float], dL_dT: Sequence[float]):
+    def transmission_vjp(self, energies: Sequence[float], dL_dT: Sequence[float], allow_noconv=False):
         """Gradient of sum_e dL_dT[e] T(E[e]) w.r.t. V (N,) and
-        (amp_L, width_L, amp_R, width_R) (4,)."""
+        (amp_L, width_L, amp_R, width_R) (4,).  With allow_noconv, a
+        projected solve that missed its tolerance (TSG_ENOCONV, outputs
+        still written) does not raise; the status is in self.vjp_status."""
         E = np.ascontiguousarray(energies, dtype=np.float64)
         w = np.ascontiguousarray(dL_dT, dtype=np.float64)
         assert w.shape == E.shape
@@ -348,7 +350,7 @@ class Operator:
         dp = C.POINTER(C.c_double)
         s = self.lib.tsg_transmission_vjp(self.ctx, E.ctypes.data_as(dp), len(E), w.ctypes.data_as(dp),
                                           dV.ctypes.data_as(dp), dab.ctypes.data_as(dp))
-        _check(self.lib, self.ctx, s)
+        self.vjp_status = _check(self.lib, self.ctx, s, allow=(TSG_ENOCONV,) if allow_noconv else ())
         return dV, dab
 
 

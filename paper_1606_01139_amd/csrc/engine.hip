@@ -728,11 +728,63 @@ void solve_group(Systems& S, const std::vector<WindowSpec>& wins, const tsg_opts
 // one group's small eigensolves (a few compute units) overlap the other
 // groups' bandwidth-bound expansion steps.  Results come back in window
 // order.
+// Device bytes one window of a batched solve holds (FP64 storage; the
+// complex64 phase of FP32-bulk needs less): the basis and its rotation
+// target, A V, A times the wanted vectors, the small matrices of the
+// eigensolve, and the FP32-bulk hand-over block.
+int64_t window_bytes(int64_t ldN, int m, int k, int b, int nv, bool bulk, bool harmonic) {
+  const int64_t grid = ldN * int64_t(4 * m + 4 * b + (bulk ? (k + b) / 2 : 0)) * 16;
+  const int64_t small = (int64_t(5) * m * m + smalleig_workspace(m) + int64_t(m) * (k + nv)) * 16 +
+                        (harmonic ? int64_t(3) * m * m * 16 : 0);
+  return grid + small;
+}
+
 void solve_core(const std::vector<tsg_ctx*>& ctx, const std::vector<int>& wsys, const std::vector<WindowSpec>& wins,
                 const tsg_opts& o, hipStream_t user, std::vector<Partition>& parts, std::vector<bool>& conv) {
   const int nw = int(wins.size());
   if (nw < 1) throw InvalidArg("need at least one window");
   if (o.groups < 0) throw InvalidArg("groups must be >= 0");
+  {
+    // memory: when the batch does not fit in the free device memory, the
+    // windows run in consecutive batches that do (each a batched iteration)
+    int nvmax = 1;
+    int64_t Nmax = 1, Nmin = ctx[0]->N;
+    for (const auto& w : wins) nvmax = std::max(nvmax, w.nev);
+    for (tsg_ctx* c : ctx) { Nmax = std::max(Nmax, c->N); Nmin = std::min(Nmin, c->N); }
+    int m = 0, k = 0, b = 0;
+    choose_sizes(Nmin, nvmax, o, m, k, b);
+    const int64_t per = window_bytes(round_up64(Nmax, 64), m, k, b, nvmax, o.precision == TSG_FP32_BULK,
+                                     o.extraction == TSG_EXTRACT_HARMONIC);
+    size_t free_b = 0, total_b = 0;
+    check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    // TSG_MEMORY_LIMIT_MB lowers the budget (to exercise the split on a test system)
+    if (const char* lim = std::getenv("TSG_MEMORY_LIMIT_MB")) {
+      const long long mb = std::atoll(lim);
+      if (mb > 0) free_b = std::min<size_t>(free_b, size_t(mb) << 20);
+    }
+    const int64_t budget = int64_t(0.9 * double(free_b));
+    const int64_t fit = per > 0 ? budget / per : nw;
+    if (fit < 1)
+      throw OutOfMemory("one window needs about " + std::to_string(per >> 20) + " MiB of device memory (basis " +
+                        std::to_string(m) + " x N = " + std::to_string(Nmax) + " complex128), but " +
+                        std::to_string(free_b >> 20) + " MiB are free: use a smaller basis (tsg_opts.basis)");
+    if (fit < nw) {
+      parts.clear();
+      conv.clear();
+      for (int w0 = 0; w0 < nw; w0 += int(fit)) {
+        const int w1 = std::min(nw, w0 + int(fit));
+        std::vector<WindowSpec> sub(wins.begin() + w0, wins.begin() + w1);
+        std::vector<int> ssys;
+        if (!wsys.empty()) ssys.assign(wsys.begin() + w0, wsys.begin() + w1);
+        std::vector<Partition> sp;
+        std::vector<bool> sc;
+        solve_core(ctx, ssys, sub, o, user, sp, sc);
+        for (auto& P : sp) parts.push_back(std::move(P));
+        for (bool c2 : sc) conv.push_back(c2);
+      }
+      return;
+    }
+  }
   const int G = std::max(1, std::min(nw, o.groups > 0 ? o.groups : 1));
   check(hipStreamSynchronize(user), "sync");
   for (size_t s = 1; s < ctx.size(); ++s) check(hipStreamSynchronize(ctx[s]->st), "sync");
@@ -1417,6 +1469,11 @@ int transmission_vjp(tsg_ctx* c, const double* E, int nE, const double* w, doubl
         all = all && hdone[k];
       }
       check(hipMemcpyAsync(done.p, hdone.data(), sizeof(int) * n, hipMemcpyHostToDevice, st), "done");
+      if (progress_on() && it % 100 == 0) {
+        int nd = 0;
+        for (int k = 0; k < n; ++k) nd += hdone[k];
+        std::fprintf(stderr, "[tsg] adjoint COCR iteration %d: %d of %d solves converged\n", it, nd, n);
+      }
       if (all) { conv = true; break; }
     }
   }

@@ -20,6 +20,12 @@
 // the log onto the rows of Z, many workgroups per window: a row of Z is
 // transformed by right rotations independently of every other row, so the
 // replay is parallel over rows and off the chase's critical path.
+// Likewise the left transformations of the columns to the right of the
+// active block [lo, ihi]: nothing in the iteration reads those columns again
+// (ihi only decreases), so the chase leaves them and a third kernel replays
+// the log onto them, many workgroups per window over bands of columns.  Each
+// record carries the ihi of its step; column j takes the records whose ihi is
+// below j, a suffix of the log.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -341,6 +347,66 @@ __device__ __attribute__((noinline)) void flush_log(c128* Z, int m, const RotRec
   }
 }
 
+// Applies one logged left rotation to a column of H (held with stride cs).
+__device__ inline void replay_rot_col(c128* col, int cs, const RotRec& R) {
+  const int p = R.p;
+  const c128 u = col[int64_t(p) * cs], v = col[int64_t(p + 1) * cs];
+  col[int64_t(p) * cs] = R.c * u + R.s * v;
+  col[int64_t(p + 1) * cs] = R.c * v - conj(R.s) * u;
+}
+
+// Outputs i = j, j + kShifts, ... of Q^H col[lo : lo+n] for a logged Q block
+// (stored by qstore_col after a barrier).
+__device__ inline void qblock_col(const c128* col, int cs, const RotRec& R0, const c128* qs, int j,
+                                  c128 (&acc)[kQAcc]) {
+  const int lo = int(R0.c), n = int(R0.s.re);
+  const c128* Q = qs + int64_t(R0.s.im);
+#pragma unroll
+  for (int q = 0; q < kQAcc; ++q) {
+    const int ii = j + q * kShifts;
+    c128 a{0.0, 0.0};
+    if (ii < n)
+      for (int pp = 0; pp < n; ++pp) fma_cacc(a, Q[pp * n + ii], col[int64_t(lo + pp) * cs]);
+    acc[q] = a;
+  }
+}
+
+__device__ inline void qstore_col(c128* col, int cs, const RotRec& R0, int j, const c128 (&acc)[kQAcc]) {
+  const int lo = int(R0.c), n = int(R0.s.re);
+#pragma unroll
+  for (int q = 0; q < kQAcc; ++q) {
+    const int ii = j + q * kShifts;
+    if (ii < n) col[int64_t(lo + ii) * cs] = acc[q];
+  }
+}
+
+// The chase's own replay of the deferred left transformations onto the
+// columns of H (global memory), used only when the log is full: column c
+// takes the records whose ihi is below c.
+__device__ __attribute__((noinline)) void flush_log_cols(c128* H, int m, const RotRec* rec, int nstep, const c128* qs) {
+  const int t = threadIdx.x, j = t % kShifts;
+  constexpr int kCols = kQT / kShifts;
+  for (int c0 = 0; c0 < m; c0 += kCols) {
+    const int c = t < kCols * kShifts ? c0 + t / kShifts : m;
+    const bool mine = c < m;
+    c128* col = H + min(c, m - 1);
+    for (int st = 0; st < nstep; ++st) {
+      const RotRec* R = rec + int64_t(st) * kShifts;
+      const bool take = mine && R[0].pad < c;
+      if (R[0].p <= -2) {
+        c128 acc[kQAcc];
+        if (take) qblock_col(col, m, R[0], qs, j, acc);
+        __syncthreads();
+        if (take) qstore_col(col, m, R[0], j, acc);
+      } else {
+        const RotRec Rj = R[j];
+        if (take && Rj.p >= 0) replay_rot_col(col, m, Rj);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
                                                     c128* logall, int64_t wsl, int64_t cap, c128* theta, int64_t wst,
                                                     int* info, const int* __restrict__ wmap, int prof,
@@ -364,6 +430,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     if (nstep < cap && nq + qneed <= kQCap) return;
     __syncthreads();
     flush_log(Z, m, rec, nstep, qs);
+    flush_log_cols(H, m, rec, nstep, qs);
     nstep = 0;
     nq = 0;
   };
@@ -436,7 +503,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
           RotRec R;
           R.c = t == 0 ? double(lo) : 0.0;
           R.p = t == 0 ? -2 : -1;
-          R.pad = 0;
+          R.pad = ihi;
           R.s = c128{t == 0 ? double(n) : 0.0, t == 0 ? double(nq) : 0.0};
           rec[int64_t(nstep) * kShifts + t] = R;
         }
@@ -445,7 +512,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       }
       __syncthreads();
       apply_right(H, m, 0, lo, lo, Q, n);
-      apply_left(H, m, lo, ihi + 1, m, Q, n);
+      // columns beyond the block take Q^H in the column replay
       tick(6);
       ihi = lo - 1;
       __syncthreads();
@@ -507,7 +574,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         RotRec R;
         R.c = t < ns ? S.bc[t] : 1.0;
         R.p = t < ns ? S.bp[t] : -1;
-        R.pad = 0;
+        R.pad = ihi;
         R.s = t < ns ? S.bs[t] : c128{0.0, 0.0};
         rec[int64_t(nstep) * kShifts + t] = R;
       }
@@ -525,7 +592,8 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       // thread loads a batch of independent items before storing any.
       {
         const int cstart = nact > 0 ? max(lo + step - 3 * jb - 1, lo) : lo;
-        const int W = m - cstart;
+        // columns beyond ihi are left to the column replay
+        const int W = max(0, ihi + 1 - cstart);
         const int total = nact * W;
         for (int base = t; base < total; base += kQT * kBatch) {
           // every item loads (a skipped one from H's first elements) so that
@@ -663,6 +731,72 @@ __global__ __launch_bounds__(256) void zreplay_kernel(c128* Zall, int64_t wsz, i
   for (int e = t; e < nr * m; e += nt) Z[int64_t(r0) * m + e] = zl[e];
 }
 
+// Replays a window's deferred left transformations onto columns
+// [c0, c0 + cols) of H, held in LDS (m x cols, row-major); column c takes
+// the records whose ihi is below c.  Lane j of a column applies record j of
+// each step; steps before the first one that concerns the band are skipped
+// (ihi never increases along the log).
+__global__ __launch_bounds__(256) void hreplay_kernel(c128* Hall, int64_t wsh, int m, const c128* __restrict__ logall,
+                                                     int64_t wsl, int cols, const int* __restrict__ wmap) {
+  extern __shared__ c128 hl[];  // m x cols, then kChunk x kShifts records
+  const int w = wmap ? wmap[blockIdx.y] : blockIdx.y;
+  if (w < 0) return;
+  const int c0 = int(blockIdx.x) * cols;
+  if (c0 >= m) return;
+  const int nc = min(cols, m - c0);
+  c128* H = Hall + int64_t(w) * wsh;
+  const c128* lg = logall + int64_t(w) * wsl;
+  const int nstep = reinterpret_cast<const int*>(lg)[0];
+  const RotRec* rec = reinterpret_cast<const RotRec*>(lg + 2);
+  const c128* qs = lg + log_qstore_offset(m);
+  RotRec* chunk = reinterpret_cast<RotRec*>(hl + int64_t(m) * cols);
+  const int t = threadIdx.x, nt = blockDim.x, j = t % kShifts, cc = t / kShifts;
+  // first step whose ihi is below the band's last column
+  int s0 = nstep;
+  {
+    int lo = 0, hi = nstep;
+    const int cmax = c0 + nc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (rec[int64_t(mid) * kShifts].pad < cmax) hi = mid; else lo = mid + 1;
+    }
+    s0 = lo;
+  }
+  if (s0 >= nstep) return;
+  for (int e = t; e < m * nc; e += nt) {
+    const int i = e / nc, q = e % nc;
+    hl[int64_t(i) * cols + q] = H[int64_t(i) * m + c0 + q];
+  }
+  const int c = c0 + min(cc, nc - 1);
+  c128* col = hl + min(cc, nc - 1);
+  const bool mine = cc < nc;
+  for (int b0 = s0; b0 < nstep; b0 += kChunk) {
+    const int n = min(kChunk, nstep - b0);
+    __syncthreads();
+    for (int e = t; e < n * kShifts; e += nt) chunk[e] = rec[int64_t(b0) * kShifts + e];
+    __syncthreads();
+    for (int st = 0; st < n; ++st) {
+      const RotRec* R = chunk + st * kShifts;
+      const bool take = mine && R[0].pad < c;
+      if (R[0].p <= -2) {
+        c128 acc[kQAcc];
+        if (take) qblock_col(col, cols, R[0], qs, j, acc);
+        __syncthreads();
+        if (take) qstore_col(col, cols, R[0], j, acc);
+      } else {
+        const RotRec Rj = R[j];
+        if (take && Rj.p >= 0) replay_rot_col(col, cols, Rj);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < m * nc; e += nt) {
+    const int i = e / nc, q = e % nc;
+    H[int64_t(i) * m + c0 + q] = hl[int64_t(i) * cols + q];
+  }
+}
+
 }  // namespace
 
 size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
@@ -710,6 +844,22 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, 
   }
   hipLaunchKernelGGL(zreplay_kernel, dim3((m + rows - 1) / rows, nwin), dim3(rows * kShifts), lds, st, Z, wsz, m,
                      log, wsl, rows, wmap);
+  // the deferred left transformations of the columns beyond each block
+  const int hcols = int(std::max<size_t>(1, std::min<size_t>(256 / kShifts,
+                                                           (size_t(150) * 1024 - rec_bytes) / (size_t(m) * sizeof(c128)))));
+  const size_t hlds = size_t(hcols) * m * sizeof(c128) + rec_bytes;
+  if (hlds > size_t(150) * 1024) throw DeviceError("schur: basis too large for the column replay");
+  if (hlds > size_t(64) * 1024) {
+    static size_t hgranted = 0;
+    if (hlds > hgranted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hreplay_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(hlds));
+      if (e != hipSuccess) throw DeviceError(std::string("hreplay: LDS attribute: ") + hipGetErrorString(e));
+      hgranted = hlds;
+    }
+  }
+  hipLaunchKernelGGL(hreplay_kernel, dim3((m + hcols - 1) / hcols, nwin), dim3(hcols * kShifts), hlds, st, H, wsh, m,
+                     log, wsl, hcols, wmap);
   if (prof) {
     unsigned long long z[8];
     (void)hipMemcpyFromSymbolAsync(z, HIP_SYMBOL(g_k4prof), sizeof(z), 0, hipMemcpyDeviceToHost, st);

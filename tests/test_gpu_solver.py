@@ -485,3 +485,32 @@ def test_planner_imaginary_bands_match_oracle(torch_cuda):
     assert [c for _, c in wins] == [c for _, c in ref]
     np.testing.assert_allclose([complex(s) for s, _ in wins], [s for s, _ in ref], rtol=0, atol=1e-9)
     oper.close()
+
+
+def test_windows_split_into_batches_that_fit(torch_cuda, monkeypatch):
+    """When the windows' bases do not fit in the device memory the solve
+    runs them in consecutive batches that do (here forced with a memory
+    limit that holds one c1 window): the result equals the one-batch solve;
+    a limit below one window is refused with TSG_ENOMEM and a size message."""
+    from paper_1606_01139_amd import Operator, default_opts, TsgError
+    from synth.workloads import workload
+    print("windows split by memory", flush=True)
+    w = workload("c1")
+    g = w.grid
+    A, gL, gR, ea, Ua, nrm = _setup(w)
+    shifts = [0.5 * (ea[0].real + ea[19].real), 0.5 * (ea[20].real + ea[39].real)]
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    n1, h1, _ = oper.solve_all_partitions([(s, 20) for s in shifts], default_opts())
+    e1 = oper.eigenvalues()
+    # one c1 window (m = 180) is estimated at about 37 MiB (the rotation log
+    # of the small eigensolve dominates), so 60 MiB hold one window, not two
+    monkeypatch.setenv("TSG_MEMORY_LIMIT_MB", "60")
+    n2, h2, _ = oper.solve_all_partitions([(s, 20) for s in shifts], default_opts())
+    e2 = oper.eigenvalues()
+    assert n1 == n2 and h1 == h2
+    _match_sets(e2, e1, 1e-10)
+    monkeypatch.setenv("TSG_MEMORY_LIMIT_MB", "1")
+    with pytest.raises(TsgError) as e:
+        oper.solve_all_partitions([(s, 20) for s in shifts], default_opts())
+    assert e.value.status == 2 and "MiB" in str(e.value)
+    oper.close()
