@@ -198,7 +198,15 @@ def k4_flops(m):
     return 4.0 * (10.0 / 3.0 + 4.0 / 3.0 + 25.0) * m ** 3
 
 
-K4_TRAFFIC_C2 = 20_964_223_232
+# Bytes in and out of the L2s per launch, from the FETCH_SIZE and WRITE_SIZE
+# counters, each scaled by what it reads for a plain 512 MiB copy (fetch x 2,
+# write x 1); only the shapes below were measured.
+K4_TRAFFIC_C2 = 21_820_724_389  # 8 x 450 x 450 complex128
+STENCIL_TRAFFIC = {
+    (32, 32, 64, 16, "c128"): 39_697_780,
+    (64, 64, 160, 64, "c64"): 1_003_855_298,
+    (64, 64, 160, 64, "c128"): 2_070_023_205,
+}
 
 
 def auto_basis(nev, block=2):
@@ -237,15 +245,12 @@ def k4_roofline(m, batch, reps=3):
     avg = sum(ms) / len(ms)
     fl = k4_flops(m) * batch
     tf = fl / (avg * 1e-3) / 1e12
-    # bytes in and out of L2 per call at the c2 shape (8 x 450 x 450), from
-    # the FETCH_SIZE and WRITE_SIZE counters (each scaled by what it reads for
-    # a plain 512 MiB copy); other shapes were not measured
     traffic = K4_TRAFFIC_C2 if (m, batch) == (450, 8) else None
     return {"bound": "alu", "achieved": round(tf, 5), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
             "kernel": "K4 small eigensolve: hess_slab_p/u_kernel (Hessenberg, row slabs over several "
                       "workgroups per window; hessenberg_kernel below m = 192) + householder_z_kernel + "
-                      "schur_kernel + zreplay_kernel + trevc_kernel + small_gemm_kernel + colnorm_kernel",
+                      "schur_kernel + hreplay_kernel + zreplay_kernel + trevc_kernel + small_gemm_kernel + colnorm_kernel",
             "launch": f"{batch} windows x {m}x{m} complex128", "avg_ms": round(avg, 3),
             "algorithmic_flops": fl}
 
@@ -279,7 +284,7 @@ def stencil_roofline(nx, ny, nz, ncols, dtype, reps=30):
     gbs = bytes_alg / (ms * 1e-3) / 1e9
     oper.close()
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": STENCIL_TRAFFIC.get((nx, ny, nz, ncols, dtype)),
             "kernel": f"stencil_kernel<{'double' if dtype == 'c128' else 'float'},6>",
             "launch": f"{nx}x{ny}x{nz} (N={N}) x {ncols} cols", "avg_ms": round(ms, 5),
             "algorithmic_bytes": bytes_alg}
@@ -471,6 +476,8 @@ def main():
     ap.add_argument("--k4-only", action="store_true",
                     help="time only the batched small eigensolve at the solve's shape and print its roofline object")
     ap.add_argument("--n-sys", type=int, default=64, help="systems of the ragged batch (config c3)")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="time only the stencil launches the line reports (with a known-size copy for the counters)")
     ap.add_argument("--large", action="store_true",
                     help="c4/c5 once: plan, solve, T(E) (and --vjp), with per-window statistics")
     ap.add_argument("--window-subset", default="", help="with --large: comma-separated indices of planned windows")
@@ -481,7 +488,7 @@ def main():
               "would be dealt across GPUs, but this benchmark measures the one-GPU share", file=sys.stderr)
         sys.exit(2)
     cpu = None
-    if not (args.no_cpu_baseline or args.k4_only or args.large or args.config == "c3"):
+    if not (args.no_cpu_baseline or args.k4_only or args.stencil_only or args.large or args.config == "c3"):
         cpu = CpuSample(args.config)  # before this process touches the GPU
     import torch
     from paper_1606_01139_amd import default_opts, FP64, FP32_BULK
@@ -492,6 +499,19 @@ def main():
         w = workload(args.config)
         out = {"roofline": k4_roofline(args.basis or auto_basis(w.nev_per_window), w.n_windows)}
         # a plain device copy of known size, the reference for HBM byte counters
+        nb = 512 << 20
+        x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nb
+        print(json.dumps(out), flush=True)
+        return
+    if args.stencil_only:
+        w = workload(args.config)
+        g = w.grid
+        out = {"stencil": [stencil_roofline(g.nx, g.ny, g.nz, 2 * w.n_windows, "c128"),
+                           stencil_roofline(64, 64, 160, 64, "c64"), stencil_roofline(64, 64, 160, 64, "c128")]}
         nb = 512 << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)

@@ -31,6 +31,7 @@ EXPORTS = [
     "tsg_solve_all_partitions", "tsg_fill_holes", "tsg_solve_batch", "tsg_combine", "tsg_get_eigenvalues", "tsg_get_eigenvectors",
     "tsg_get_partition", "tsg_get_stats", "tsg_transmission", "tsg_transmission_vjp", "tsg_apply_operator",
     "tsg_dense_eig", "tsg_dense_eig_noalloc", "tsg_tune_stencil", "tsg_load_tuning",
+    "tsg_stencil_geometry",
     "tsg_last_error", "tsg_destroy",
 ]
 
@@ -117,6 +118,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib.tsg_dense_eig_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.tsg_tune_stencil.argtypes = [vp, i32, i32, i32, C.c_char_p, C.POINTER(i32), dp]
     lib.tsg_load_tuning.argtypes = [C.c_char_p, C.POINTER(i32)]
+    lib.tsg_stencil_geometry.argtypes = [i32, i32, i32, i32, i32, i32, C.POINTER(i32)]
     lib.tsg_last_error.argtypes = [vp]
     lib.tsg_last_error.restype = C.c_char_p
     lib.tsg_destroy.argtypes = [vp]
@@ -320,13 +322,13 @@ class Operator:
     def tune_stencil(self, ncols: int, dtype: int = C128, reps: int = 10, path: Optional[str] = None):
         """tsg_tune_stencil: times every candidate stencil geometry for a
         launch of ncols vectors on this grid and keeps the fastest.  Returns
-        ({tx, yb, zchunk, tried}, best microseconds per launch)."""
-        g = (C.c_int32 * 4)()
+        ({tx, yb, zchunk, xcd, nt, tried}, best microseconds per launch)."""
+        g = (C.c_int32 * 6)()
         us = C.c_double()
         s = self.lib.tsg_tune_stencil(self.ctx, int(ncols), int(dtype), int(reps),
                                       path.encode() if path else None, g, C.byref(us))
         _check(self.lib, self.ctx, s)
-        return {"tx": g[0], "yb": g[1], "zchunk": g[2], "tried": g[3]}, us.value
+        return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "tried": g[5]}, us.value
 
     def transmission(self, energies: Sequence[float]) -> np.ndarray:
         E = np.ascontiguousarray(energies, dtype=np.float64)
@@ -415,3 +417,12 @@ def load_tuning(path: str) -> int:
     n = C.c_int32()
     _check(lib, None, lib.tsg_load_tuning(path.encode(), C.byref(n)))
     return n.value
+
+
+def stencil_geometry(nx: int, ny: int, nz: int, ncols: int, dtype: int = C128, radius: int = 6) -> dict:
+    """tsg_stencil_geometry: the launch geometry the library uses for ncols
+    vectors of this grid (the tuned entry if the table holds one)."""
+    lib = load()
+    g = (C.c_int32 * 6)()
+    _check(lib, None, lib.tsg_stencil_geometry(int(nx), int(ny), int(nz), int(radius), int(ncols), int(dtype), g))
+    return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "tuned": bool(g[5])}

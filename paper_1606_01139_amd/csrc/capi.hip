@@ -1,6 +1,7 @@
 // extern "C" boundary of libtransec_gpu (declared in include/transec_gpu.h).
 // Every entry point converts internal exceptions into a tsg_status and a
 // message retrievable with tsg_last_error().
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -337,7 +338,7 @@ tsg_status tsg_tune_stencil(tsg_ctx* ctx, int32_t ncols, int32_t dtype, int32_t 
     int tried = 0;
     const tsg::StencilTuneEntry e = tsg::tune_stencil(ctx, ncols, dtype, reps, &tried);
     if (path) tsg::write_tuning(path);
-    if (geometry) { geometry[0] = e.g.tx; geometry[1] = e.g.yb; geometry[2] = e.g.zchunk; geometry[3] = tried; }
+    if (geometry) { geometry[0] = e.g.tx; geometry[1] = e.g.yb; geometry[2] = e.g.zchunk; geometry[3] = e.g.xcd; geometry[4] = e.g.nt; geometry[5] = tried; }
     if (best_us) *best_us = e.us;
     return TSG_OK;
   });
@@ -348,6 +349,25 @@ tsg_status tsg_load_tuning(const char* path, int32_t* n_entries) {
   return guarded(nullptr, [&]() {
     const int n = tsg::load_tuning(path);
     if (n_entries) *n_entries = n;
+    return TSG_OK;
+  });
+}
+
+tsg_status tsg_stencil_geometry(int32_t nx, int32_t ny, int32_t nz, int32_t radius, int32_t ncols, int32_t dtype,
+                                int32_t* geometry) {
+  if (!geometry) return fail(nullptr, TSG_EINVAL, "geometry is NULL");
+  if (nx < 1 || ny < 1 || nz < 1 || radius < 1 || radius > 6 || ncols < 1)
+    return fail(nullptr, TSG_EINVAL, "grid, radius (1..6) and ncols must be positive");
+  if (dtype != TSG_C128 && dtype != TSG_C64) return fail(nullptr, TSG_EINVAL, "dtype must be TSG_C128 or TSG_C64");
+  return guarded(nullptr, [&]() {
+    bool tuned = false;
+    const tsg::StencilGeom g = tsg::stencil_lookup(nx, ny, nz, ncols, dtype == TSG_C128 ? 16 : 8, radius, &tuned);
+    geometry[0] = g.tx;
+    geometry[1] = g.yb;
+    geometry[2] = std::max(1, std::min(g.zchunk, int(nz)));
+    geometry[3] = g.xcd;
+    geometry[4] = g.nt;
+    geometry[5] = tuned ? 1 : 0;
     return TSG_OK;
   });
 }

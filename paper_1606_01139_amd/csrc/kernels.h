@@ -1,5 +1,6 @@
 // Internal kernel launchers of libtransec_gpu.  Not part of the C-ABI.
 #pragma once
+#include <mutex>
 #include <vector>
 
 #include "tsg_common.h"
@@ -38,7 +39,11 @@ template <typename T> struct StencilArgs {
   const int* wsys;                         // window -> system index, or null (system 0)
   const int* wmap;                         // launch slot -> window index (< 0: idle), or null
   int tx, ty, zchunk, tiles;               // launch geometry (tiles = largest tile count)
+  int nt;                                  // threads per workgroup (256 or 512)
   int yb;                                  // points per thread stacked in y (1 or 2)
+  int xcd;                                 // 1: XCD-aware block order (one-dimensional, padded grid)
+  int nzc;                                 // z chunks of the largest system (set at launch)
+  int64_t nblocks;                         // logical blocks (set at launch)
 };
 template <typename T> void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s);
 // Tile geometry for the largest system of a launch: the tuned one for this
@@ -46,12 +51,20 @@ template <typename T> void launch_stencil(StencilArgs<T> a, int nwin, int max_nz
 // default rule.
 template <typename T> void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin);
 
-// A stencil launch geometry: tile width tx (512 / tx thread rows), yb points
-// per thread in y, zchunk planes per workgroup.
+// A stencil launch geometry: tile width tx (nt / tx thread rows, nt = 256 or
+// 512 threads per workgroup), yb points per thread in y, zchunk planes per
+// workgroup, xcd = 1 for the XCD-grouped block order.
 struct StencilGeom {
-  int tx = 64, yb = 1, zchunk = 32;
+  int tx = 64, yb = 1, zchunk = 32, xcd = 0, nt = 512;
 };
+// Whether the kernel supports g at this radius (tile, block size and a halo
+// that fits the per-thread slots).
+bool stencil_geometry_valid(const StencilGeom& g, int radius);
 StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols, int radius);
+// The geometry a launch uses: the tuned entry for (shape, launch columns,
+// complex element size in bytes, radius) if the table has one (*tuned set
+// to true), else the default rule.
+StencilGeom stencil_lookup(int nx, int ny, int nz, int64_t launch_cols, int elem, int radius, bool* tuned);
 template <typename T>
 void stencil_apply_geometry(StencilArgs<T>& a, int nx, int ny, int nz, const StencilGeom& gm);
 // Tuned geometries (filled by the autotuner or read from a tuning file).
@@ -60,9 +73,11 @@ struct StencilTuneEntry {
   StencilGeom g;
   double us;  // measured time per launch
 };
+// Process-wide; every member locks, so launches may read it while another
+// thread loads or tunes.
 struct StencilTuneTable {
-  std::vector<StencilTuneEntry> e;
-  bool find(int nx, int ny, int nz, int cols, int elem, int radius, StencilGeom& out) const {
+  bool find(int nx, int ny, int nz, int64_t cols, int elem, int radius, StencilGeom& out) const {
+    std::lock_guard<std::mutex> lock(mu);
     for (const auto& x : e)
       if (x.nx == nx && x.ny == ny && x.nz == nz && x.cols == cols && x.elem == elem && x.radius == radius) {
         out = x.g;
@@ -71,6 +86,7 @@ struct StencilTuneTable {
     return false;
   }
   void put(const StencilTuneEntry& v) {
+    std::lock_guard<std::mutex> lock(mu);
     for (auto& x : e)
       if (x.nx == v.nx && x.ny == v.ny && x.nz == v.nz && x.cols == v.cols && x.elem == v.elem &&
           x.radius == v.radius) {
@@ -79,6 +95,14 @@ struct StencilTuneTable {
       }
     e.push_back(v);
   }
+  std::vector<StencilTuneEntry> entries() const {
+    std::lock_guard<std::mutex> lock(mu);
+    return e;
+  }
+
+ private:
+  mutable std::mutex mu;
+  std::vector<StencilTuneEntry> e;
 };
 StencilTuneTable& stencil_tune_table();
 

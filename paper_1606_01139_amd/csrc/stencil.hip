@@ -13,11 +13,15 @@
 // Mapping (2.5-D blocking): a workgroup owns a tx x ty tile of one xy plane
 // and walks a chunk of z planes.  Each thread keeps its point's 2R+1 z
 // neighbours in a register queue, so every interior value is read from HBM
-// once per walk; the x and y neighbours come from an LDS copy of the plane
-// with an R-wide halo (double-buffered: one barrier per plane).  Halo cells
-// outside the box hold zeros, which is the Dirichlet condition, so the tap
-// loop has no branches.
+// once per walk; the walk is unrolled by 2R+1 planes so that the queue
+// advances by renaming registers rather than moving them.  The x and y
+// neighbours come from an LDS copy of the plane with an R-wide halo
+// (double-buffered: one barrier per plane); each thread's halo cells are
+// fixed for the walk, and the next plane's are fetched into registers before
+// the barrier.  Halo cells outside the box hold zeros, which is the Dirichlet
+// condition, so the tap loop has no branches.
 #include <algorithm>
+#include <atomic>
 #include <string>
 
 #include "kernels.h"
@@ -26,7 +30,8 @@ namespace tsg {
 
 namespace {
 
-constexpr int kST = 512;  // threads per workgroup
+constexpr int kHaloSlots = 3;  // halo cells per thread and plane, at most
+constexpr int kPrefetch = 1;   // planes fetched ahead of the one being computed (measured: 1 is fastest)
 
 // Conditional load into registers (a value select, so the load stays a
 // global load rather than a generic one through a selected pointer).
@@ -42,25 +47,46 @@ __device__ inline void ld_or_zero(const cplx<T>* p, bool ok, T& re, T& im) {
   }
 }
 
-// YB points per thread, stacked in y (ty = kST / tx thread rows, tile height
+// NT threads per workgroup (256 or 512).
+// YB points per thread, stacked in y (ty = NT / tx thread rows, tile height
 // ty * YB): the y taps of a thread's points share one LDS column, and the
 // halo per output point shrinks as the tile grows taller.
-template <typename T, int R, int YB>
-__global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
+template <typename T, int R, int YB, int NT>
+__global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int slot = int(blockIdx.z) / a.ncols, col = int(blockIdx.z) % a.ncols;
+  // block -> (tile, z chunk, slot and column).  With the XCD-aware order
+  // the grid is one-dimensional and padded to a multiple of 8: hardware
+  // block b runs on XCD b % 8, and logical block (b % 8) * (nb / 8) + b / 8
+  // gives each XCD a contiguous range of logical blocks, tile fastest, so
+  // that neighbouring tiles and z chunks (which share halo planes) meet in
+  // the same L2.
+  int btile, bz, bsc;
+  if (a.xcd) {
+    const int64_t nb = int64_t(gridDim.x), b = int64_t(blockIdx.x);
+    const int64_t L = (b % 8) * (nb / 8) + b / 8;
+    if (L >= a.nblocks) return;
+    btile = int(L % a.tiles);
+    const int64_t rest = L / a.tiles;
+    bz = int(rest % a.nzc);
+    bsc = int(rest / a.nzc);
+  } else {
+    btile = int(blockIdx.x);
+    bz = int(blockIdx.y);
+    bsc = int(blockIdx.z);
+  }
+  const int slot = bsc / a.ncols, col = bsc % a.ncols;
   const int w = a.wmap ? a.wmap[slot] : slot;
   if (w < 0) return;  // idle slot (whole workgroup)
   const SysDesc& S = a.sys[a.wsys ? a.wsys[w] : 0];
   const int nx = S.nx, ny = S.ny, nz = S.nz;
   const int tx = a.tx, ty = a.ty, TY = ty * YB;
   const int tilesx = (nx + tx - 1) / tx, tilesy = (ny + TY - 1) / TY;
-  if (int(blockIdx.x) >= tilesx * tilesy) return;  // whole workgroup: smaller system
-  const int z0 = int(blockIdx.y) * a.zchunk;
+  if (btile >= tilesx * tilesy) return;  // whole workgroup: smaller system
+  const int z0 = bz * a.zchunk;
   if (z0 >= nz) return;
   const int z1 = min(nz, z0 + a.zchunk);
-  const int bx = int(blockIdx.x) % tilesx, by = int(blockIdx.x) / tilesx;
+  const int bx = btile % tilesx, by = btile / tilesx;
   const int lx = int(threadIdx.x) % tx, ly = int(threadIdx.x) / tx;
   const bool active = ly < ty;
   const int x = bx * tx + lx, y0 = by * TY + ly * YB;
@@ -84,29 +110,20 @@ __global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
   const int LW = tx + 2 * R, LH = TY + 2 * R;
   const int nhalo = 2 * R * LW + 2 * R * TY;
 
-  // qr[i][j], qi[i][j] hold point i's value at plane z - R + j (separate real
-  // arrays keep the queues in registers)
-  T qr[YB][2 * R + 1], qi[YB][2 * R + 1];
+  // This thread's halo cells, the same for every plane: LDS index (-1: none)
+  // and in-plane offset (valid only when the cell lies inside the box; cells
+  // outside stay zero, the Dirichlet condition).  kHaloSlots * NT covers the
+  // largest halo of the supported geometries (checked at launch).
+  int hl[kHaloSlots];
+  int64_t hg[kHaloSlots];
+  bool hok[kHaloSlots];
 #pragma unroll
-  for (int i = 0; i < YB; ++i)
-#pragma unroll
-    for (int j = 0; j < 2 * R + 1; ++j) {
-      const int zz = z0 - R + j;
-      ld_or_zero(X + zz * plane + xy[i], inside[i] && zz >= 0 && zz < nz, qr[i][j], qi[i][j]);
-    }
-  for (int z = z0; z < z1; ++z) {
-    cplx<T>* L = smem + ((z - z0) & 1) * (LW * LH);
-    // the next plane's values are fetched early to overlap their latency
-    const int zn = z + R + 1;
-    T nr[YB], ni[YB];
-#pragma unroll
-    for (int i = 0; i < YB; ++i) ld_or_zero(X + zn * plane + xy[i], inside[i] && zn < nz, nr[i], ni[i]);
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < YB; ++i) L[(ly * YB + i + R) * LW + lx + R] = cplx<T>{qr[i][R], qi[i][R]};
-    }
-    const cplx<T>* __restrict__ Xz = X + z * plane;
-    for (int e = int(threadIdx.x); e < nhalo; e += kST) {
+  for (int k = 0; k < kHaloSlots; ++k) {
+    const int e = int(threadIdx.x) + k * NT;
+    hl[k] = -1;
+    hg[k] = 0;
+    hok[k] = false;
+    if (e < nhalo) {
       int hx, hy;
       if (e < 2 * R * LW) {  // bands above and below the tile
         hy = e / LW;
@@ -115,51 +132,112 @@ __global__ __launch_bounds__(kST) void stencil_kernel(StencilArgs<T> a) {
       } else {               // bands left and right of the tile
         const int f = e - 2 * R * LW;
         hy = R + f / (2 * R);
-        const int k = f % (2 * R);
-        hx = k < R ? k : tx + k;
+        const int kk = f % (2 * R);
+        hx = kk < R ? kk : tx + kk;
       }
       const int gx = bx * tx + hx - R, gy = by * TY + hy - R;
-      T hr, hi;
-      ld_or_zero(Xz + (int64_t(gy) * nx + gx), gx >= 0 && gx < nx && gy >= 0 && gy < ny, hr, hi);
-      L[hy * LW + hx] = cplx<T>{hr, hi};
+      hl[k] = hy * LW + hx;
+      hok[k] = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      hg[k] = hok[k] ? int64_t(gy) * nx + gx : 0;
     }
-    __syncthreads();
-    if (active) {
-      const T g = G[z];
-      // x taps per point; y taps from one LDS column shared by the YB points
-      T ar[YB], ai[YB];
+  }
+
+  // z queue and prefetch pipeline.  Planes up to kPrefetch ahead are in
+  // flight: at unrolled step s of a group of Q planes (Q >= 2R + kPrefetch, a
+  // multiple of kPrefetch), plane z - R + j of point i sits in slot
+  // (s + j) % Q, so the queue advances by renaming registers rather than
+  // moving them; the halo cells and the potential of plane z sit in ring
+  // slot s % kPrefetch.
+  T cf[R + 1];  // tap weights, held in registers for the walk
 #pragma unroll
-      for (int i = 0; i < YB; ++i) {
-        const int64_t n = z * plane + xy[i];
-        const T d = diag0 + (inside[i] ? V[n] : T(0));
-        ar[i] = d * qr[i][R] + g * qi[i][R];
-        ai[i] = d * qi[i][R] - g * qr[i][R];
+  for (int m = 0; m <= R; ++m) cf[m] = T(S.coef[m]);
+
+  constexpr int PD = kPrefetch;
+  constexpr int Q = PD * ((2 * R + PD + PD - 1) / PD);
+  T qr[YB][Q], qi[YB][Q];
+#pragma unroll
+  for (int i = 0; i < YB; ++i)
+#pragma unroll
+    for (int j = 0; j < 2 * R + PD; ++j) {
+      const int zz = z0 - R + j;
+      ld_or_zero(X + zz * plane + xy[i], inside[i] && zz >= 0 && zz < nz, qr[i][j], qi[i][j]);
+    }
+  T hr[PD][kHaloSlots], hi[PD][kHaloSlots], vp[PD][YB];
+#pragma unroll
+  for (int r = 0; r < PD; ++r) {
+    const int zz = z0 + r;
+#pragma unroll
+    for (int k = 0; k < kHaloSlots; ++k) ld_or_zero(X + zz * plane + hg[k], zz < z1 && hok[k], hr[r][k], hi[r][k]);
+#pragma unroll
+    for (int i = 0; i < YB; ++i) vp[r][i] = (zz < z1 && inside[i]) ? V[zz * plane + xy[i]] : T(0);
+  }
+
+  for (int zb = z0; zb < z1; zb += Q) {
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      const int z = zb + s;
+      if (z >= z1) break;  // uniform over the workgroup
+      const int rs = s % PD;
+      cplx<T>* L = smem + ((z - z0) & 1) * (LW * LH);
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < YB; ++i)
+          L[(ly * YB + i + R) * LW + lx + R] = cplx<T>{qr[i][(s + R) % Q], qi[i][(s + R) % Q]};
       }
-      const cplx<T>* Lc = L + (ly * YB + R) * LW + lx + R;  // point 0
-      cplx<T> col[YB + 2 * R];
 #pragma unroll
-      for (int j = 0; j < YB + 2 * R; ++j) col[j] = Lc[(j - R) * LW];
+      for (int k = 0; k < kHaloSlots; ++k)
+        if (hl[k] >= 0) L[hl[k]] = cplx<T>{hr[rs][k], hi[rs][k]};
+      T vz[YB];
 #pragma unroll
-      for (int i = 0; i < YB; ++i) {
-        const cplx<T>* Li = Lc + i * LW;
+      for (int i = 0; i < YB; ++i) vz[i] = vp[rs][i];
+      // plane z + PD's halo and potential and plane z + R + PD's values are
+      // fetched before the barrier; their latency overlaps PD planes of taps
+      const int zf = z + PD;
+      const bool more = zf < z1;
 #pragma unroll
-        for (int m = 1; m <= R; ++m) {
-          const cplx<T> xa = Li[-m], xb = Li[m], c = col[R + i - m], e = col[R + i + m];
-          const T sr = (qr[i][R - m] + qr[i][R + m]) + ((xa.re + xb.re) + (c.re + e.re));
-          const T si = (qi[i][R - m] + qi[i][R + m]) + ((xa.im + xb.im) + (c.im + e.im));
-          const T cm = T(S.coef[m]);
-          ar[i] = fma(cm, sr, ar[i]);
-          ai[i] = fma(cm, si, ai[i]);
+      for (int k = 0; k < kHaloSlots; ++k) ld_or_zero(X + zf * plane + hg[k], more && hok[k], hr[rs][k], hi[rs][k]);
+#pragma unroll
+      for (int i = 0; i < YB; ++i) vp[rs][i] = (more && inside[i]) ? V[zf * plane + xy[i]] : T(0);
+      const int zn = z + R + PD;
+      T nr[YB], ni[YB];
+#pragma unroll
+      for (int i = 0; i < YB; ++i) ld_or_zero(X + zn * plane + xy[i], inside[i] && zn < nz, nr[i], ni[i]);
+      __syncthreads();
+      if (active) {
+        const T g = G[z];
+        // x taps per point; y taps from one LDS column shared by the YB points
+        T ar[YB], ai[YB];
+#pragma unroll
+        for (int i = 0; i < YB; ++i) {
+          const T d = diag0 + vz[i];
+          ar[i] = d * qr[i][(s + R) % Q] + g * qi[i][(s + R) % Q];
+          ai[i] = d * qi[i][(s + R) % Q] - g * qr[i][(s + R) % Q];
         }
-        if (inside[i]) Y[z * plane + xy[i]] = cplx<T>{ar[i], ai[i]};
+        const cplx<T>* Lc = L + (ly * YB + R) * LW + lx + R;  // point 0
+        cplx<T> col[YB + 2 * R];
+#pragma unroll
+        for (int j = 0; j < YB + 2 * R; ++j) col[j] = Lc[(j - R) * LW];
+#pragma unroll
+        for (int i = 0; i < YB; ++i) {
+          const cplx<T>* Li = Lc + i * LW;
+#pragma unroll
+          for (int m = 1; m <= R; ++m) {
+            const cplx<T> xa = Li[-m], xb = Li[m], c = col[R + i - m], e = col[R + i + m];
+            const int lo = (s + R - m) % Q, hi2 = (s + R + m) % Q;
+            const T sr = (qr[i][lo] + qr[i][hi2]) + ((xa.re + xb.re) + (c.re + e.re));
+            const T si = (qi[i][lo] + qi[i][hi2]) + ((xa.im + xb.im) + (c.im + e.im));
+            ar[i] = fma(cf[m], sr, ar[i]);
+            ai[i] = fma(cf[m], si, ai[i]);
+          }
+          if (inside[i]) Y[z * plane + xy[i]] = cplx<T>{ar[i], ai[i]};
+        }
       }
-    }
+      // plane z + R + PD enters the queue in the slot after the newest
 #pragma unroll
-    for (int i = 0; i < YB; ++i) {
-#pragma unroll
-      for (int j = 0; j < 2 * R; ++j) { qr[i][j] = qr[i][j + 1]; qi[i][j] = qi[i][j + 1]; }
-      qr[i][2 * R] = nr[i];
-      qi[i][2 * R] = ni[i];
+      for (int i = 0; i < YB; ++i) {
+        qr[i][(s + 2 * R + PD) % Q] = nr[i];
+        qi[i][(s + 2 * R + PD) % Q] = ni[i];
+      }
     }
   }
 }
@@ -174,12 +252,30 @@ StencilTuneTable& stencil_tune_table() {
   return t;
 }
 
+StencilGeom stencil_lookup(int nx, int ny, int nz, int64_t launch_cols, int elem, int radius, bool* tuned) {
+  StencilGeom gm;
+  const bool hit = stencil_tune_table().find(nx, ny, nz, launch_cols, elem, radius, gm);
+  if (!hit) gm = stencil_default_geometry(nx, ny, nz, launch_cols, radius);
+  if (tuned) *tuned = hit;
+  return gm;
+}
+
 template <typename T>
 void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin) {
-  StencilGeom gm;
-  if (!stencil_tune_table().find(nx, ny, nz, a.ncols * std::max(nwin, 1), int(sizeof(T)), a.radius, gm))
-    gm = stencil_default_geometry(nx, ny, nz, a.ncols * std::max(nwin, 1), a.radius);
+  // keyed by the complex element size, as the autotuner records it
+  const StencilGeom gm = stencil_lookup(nx, ny, nz, int64_t(a.ncols) * std::max(nwin, 1), int(sizeof(cplx<T>)),
+                                        a.radius, nullptr);
   stencil_apply_geometry(a, nx, ny, nz, gm);
+}
+
+bool stencil_geometry_valid(const StencilGeom& g, int radius) {
+  if (g.nt != 256 && g.nt != 512) return false;
+  if (g.tx < 1 || g.nt % g.tx != 0 || (g.yb != 1 && g.yb != 2) || g.zchunk < 1 || (g.xcd != 0 && g.xcd != 1))
+    return false;
+  if (radius < 1 || radius > 6) return false;
+  const int64_t TY = int64_t(g.nt / g.tx) * g.yb;
+  const int64_t nhalo = 2 * int64_t(radius) * (g.tx + 2 * radius) + 2 * int64_t(radius) * TY;
+  return nhalo <= int64_t(kHaloSlots) * g.nt;  // each thread holds at most kHaloSlots halo cells
 }
 
 StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols, int radius) {
@@ -188,7 +284,8 @@ StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols
   while (tx > 16 && tx / 2 >= nx) tx /= 2;
   g.tx = tx;
   g.yb = 1;
-  const int ty = kST / tx;
+  g.nt = 512;
+  const int ty = g.nt / tx;
   const int64_t tiles = int64_t((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
   // enough workgroups to fill the chip (a few per compute unit), but z
   // chunks long enough that the 2R planes a chunk re-reads stay minor
@@ -203,40 +300,57 @@ StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols
 template <typename T>
 void stencil_apply_geometry(StencilArgs<T>& a, int nx, int ny, int nz, const StencilGeom& gm) {
   a.tx = gm.tx;
-  a.ty = kST / gm.tx;
+  a.nt = gm.nt;
+  a.ty = gm.tx > 0 ? gm.nt / gm.tx : 0;
   a.yb = gm.yb;
+  a.xcd = gm.xcd;
   a.zchunk = std::max(1, std::min(gm.zchunk, nz));
   const int TY = a.ty * a.yb;
   a.tiles = ((nx + a.tx - 1) / a.tx) * ((ny + TY - 1) / TY);
 }
 
-template <typename T, int R, int YB>
+template <typename T, int R, int YB, int NT>
 void launch_r(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
   const size_t lds = size_t(2) * (a.tx + 2 * R) * (a.ty * YB + 2 * R) * sizeof(cplx<T>);
   if (lds > size_t(64) * 1024) {
-    static size_t granted = 0;
-    if (lds > granted) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T, R, YB>),
+    static std::atomic<size_t> granted{0};
+    if (lds > granted.load()) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T, R, YB, NT>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) throw DeviceError(std::string("stencil: LDS attribute: ") + hipGetErrorString(e));
-      granted = lds;
+      size_t cur = granted.load();
+      while (lds > cur && !granted.compare_exchange_weak(cur, lds)) {
+      }
     }
   }
-  hipLaunchKernelGGL((stencil_kernel<T, R, YB>), grid, dim3(kST), lds, s, a);
+  hipLaunchKernelGGL((stencil_kernel<T, R, YB, NT>), grid, dim3(NT), lds, s, a);
 }
 
 template <typename T, int R>
 void launch_yb(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
-  if (a.yb == 2) launch_r<T, R, 2>(a, grid, s);
-  else launch_r<T, R, 1>(a, grid, s);
+  if (a.nt == 256) {
+    if (a.yb == 2) launch_r<T, R, 2, 256>(a, grid, s);
+    else launch_r<T, R, 1, 256>(a, grid, s);
+  } else {
+    if (a.yb == 2) launch_r<T, R, 2, 512>(a, grid, s);
+    else launch_r<T, R, 1, 512>(a, grid, s);
+  }
 }
 
 template <typename T>
 void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s) {
   if (nwin <= 0 || a.ncols <= 0) return;
-  if (a.tx < 1 || kST % a.tx != 0 || (a.yb != 1 && a.yb != 2) || a.zchunk < 1)
+  if (!stencil_geometry_valid(StencilGeom{a.tx, a.yb, a.zchunk, a.xcd, a.nt}, a.radius))
     throw DeviceError("stencil: invalid launch geometry");
-  dim3 grid(unsigned(a.tiles), unsigned((max_nz + a.zchunk - 1) / a.zchunk), unsigned(nwin * a.ncols));
+  a.nzc = (max_nz + a.zchunk - 1) / a.zchunk;
+  a.nblocks = int64_t(a.tiles) * a.nzc * nwin * a.ncols;
+  dim3 grid(unsigned(a.tiles), unsigned(a.nzc), unsigned(nwin * a.ncols));
+  if (a.xcd) {
+    const int64_t padded = ((a.nblocks + 7) / 8) * 8;
+    // the dispatch counts work-items in 32 bits
+    if (padded * a.nt > int64_t(0xffffffff)) throw DeviceError("stencil: grid too large for the XCD-aware order");
+    grid = dim3(unsigned(padded), 1, 1);
+  }
   switch (a.radius) {
     case 1: launch_yb<T, 1>(a, grid, s); break;
     case 2: launch_yb<T, 2>(a, grid, s); break;

@@ -23,8 +23,8 @@ std::string entry_json(const StencilTuneEntry& x) {
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "{\"nx\": %d, \"ny\": %d, \"nz\": %d, \"cols\": %d, \"elem\": %d, \"radius\": %d, \"tx\": %d, "
-                "\"yb\": %d, \"zchunk\": %d, \"us\": %.3f}",
-                x.nx, x.ny, x.nz, x.cols, x.elem, x.radius, x.g.tx, x.g.yb, x.g.zchunk, x.us);
+                "\"yb\": %d, \"zchunk\": %d, \"xcd\": %d, \"nt\": %d, \"us\": %.3f}",
+                x.nx, x.ny, x.nz, x.cols, x.elem, x.radius, x.g.tx, x.g.yb, x.g.zchunk, x.g.xcd, x.g.nt, x.us);
   return buf;
 }
 
@@ -41,11 +41,11 @@ bool field(const std::string& obj, const char* key, double& v) {
 }  // namespace
 
 void write_tuning(const std::string& path) {
-  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::lock_guard<std::mutex> lock(g_tune_mu);  // one writer of the file at a time
   FILE* f = std::fopen(path.c_str(), "w");
   if (!f) throw InvalidArg("cannot write the tuning file " + path);
   std::fprintf(f, "{\"stencil\": [\n");
-  const auto& e = stencil_tune_table().e;
+  const std::vector<StencilTuneEntry> e = stencil_tune_table().entries();
   for (size_t i = 0; i < e.size(); ++i)
     std::fprintf(f, "  %s%s\n", entry_json(e[i]).c_str(), i + 1 < e.size() ? "," : "");
   std::fprintf(f, "]}\n");
@@ -73,15 +73,16 @@ int load_tuning(const std::string& path) {
     bool ok = true;
     for (int i = 0; i < 10; ++i) ok = ok && field(obj, keys[i], v[i]);
     if (!ok) throw InvalidArg("malformed tuning entry: " + obj);
+    double xcd = 0.0, nt = 512.0;  // optional keys: launch order, 512 threads
+    (void)field(obj, "xcd", xcd);
+    (void)field(obj, "nt", nt);
     StencilTuneEntry x{int(v[0]), int(v[1]), int(v[2]), int(v[3]), int(v[4]), int(v[5]),
-                       StencilGeom{int(v[6]), int(v[7]), int(v[8])}, v[9]};
-    if (x.g.tx < 1 || 512 % x.g.tx != 0 || (x.g.yb != 1 && x.g.yb != 2) || x.g.zchunk < 1 || x.cols < 1 ||
-        (x.elem != 8 && x.elem != 16) || x.radius < 1 || x.radius > 6)
+                       StencilGeom{int(v[6]), int(v[7]), int(v[8]), int(xcd), int(nt)}, v[9]};
+    if (x.cols < 1 || (x.elem != 8 && x.elem != 16) || !stencil_geometry_valid(x.g, x.radius))
       throw InvalidArg("invalid tuning entry: " + obj);
     got.push_back(x);
     p = b + 1;
   }
-  std::lock_guard<std::mutex> lock(g_tune_mu);
   for (const auto& x : got) stencil_tune_table().put(x);
   return int(got.size());
 }
@@ -124,14 +125,18 @@ StencilTuneEntry tune_t(tsg_ctx* c, int ncols, int reps, int* n_tried) {
   struct Ev { hipEvent_t a, b; ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); } } ev{e0, e1};
   const StencilGeom def = stencil_default_geometry(c->nx, c->ny, c->nz, ncols, c->R);
   std::vector<StencilGeom> cand{def};
-  for (int tx : {16, 32, 64}) {
-    if (tx > 2 * std::max(c->nx, 16)) continue;
-    for (int yb : {1, 2})
-      for (int zc : {16, 24, 32, 48, 64, 96, 128, 192}) {
-        if (zc > c->nz && zc != 16) continue;
-        cand.push_back(StencilGeom{tx, yb, std::min(zc, c->nz)});
-      }
-  }
+  for (int nt : {256, 512})
+    for (int tx : {16, 32, 64}) {
+      if (tx > 2 * std::max(c->nx, 16)) continue;
+      for (int yb : {1, 2})
+        for (int zc : {16, 24, 32, 48, 64, 96, 128, 192}) {
+          if (zc > c->nz && zc != 16) continue;
+          for (int xcd : {0, 1}) {
+            const StencilGeom g{tx, yb, std::min(zc, c->nz), xcd, nt};
+            if (stencil_geometry_valid(g, c->R)) cand.push_back(g);
+          }
+        }
+    }
   StencilTuneEntry best{c->nx, c->ny, c->nz, ncols, int(sizeof(cplx<T>)), c->R, def, 1e300};
   for (const StencilGeom& g : cand) {
     const double us = time_geometry<T>(c, X.p, Y.p, ncols, g, reps, e0, e1);
@@ -150,7 +155,6 @@ StencilTuneEntry tune_stencil(tsg_ctx* c, int ncols, int dtype, int reps, int* n
   if (dtype == TSG_C128) e = tune_t<double>(c, ncols, reps, n_tried);
   else if (dtype == TSG_C64) e = tune_t<float>(c, ncols, reps, n_tried);
   else throw InvalidArg("dtype must be TSG_C128 or TSG_C64");
-  std::lock_guard<std::mutex> lock(g_tune_mu);
   stencil_tune_table().put(e);
   return e;
 }

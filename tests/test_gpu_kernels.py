@@ -84,22 +84,29 @@ def test_stencil_c64_matches_oracle(torch_cuda, shape, B):
 
 
 # every geometry the autotuner may pick: tile widths 16/32/64, one or two
-# points per thread in y, z chunks shorter and longer than the grid, on
-# ragged tiles in x and y
-@pytest.mark.parametrize("tx,yb,zc", [(16, 1, 16), (16, 2, 24), (32, 2, 5), (64, 2, 48), (32, 1, 192), (64, 1, 7)])
+# points per thread in y, z chunks shorter and longer than the grid, launch
+# order and XCD-grouped order, on ragged tiles in x and y (block counts that
+# are not multiples of 8, so the padded XCD grid has idle workgroups)
+@pytest.mark.parametrize("tx,yb,zc,xcd,nt", [(16, 1, 16, 0, 512), (16, 2, 24, 1, 512), (32, 2, 5, 0, 512),
+                                             (32, 2, 5, 1, 512), (64, 2, 48, 0, 512), (32, 1, 192, 1, 512),
+                                             (64, 1, 7, 0, 512), (64, 1, 7, 1, 512), (16, 1, 16, 1, 256),
+                                             (16, 2, 9, 0, 256), (32, 1, 5, 1, 256), (32, 2, 48, 1, 256)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_stencil_tuned_geometries_match_oracle(torch_cuda, tmp_path, tx, yb, zc, dtype):
+def test_stencil_tuned_geometries_match_oracle(torch_cuda, tmp_path, tx, yb, zc, xcd, nt, dtype):
     torch = torch_cuda
     from oracle import operator as op
     from paper_1606_01139_amd import Operator
     from paper_1606_01139_amd.binding import load_tuning
     nx, ny, nz, B = 37, 29, 21, 3
-    print(f"stencil geometry tx={tx} yb={yb} zchunk={zc} {dtype}", flush=True)
+    print(f"stencil geometry tx={tx} yb={yb} zchunk={zc} xcd={xcd} nt={nt} {dtype}", flush=True)
     elem = 16 if dtype == "c128" else 8
     f = tmp_path / "tune.json"
     f.write_text('{"stencil": [{"nx": %d, "ny": %d, "nz": %d, "cols": %d, "elem": %d, "radius": 6, "tx": %d, '
-                 '"yb": %d, "zchunk": %d, "us": 0}]}' % (nx, ny, nz, B, elem, tx, yb, zc))
+                 '"yb": %d, "zchunk": %d, "xcd": %d, "nt": %d, "us": 0}]}' % (nx, ny, nz, B, elem, tx, yb, zc, xcd, nt))
     assert load_tuning(str(f)) == 1
+    from paper_1606_01139_amd.binding import stencil_geometry, C128, C64
+    used = stencil_geometry(nx, ny, nz, B, C128 if dtype == "c128" else C64)
+    assert used == {"tx": tx, "yb": yb, "zchunk": min(zc, nz), "xcd": xcd, "nt": nt, "tuned": True}, used
     V, ab, gL, gR = _fields(nx, ny, nz, 8)
     N = nx * ny * nz
     rng = np.random.default_rng(9)
@@ -132,6 +139,9 @@ def test_stencil_autotuner_picks_a_candidate_and_keeps_parity(torch_cuda, tmp_pa
     assert geo["tx"] in (16, 32, 64) and geo["yb"] in (1, 2) and 1 <= geo["zchunk"] <= nz and geo["tried"] > 10
     assert us > 0
     assert load_tuning(str(out)) >= 1
+    from paper_1606_01139_amd.binding import stencil_geometry
+    used = stencil_geometry(nx, ny, nz, B, 0)
+    assert used["tuned"] and all(used[k] == geo[k] for k in ("tx", "yb", "zchunk", "xcd", "nt")), (used, geo)
     N = nx * ny * nz
     X = np.random.default_rng(12).standard_normal((N, B)) + 0.5j
     ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X, 6)
