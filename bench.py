@@ -356,7 +356,16 @@ class CpuSample:
         """Result of the started job, waiting until `deadline` (perf_counter
         seconds) at most; an unfinished run ends the worker."""
         kind, shift, nev, threads = self.job
-        if self.conn.poll(max(deadline - time.perf_counter(), 0.0)):
+        ready = False
+        while True:  # a progress line every 30 s while the oracle runs
+            left = deadline - time.perf_counter()
+            if self.conn.poll(max(min(left, 30.0), 0.0)):
+                ready = True
+                break
+            if left <= 30.0:
+                break
+            log(f"oracle {kind} sample still running ({time.perf_counter() - self.t_job:.0f} s, {threads} threads)")
+        if ready:
             kind, dt, n = self.conn.recv()
             if kind == "ok":
                 return {"seconds": round(dt, 2), "eigenpairs": n, "value": round(n / dt, 4), "threads": threads}
@@ -457,8 +466,9 @@ def main():
                     help="seconds of timed steps at most (at least one step is timed)")
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "bulk"])
-    ap.add_argument("--compare-bulk", action="store_true",
-                    help="also time the same steps in the other precision mode and report the FP32-bulk speedup")
+    ap.add_argument("--no-compare-bulk", dest="compare_bulk", action="store_false",
+                    help="skip the steps in the other precision mode (by default they run after the timed "
+                         "steps, beside the oracle's interior-window sample, for the FP32-bulk speedup)")
     ap.add_argument("--max-restarts", type=int, default=2000)
     ap.add_argument("--max-windows", type=int, default=0)
     ap.add_argument("--plan", default="semiclassical", choices=["semiclassical", "sampled", "alg1"])
@@ -604,21 +614,11 @@ def main():
                      "max_backward_error": s.max_backward_error} for s in stats],
     }
     oper.close()
-    if args.compare_bulk:
-        other = FP32_BULK if prec == FP64 else FP64
-        t_now = time.perf_counter()
-        left = max(deadline - reserve - t_now, 0.0)
-        dt2, total2, steps2, _, last2 = run_budgeted(w, make_opts(other), args, "other precision",
-                                                     t_now + 0.3 * left, t_now + left)
-        last2[0].close()
-        t64, tb = (dt / steps, dt2 / steps2) if prec == FP64 else (dt2 / steps2, dt / steps)
-        out["fp32_bulk_vs_fp64"] = {"fp64_s_per_step": round(t64, 2), "bulk_s_per_step": round(tb, 2),
-                                    "speedup": round(t64 / tb, 3), "other_unique_converged": last2[1],
-                                    "other_steps": steps2}
+    single = multi = window = None
+    window_started = False
     if cpu is not None:
         log("waiting for the oracle's single-thread sample")
         single = cpu.result(deadline - 0.5 * reserve)
-        multi = window = None
         if "value" in single:
             ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
             threads = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS", ncpu))))
@@ -628,9 +628,29 @@ def main():
                 multi = cpu.result(deadline - 5.0)
             left = deadline - time.perf_counter() - 5.0
             if "value" in (multi or {}) and left > 20.0:
+                # one thread, beside the other-precision steps on the GPU
                 log(f"the oracle on an interior window for {left:.0f} s at most")
                 cpu.start("window", cpu_shift, CPU_SAMPLE_NEV, 1)
-                window = cpu.result(deadline - 3.0)
+                window_started = True
+    if args.compare_bulk:
+        other = FP32_BULK if prec == FP64 else FP64
+        t_now = time.perf_counter()
+        left = max(deadline - 5.0 - t_now, 0.0)
+        steps2 = 0
+        if left > 3.0 * dt / steps:  # room for a warm-up and a timed step at about 1.5 x the time
+            dt2, total2, steps2, _, last2 = run_budgeted(w, make_opts(other), args, "other precision",
+                                                         t_now + 0.3 * left, t_now + left)
+        if steps2:
+            last2[0].close()
+            t64, tb = (dt / steps, dt2 / steps2) if prec == FP64 else (dt2 / steps2, dt / steps)
+            out["fp32_bulk_vs_fp64"] = {"fp64_s_per_step": round(t64, 2), "bulk_s_per_step": round(tb, 2),
+                                        "speedup": round(t64 / tb, 3), "other_unique_converged": last2[1],
+                                        "other_status": int(last2[3]), "other_steps": steps2}
+        else:
+            out["fp32_bulk_vs_fp64"] = {"skipped": "no time left in the budget for a step"}
+    if cpu is not None:
+        if window_started:
+            window = cpu.result(deadline - 3.0)
         cpu.close()
         out["cpu_baseline"] = cpu_baseline_line(single, multi, window, args.config, CPU_LOWEST_NEV, cpu_shift)
     out["wall_s"] = round(time.perf_counter() - t_launch, 1)

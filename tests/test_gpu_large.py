@@ -1,0 +1,75 @@
+"""The large grid (c5: 64 x 64 x 160, N = 655,360, 32 windows x 64 pairs) on
+three of its planned windows: the first, a middle and the last.  No oracle
+eigensolve finishes at this size, so the pairs are checked against the
+oracle's own FP64 operator (a property that holds at any size): each sampled
+pair is an eigenpair of A to backward error 1e-8, c-normalised, with
+Im eps in [-max Gamma, 0].
+
+The first window (the exterior end) converges in a few restarts.  The
+interior ones do not converge within 800 complex64 + 600 FP64 restarts at
+this size (worst backward error still about 5e-4), so they run under a small
+restart cap here (TSG_LARGE_RESTARTS, default 40) and only the pairs they
+return are checked.  Minutes of GPU time, so opt-in: TSG_LARGE=1.  Run with
+-s to see the statistics."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("TSG_LARGE") != "1",
+                                 reason="c5 subset takes minutes of GPU time; set TSG_LARGE=1")]
+
+
+def test_c5_first_middle_last_windows_against_oracle_operator():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import operator as op
+    from paper_1606_01139_amd import FP32_BULK, Operator, PLAN_SEMICLASSICAL, default_opts
+    from synth.workloads import workload
+    torch.cuda.set_device(0)
+    w = workload("c5")
+    g = w.grid
+    ab = w.absorber.as_tuple()
+    cap = int(os.environ.get("TSG_LARGE_RESTARTS", "40"))
+    opts = default_opts(precision=FP32_BULK, tol=1e-8, max_restarts=cap)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, ab)
+    plan, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    pick = [0, len(plan) // 2, len(plan) - 1]
+    wins = [plan[i] for i in pick]
+    print(f"c5: planned {len(plan)} windows over {erange}; solving {pick}: {wins}", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n, holes, status = oper.solve_all_partitions(wins, opts, allow_noconv=True)
+    dt = time.perf_counter() - t0
+    print(f"c5 subset: {n} unique pairs in {dt:.1f} s ({n / dt:.2f} pairs/s), status {status}", flush=True)
+
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    gmax = float((gL + gR).max())
+    nrm = op.gershgorin_norm(g.h, w.V, gmax)
+    rng = np.random.default_rng(5)
+    for j in range(len(wins)):
+        st = oper.stats(j)
+        print(f"window {pick[j]} shift {st.shift:.6f}: {st.n_conv}/{st.nev} converged, restarts "
+              f"{st.restarts_bulk} complex64 + {st.restarts} FP64, {st.matvecs} matvecs, "
+              f"worst backward error {st.max_backward_error:.2e}", flush=True)
+        eps, U = oper.partition(j)
+        assert len(eps) == st.n_conv
+        if j == 0:
+            # the exterior window converges well inside any cap
+            assert st.n_conv == st.nev
+        assert (eps.imag <= 1e-12 * nrm).all() and (eps.imag >= -gmax - 1e-12 * nrm).all()
+        if len(eps) == 0:
+            continue
+        idx = rng.choice(len(eps), size=min(3, len(eps)), replace=False)
+        for k in idx:
+            u = U[:, int(k)].cpu().numpy()
+            r = op.apply_operator(g.nx, g.ny, g.nz, g.h, w.V, gL, gR, u[:, None])[:, 0] - eps[k] * u
+            be = np.linalg.norm(r) / (nrm * np.linalg.norm(u))
+            print(f"  pair {int(k)}: eps {eps[k]:.8f}, oracle backward error {be:.2e}, "
+                  f"|u^T u - 1| {abs(u @ u - 1.0):.1e}", flush=True)
+            assert be <= 1e-8
+            assert abs(u @ u - 1.0) <= 1e-10
+    oper.close()
