@@ -261,6 +261,55 @@ def test_gradient_matches_central_differences():
         assert abs(fd - gr["abs"][p]) <= 1e-6 * max(1.0, abs(fd)), (p, fd, gr["abs"][p])
 
 
+def test_gradient_projected_matches_central_differences():
+    # Tier B (set S alone, bordered sparse solves) against central
+    # differences of the oracle pipeline, on the same system as above.
+    w = small_workload(4, 4, 8, 2, seed=13, amp=0.6, width=1.5)
+    g = w.grid
+    ab = np.array(w.absorber.as_tuple())
+    shifts, nev = [-1.0, 1.0], 8
+    T0, ea, Ua, c, gL, gR = _pipeline_T(g.nx, g.ny, g.nz, g.h, w.V, ab, shifts, nev, [0.0])
+    E = transport.energy_grid(c.eps, 5)
+    wts = np.linspace(0.5, 1.5, len(E))
+    As = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    dg = gradient.absorber_param_derivs(g.nx, g.ny, g.nz, g.h, ab)
+    gr = gradient.gradient_projected(As, c.eps, c.U, gL, gR, dg, E, wts)
+    L = lambda V, a: float(wts @ _pipeline_T(g.nx, g.ny, g.nz, g.h, V, a, shifts, nev, E)[0])
+    step = 1e-5
+    rng = np.random.default_rng(1)
+    for r in rng.choice(g.n, 6, replace=False):
+        dv = np.zeros(g.n); dv[r] = step
+        fd = (L(w.V + dv, ab) - L(w.V - dv, ab)) / (2 * step)
+        assert abs(fd - gr["V"][r]) <= 1e-6 * max(1.0, abs(fd)), (r, fd, gr["V"][r])
+    for p, ip in enumerate([0, 1, 3, 4]):
+        da = np.zeros(6); da[ip] = step
+        fd = (L(w.V, ab + da) - L(w.V, ab - da)) / (2 * step)
+        assert abs(fd - gr["abs"][p]) <= 1e-6 * max(1.0, abs(fd)), (p, fd, gr["abs"][p])
+
+
+def test_gradient_projected_equals_full_basis_on_interior_window():
+    # The two tiers compute the same derivative by different routes (the
+    # full eigen-expansion against sparse solves with S alone): an interior
+    # window of 12 on an 8 x 8 x 12 grid, whose out-of-set part is large.
+    w = small_workload(8, 8, 12, 3, seed=11)
+    g = w.grid
+    ab = w.absorber.as_tuple()
+    gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, ab)
+    A = op.assemble_dense(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    As = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR)
+    ea, Ua = eigen.dense_spectrum(A)
+    order = eigen.order_nearest(ea, float(ea[30].real))
+    in_set = np.zeros(len(ea), bool)
+    in_set[order[:12]] = True
+    dg = gradient.absorber_param_derivs(g.nx, g.ny, g.nz, g.h, ab)
+    E = np.linspace(ea[in_set].real.min() - 0.1, ea[in_set].real.max() + 0.1, 5)
+    wts = np.random.default_rng(1).uniform(0.5, 1.5, 5)
+    ref = gradient.gradient_full_basis(ea, Ua, in_set, gL, gR, dg, E, wts)
+    got = gradient.gradient_projected(As, ea[in_set], Ua[:, in_set], gL, gR, dg, E, wts)
+    assert np.abs(got["V"] - ref["V"]).max() <= 1e-10 * np.abs(ref["V"]).max()
+    np.testing.assert_allclose(got["abs"], ref["abs"], rtol=1e-10, atol=1e-10 * np.abs(ref["abs"]).max())
+
+
 def test_gradient_full_spectrum_equals_direct_adjoint():
     # With S = whole spectrum the out-of-set term vanishes and the gradient
     # of T wrt V(r) is 2 Re[(G Gamma_R G^H Gamma_L G)_rr] of the direct G.
