@@ -214,6 +214,61 @@ def test_ragged_batch_matches_oracle(torch_cuda, precision):
         op_.close()
 
 
+def test_ragged_batch_c3_systems_match_oracle(torch_cuda):
+    """Three systems of the c3 draw itself (N = 6,336 to 7,904, different
+    shapes and wells) with 4 windows each in one batched iteration, the c3
+    precision (complex64 bulk, FP64 small eigensolves and finish).  The
+    oracle takes each system's lowest eigenpairs (ARPACK 'SR', exact below
+    its trusted bound), places each window between two of them with a gap of
+    at least 1e-3 Ha at the window's edge, and forms the window sets and
+    Algorithm 2's combined set; the GPU must return the same set (1e-10)
+    with vectors that are eigenvectors of the oracle's operator."""
+    from oracle import eigen, operator as op, partition
+    from paper_1606_01139_amd import FP32_BULK, Operator, default_opts, solve_batch
+    from synth.workloads import batch_workloads
+    print("ragged batch on c3 systems", flush=True)
+    ws = batch_workloads(64)
+    ops, refs, wins = [], [], []
+    for i in (6, 2, 12):
+        w = ws[i]
+        g = w.grid
+        gL, gR = op.gamma_fields(g.nx, g.ny, g.nz, g.h, w.absorber.as_tuple())
+        As = op.assemble_sparse(g.nx, g.ny, g.nz, g.h, w.V, gL, gR).tocsr()
+        nrm = op.gershgorin_norm(g.h, w.V, (gL + gR).max())
+        e, U, e_trust = eigen.lowest_real_pairs(As, 72, guard=24)
+        wj, parts = [], []
+        for j in range(4):
+            sigma = 0.5 * float(e[12 * j + 5].real + e[12 * j + 6].real)
+            order = eigen.order_nearest(e, sigma)
+            d = np.abs(e[order] - sigma)
+            nev = next(k for k in range(8, 14) if d[k] - d[k - 1] > 1e-3)
+            # every eigenvalue nearer sigma than the window's edge is in the trusted set
+            assert d[nev - 1] < e_trust - sigma
+            wj.append((sigma, nev))
+            parts.append((e[order[:nev]], U[:, order[:nev]]))
+        ref = partition.combine(parts, nrm)
+        refs.append((ref, As, nrm, e))
+        wins.append(wj)
+        ops.append(Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple()))
+        print(f"system {i}: {g.nx}x{g.ny}x{g.nz}, windows {[(round(s, 4), k) for s, k in wj]}", flush=True)
+    nu, status = solve_batch(ops, wins, default_opts(precision=FP32_BULK))
+    assert status == 0
+    for s_, op_ in enumerate(ops):
+        ref, As, nrm, e = refs[s_]
+        assert nu[s_] == len(ref.eps)
+        eps = op_.eigenvalues()
+        _match_sets(eps, ref.eps, 1e-10)
+        Ug = op_.eigenvectors().cpu().numpy()
+        vt = _vector_tol(e, eps, nrm)
+        np.testing.assert_allclose(np.diag(Ug.T @ Ug), np.ones(len(eps)), atol=1e-12)
+        for k in range(len(eps)):
+            dk = min(np.linalg.norm(Ug[:, k] - ref.U[:, k]), np.linalg.norm(Ug[:, k] + ref.U[:, k]))
+            assert dk <= vt, (s_, k, dk, vt)
+            r = As @ Ug[:, k] - eps[k] * Ug[:, k]
+            assert np.linalg.norm(r) / (nrm * np.linalg.norm(Ug[:, k])) <= 1e-8
+        op_.close()
+
+
 def test_hole_filling_matches_oracle(torch_cuda):
     # Algorithm 1's repeat loop from two windows far apart: the same inserted
     # partitions, round count and final combined set as the oracle's loop
