@@ -20,7 +20,6 @@ namespace {
 
 constexpr int kGT = 64;   // gram tile (rows and columns of C)
 constexpr int kGK = 16;   // grid rows of X, Y staged per step
-constexpr int kGR = kGT / 16;  // outputs per thread along each tile axis
 
 inline int gram_chunks(int64_t N, int r, int s, int nwin) {
   const int64_t tiles = int64_t((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT) * nwin;
@@ -37,13 +36,27 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// One tile C[i0 : i0 + 64, j0 : j0 + 64] of X^H Y over one chunk of grid
+// rows, on the matrix cores.  Complex products are four real ones:
+//   Re(conj(x) y) = xr yr + xi yi,   Im(conj(x) y) = xr yi - xi yr,
+// each a 16 x 16 x 4 FP64 MFMA (A = X^T, 16 columns by 4 grid rows; B = Y,
+// 4 grid rows by 16 columns).  Operand layout of that instruction (measured
+// on gfx950 with one-hot inputs): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16] in its v-th
+// accumulator (v < 4).  The four
+// wavefronts of the workgroup each own a 32 x 32 quarter of the tile
+// (2 x 2 blocks of 16 x 16); kGK staged grid rows are 4 k-steps.
+typedef double gram_v4d __attribute__((ext_vector_type(4)));
+
 template <typename TX, typename TY>
-__global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
-                                                           const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
-                                                           Rows rows, int r, int s, int nchunk,
-                                                           c128* __restrict__ P, const int* __restrict__ wmap) {
-  __shared__ c128 Xs[kGK][kGT + 1];
-  __shared__ c128 Ys[kGK][kGT + 1];
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const cplx<TX>* __restrict__ X, int64_t ldx, int64_t wsx,
+                                                        const cplx<TY>* __restrict__ Y, int64_t ldy, int64_t wsy,
+                                                        Rows rows, int r, int s, int nchunk,
+                                                        c128* __restrict__ P, const int* __restrict__ wmap) {
+  // staged rows, real and imaginary parts apart (a lane's 16 neighbours
+  // read 16 consecutive doubles)
+  __shared__ double Xr[kGK][kGT + 1], Xi[kGK][kGT + 1];
+  __shared__ double Yr[kGK][kGT + 1], Yi[kGK][kGT + 1];
   const int wz = blockIdx.z;
   const int w = wmap ? wmap[wz] : wz;
   if (w < 0) return;  // idle slot (whole workgroup)
@@ -55,54 +68,72 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const cplx<TX>* __res
   const int64_t n0 = chunk * rows_per;
   const int64_t n1 = min(N, n0 + rows_per);
   const int t = threadIdx.x;
-  const int tx = t % 16, ty = t / 16;
+  const int lane = t % 64, wave = t / 64;
+  const int li = lane % 16, lq = lane / 16;
+  const int wi = (wave / 2) * 32, wj = (wave % 2) * 32;  // this wavefront's quarter
   const int i0 = ti * kGT, j0 = tj * kGT;
   X += int64_t(w) * wsx;
   Y += int64_t(w) * wsy;
-  // thread (tx, ty) owns C[i0 + ty + 16 a][j0 + tx + 16 b]: per staged row,
-  // kGR + kGR LDS reads feed kGR * kGR complex multiply-adds
-  c128 acc[kGR][kGR];
+  gram_v4d cr[2][2], ci[2][2];
 #pragma unroll
-  for (int a = 0; a < kGR; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < kGR; ++b) acc[a][b] = c128{0.0, 0.0};
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = gram_v4d{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = gram_v4d{0.0, 0.0, 0.0, 0.0};
+    }
   for (int64_t nb = n0; nb < n1; nb += kGK) {
-    // stage kGK rows of kGT columns of X and Y; consecutive threads read
-    // consecutive rows of one column
+    // consecutive threads read consecutive rows of one column
     for (int e = t; e < kGK * kGT; e += 256) {
       const int cc = e / kGK, rr = e % kGK;
       const int64_t n = nb + rr;
-      c128 xv{0.0, 0.0}, yv{0.0, 0.0};
+      double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
       if (n < n1) {
-        if (i0 + cc < r) { cplx<TX> v = X[int64_t(i0 + cc) * ldx + n]; xv = c128{double(v.re), double(v.im)}; }
-        if (j0 + cc < s) { cplx<TY> v = Y[int64_t(j0 + cc) * ldy + n]; yv = c128{double(v.re), double(v.im)}; }
+        if (i0 + cc < r) { const cplx<TX> v = X[int64_t(i0 + cc) * ldx + n]; xr = double(v.re); xi = double(v.im); }
+        if (j0 + cc < s) { const cplx<TY> v = Y[int64_t(j0 + cc) * ldy + n]; yr = double(v.re); yi = double(v.im); }
       }
-      Xs[rr][cc] = xv;
-      Ys[rr][cc] = yv;
+      Xr[rr][cc] = xr;
+      Xi[rr][cc] = xi;
+      Yr[rr][cc] = yr;
+      Yi[rr][cc] = yi;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kGK; ++k) {
-      c128 xv[kGR], yv[kGR];
 #pragma unroll
-      for (int a = 0; a < kGR; ++a) xv[a] = Xs[k][ty + 16 * a];
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const int k = 4 * ks + lq;
+      double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int b = 0; b < kGR; ++b) yv[b] = Ys[k][tx + 16 * b];
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Xr[k][wi + 16 * a + li];
+        ai[a] = Xi[k][wi + 16 * a + li];
+      }
 #pragma unroll
-      for (int a = 0; a < kGR; ++a)
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Yr[k][wj + 16 * b + li];
+        bi[b] = Yi[k][wj + 16 * b + li];
+      }
 #pragma unroll
-        for (int b = 0; b < kGR; ++b) fma_cacc(acc[a][b], xv[a], yv[b]);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], br[b], ci[a][b], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
   c128* Pw = P + (int64_t(wz) * nchunk + chunk) * int64_t(r) * s;
 #pragma unroll
-  for (int a = 0; a < kGR; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < kGR; ++b) {
-      const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
-      if (i < r && j < s) Pw[int64_t(i) * s + j] = acc[a][b];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wi + 16 * a + lq + 4 * v, j = j0 + wj + 16 * b + li;
+        if (i < r && j < s) Pw[int64_t(i) * s + j] = c128{cr[a][b][v], ci[a][b][v]};
+      }
 }
 
 __global__ void gram_reduce_kernel(const c128* __restrict__ P, int nchunk, int r, int s, c128* __restrict__ C,
@@ -712,7 +743,7 @@ void gram(const cplx<TX>* X, int64_t ldx, int64_t wsx, const cplx<TY>* Y, int64_
                          r, s, nchunk, partials, wmap);
   } else {
     const int tiles = ((r + kGT - 1) / kGT) * ((s + kGT - 1) / kGT);
-    hipLaunchKernelGGL((gram_partial_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
+    hipLaunchKernelGGL((gram_mfma_kernel<TX, TY>), dim3(nchunk, tiles, nwin), dim3(256), 0, st, X, ldx, wsx, Y,
                        ldy, wsy, rows, r, s, nchunk, partials, wmap);
   }
   const int64_t rs = int64_t(r) * s;
