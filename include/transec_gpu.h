@@ -314,18 +314,19 @@ tsg_status tsg_dense_eig(void* H, int32_t m, int32_t batch, void* theta, void* Y
  * (256 or 512 threads per workgroup, tile width 16/32/64, one or two
  * points per thread in y, z chunk of 16..192 planes, workgroups in launch
  * order or grouped so that each of the eight XCDs runs a contiguous range of
- * neighbouring tiles) is timed on ctx's grid for a launch of ncols vectors of
+ * neighbouring tiles, one or (complex64 only) two columns per thread) is timed on ctx's grid for a launch of ncols vectors of
  * element type dtype (reps launches each, HIP events on ctx's stream); the
  * fastest is recorded in the process-wide table that every later stencil
  * launch with the same grid shape, column count, element size and radius
  * uses.  Solver launches cover (windows x columns) vectors, which is the
  * count to tune for.
  *   path:     if not NULL, the whole table is written there as JSON
- *             ({"stencil": [{nx, ny, nz, cols, elem, radius, tx, yb, zchunk, xcd, nt, us}, ...]};
+ *             ({"stencil": [{nx, ny, nz, cols, elem, radius, tx, yb, zchunk, xcd, nt, cb, us}, ...]};
  *             elem is the complex element size, 16 or 8 bytes; an entry
- *             without "xcd" reads as launch order, without "nt" as 512);
- *   geometry: host, 6 outputs or NULL: tx, yb, zchunk, xcd (0 or 1), nt,
- *             candidates timed;
+ *             without "xcd" reads as launch order, without "nt" as 512,
+ *             without "cb" as one column per thread);
+ *   geometry: host, 7 outputs or NULL: tx, yb, zchunk, xcd (0 or 1), nt,
+ *             cb, candidates timed;
  *   best_us:  host, or NULL: the best time per launch in microseconds.
  * Allocates two N x ncols blocks while it runs and synchronises ctx's stream.
  * Errors: TSG_EINVAL (ncols, reps < 1, dtype, unwritable path), TSG_ENOMEM,
@@ -338,7 +339,7 @@ tsg_status tsg_tune_stencil(tsg_ctx* ctx, int32_t ncols, int32_t dtype, int32_t 
  * grid with the given radius (1..6): the tuned entry when the process-wide
  * table holds one for exactly this key, else the built-in rule.  Host only:
  * needs no device and launches nothing.
- *   geometry: host, 6 outputs: tx, yb, zchunk, xcd, nt, 1 if tuned else 0.
+ *   geometry: host, 7 outputs: tx, yb, zchunk, xcd, nt, cb, 1 if tuned else 0.
  * Errors: TSG_EINVAL (NULL geometry, sizes out of range, dtype). */
 tsg_status tsg_stencil_geometry(int32_t nx, int32_t ny, int32_t nz, int32_t radius, int32_t ncols, int32_t dtype,
                                 int32_t* geometry);

@@ -322,13 +322,13 @@ class Operator:
     def tune_stencil(self, ncols: int, dtype: int = C128, reps: int = 10, path: Optional[str] = None):
         """tsg_tune_stencil: times every candidate stencil geometry for a
         launch of ncols vectors on this grid and keeps the fastest.  Returns
-        ({tx, yb, zchunk, xcd, nt, tried}, best microseconds per launch)."""
-        g = (C.c_int32 * 6)()
+        ({tx, yb, zchunk, xcd, nt, cb, tried}, best microseconds per launch)."""
+        g = (C.c_int32 * 7)()
         us = C.c_double()
         s = self.lib.tsg_tune_stencil(self.ctx, int(ncols), int(dtype), int(reps),
                                       path.encode() if path else None, g, C.byref(us))
         _check(self.lib, self.ctx, s)
-        return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "tried": g[5]}, us.value
+        return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "cb": g[5], "tried": g[6]}, us.value
 
     def transmission(self, energies: Sequence[float]) -> np.ndarray:
         E = np.ascontiguousarray(energies, dtype=np.float64)
@@ -423,6 +423,6 @@ def stencil_geometry(nx: int, ny: int, nz: int, ncols: int, dtype: int = C128, r
     """tsg_stencil_geometry: the launch geometry the library uses for ncols
     vectors of this grid (the tuned entry if the table holds one)."""
     lib = load()
-    g = (C.c_int32 * 6)()
+    g = (C.c_int32 * 7)()
     _check(lib, None, lib.tsg_stencil_geometry(int(nx), int(ny), int(nz), int(radius), int(ncols), int(dtype), g))
-    return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "tuned": bool(g[5])}
+    return {"tx": g[0], "yb": g[1], "zchunk": g[2], "xcd": g[3], "nt": g[4], "cb": g[5], "tuned": bool(g[6])}

@@ -338,7 +338,7 @@ tsg_status tsg_tune_stencil(tsg_ctx* ctx, int32_t ncols, int32_t dtype, int32_t 
     int tried = 0;
     const tsg::StencilTuneEntry e = tsg::tune_stencil(ctx, ncols, dtype, reps, &tried);
     if (path) tsg::write_tuning(path);
-    if (geometry) { geometry[0] = e.g.tx; geometry[1] = e.g.yb; geometry[2] = e.g.zchunk; geometry[3] = e.g.xcd; geometry[4] = e.g.nt; geometry[5] = tried; }
+    if (geometry) { geometry[0] = e.g.tx; geometry[1] = e.g.yb; geometry[2] = e.g.zchunk; geometry[3] = e.g.xcd; geometry[4] = e.g.nt; geometry[5] = e.g.cb; geometry[6] = tried; }
     if (best_us) *best_us = e.us;
     return TSG_OK;
   });
@@ -367,7 +367,8 @@ tsg_status tsg_stencil_geometry(int32_t nx, int32_t ny, int32_t nz, int32_t radi
     geometry[2] = std::max(1, std::min(g.zchunk, int(nz)));
     geometry[3] = g.xcd;
     geometry[4] = g.nt;
-    geometry[5] = tuned ? 1 : 0;
+    geometry[5] = g.cb;
+    geometry[6] = tuned ? 1 : 0;
     return TSG_OK;
   });
 }

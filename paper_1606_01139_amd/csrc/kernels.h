@@ -40,6 +40,7 @@ template <typename T> struct StencilArgs {
   const int* wmap;                         // launch slot -> window index (< 0: idle), or null
   int tx, ty, zchunk, tiles;               // launch geometry (tiles = largest tile count)
   int nt;                                  // threads per workgroup (256 or 512)
+  int cb;                                  // columns per thread (1, or 2 for complex64)
   int yb;                                  // points per thread stacked in y (1 or 2)
   int xcd;                                 // 1: XCD-aware block order (one-dimensional, padded grid)
   int nzc;                                 // z chunks of the largest system (set at launch)
@@ -53,13 +54,14 @@ template <typename T> void stencil_geometry(StencilArgs<T>& a, int nx, int ny, i
 
 // A stencil launch geometry: tile width tx (nt / tx thread rows, nt = 256 or
 // 512 threads per workgroup), yb points per thread in y, zchunk planes per
-// workgroup, xcd = 1 for the XCD-grouped block order.
+// workgroup, xcd = 1 for the XCD-grouped block order, cb columns per thread.
 struct StencilGeom {
-  int tx = 64, yb = 1, zchunk = 32, xcd = 0, nt = 512;
+  int tx = 64, yb = 1, zchunk = 32, xcd = 0, nt = 512, cb = 1;
 };
-// Whether the kernel supports g at this radius (tile, block size and a halo
-// that fits the per-thread slots).
-bool stencil_geometry_valid(const StencilGeom& g, int radius);
+// Whether the kernel supports g at this radius and complex element size
+// (tile, block size, columns per thread and a halo that fits the per-thread
+// slots).
+bool stencil_geometry_valid(const StencilGeom& g, int radius, int elem);
 StencilGeom stencil_default_geometry(int nx, int ny, int nz, int64_t launch_cols, int radius);
 // The geometry a launch uses: the tuned entry for (shape, launch columns,
 // complex element size in bytes, radius) if the table has one (*tuned set

@@ -51,7 +51,10 @@ __device__ inline void ld_or_zero(const cplx<T>* p, bool ok, T& re, T& im) {
 // YB points per thread, stacked in y (ty = NT / tx thread rows, tile height
 // ty * YB): the y taps of a thread's points share one LDS column, and the
 // halo per output point shrinks as the tile grows taller.
-template <typename T, int R, int YB, int NT>
+// CB columns per thread (1 or 2): the columns of a workgroup share its
+// barriers, halo offsets, potential and tap weights; each has its own z
+// queue and LDS plane.
+template <typename T, int R, int YB, int NT, int CB>
 __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
     bz = int(blockIdx.y);
     bsc = int(blockIdx.z);
   }
-  const int slot = bsc / a.ncols, col = bsc % a.ncols;
+  const int ncg = (a.ncols + CB - 1) / CB;  // column groups per window
+  const int slot = bsc / ncg, cg = bsc % ncg;
   const int w = a.wmap ? a.wmap[slot] : slot;
   if (w < 0) return;  // idle slot (whole workgroup)
   const SysDesc& S = a.sys[a.wsys ? a.wsys[w] : 0];
@@ -99,8 +103,18 @@ __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
     xy[i] = inside[i] ? int64_t(y0 + i) * nx + x : 0;
   }
 
-  const cplx<T>* __restrict__ X = a.X + int64_t(w) * a.wsx + int64_t(col) * a.ldx;
-  cplx<T>* __restrict__ Y = a.Y + int64_t(w) * a.wsy + int64_t(col) * a.ldy;
+  // this thread's columns; a missing last column of an odd count reads and
+  // writes nothing (its pointers alias the group's first column)
+  const cplx<T>* __restrict__ Xc[CB];
+  cplx<T>* __restrict__ Yc[CB];
+  bool cv[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    cv[c] = cg * CB + c < a.ncols;
+    const int col = cv[c] ? cg * CB + c : cg * CB;
+    Xc[c] = a.X + int64_t(w) * a.wsx + int64_t(col) * a.ldx;
+    Yc[c] = a.Y + int64_t(w) * a.wsy + int64_t(col) * a.ldy;
+  }
   const T* __restrict__ V;
   const T* __restrict__ G;
   if constexpr (sizeof(T) == 8) { V = reinterpret_cast<const T*>(S.Vd); G = reinterpret_cast<const T*>(S.Gd); }
@@ -154,20 +168,25 @@ __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
 
   constexpr int PD = kPrefetch;
   constexpr int Q = PD * ((2 * R + PD + PD - 1) / PD);
-  T qr[YB][Q], qi[YB][Q];
+  T qr[CB][YB][Q], qi[CB][YB][Q];
 #pragma unroll
-  for (int i = 0; i < YB; ++i)
+  for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int j = 0; j < 2 * R + PD; ++j) {
-      const int zz = z0 - R + j;
-      ld_or_zero(X + zz * plane + xy[i], inside[i] && zz >= 0 && zz < nz, qr[i][j], qi[i][j]);
-    }
-  T hr[PD][kHaloSlots], hi[PD][kHaloSlots], vp[PD][YB];
+    for (int i = 0; i < YB; ++i)
+#pragma unroll
+      for (int j = 0; j < 2 * R + PD; ++j) {
+        const int zz = z0 - R + j;
+        ld_or_zero(Xc[c] + zz * plane + xy[i], cv[c] && inside[i] && zz >= 0 && zz < nz, qr[c][i][j], qi[c][i][j]);
+      }
+  T hr[CB][PD][kHaloSlots], hi[CB][PD][kHaloSlots], vp[PD][YB];
 #pragma unroll
   for (int r = 0; r < PD; ++r) {
     const int zz = z0 + r;
 #pragma unroll
-    for (int k = 0; k < kHaloSlots; ++k) ld_or_zero(X + zz * plane + hg[k], zz < z1 && hok[k], hr[r][k], hi[r][k]);
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int k = 0; k < kHaloSlots; ++k)
+        ld_or_zero(Xc[c] + zz * plane + hg[k], cv[c] && zz < z1 && hok[k], hr[c][r][k], hi[c][r][k]);
 #pragma unroll
     for (int i = 0; i < YB; ++i) vp[r][i] = (zz < z1 && inside[i]) ? V[zz * plane + xy[i]] : T(0);
   }
@@ -178,15 +197,20 @@ __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
       const int z = zb + s;
       if (z >= z1) break;  // uniform over the workgroup
       const int rs = s % PD;
-      cplx<T>* L = smem + ((z - z0) & 1) * (LW * LH);
-      if (active) {
+      // column c's plane buffers: CB planes, each double-buffered
+      cplx<T>* Lb = smem + ((z - z0) & 1) * (CB * LW * LH);
 #pragma unroll
-        for (int i = 0; i < YB; ++i)
-          L[(ly * YB + i + R) * LW + lx + R] = cplx<T>{qr[i][(s + R) % Q], qi[i][(s + R) % Q]};
+      for (int c = 0; c < CB; ++c) {
+        cplx<T>* L = Lb + c * (LW * LH);
+        if (active) {
+#pragma unroll
+          for (int i = 0; i < YB; ++i)
+            L[(ly * YB + i + R) * LW + lx + R] = cplx<T>{qr[c][i][(s + R) % Q], qi[c][i][(s + R) % Q]};
+        }
+#pragma unroll
+        for (int k = 0; k < kHaloSlots; ++k)
+          if (hl[k] >= 0) L[hl[k]] = cplx<T>{hr[c][rs][k], hi[c][rs][k]};
       }
-#pragma unroll
-      for (int k = 0; k < kHaloSlots; ++k)
-        if (hl[k] >= 0) L[hl[k]] = cplx<T>{hr[rs][k], hi[rs][k]};
       T vz[YB];
 #pragma unroll
       for (int i = 0; i < YB; ++i) vz[i] = vp[rs][i];
@@ -195,49 +219,61 @@ __global__ __launch_bounds__(NT) void stencil_kernel(StencilArgs<T> a) {
       const int zf = z + PD;
       const bool more = zf < z1;
 #pragma unroll
-      for (int k = 0; k < kHaloSlots; ++k) ld_or_zero(X + zf * plane + hg[k], more && hok[k], hr[rs][k], hi[rs][k]);
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int k = 0; k < kHaloSlots; ++k)
+          ld_or_zero(Xc[c] + zf * plane + hg[k], cv[c] && more && hok[k], hr[c][rs][k], hi[c][rs][k]);
 #pragma unroll
       for (int i = 0; i < YB; ++i) vp[rs][i] = (more && inside[i]) ? V[zf * plane + xy[i]] : T(0);
       const int zn = z + R + PD;
-      T nr[YB], ni[YB];
+      T nr[CB][YB], ni[CB][YB];
 #pragma unroll
-      for (int i = 0; i < YB; ++i) ld_or_zero(X + zn * plane + xy[i], inside[i] && zn < nz, nr[i], ni[i]);
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int i = 0; i < YB; ++i)
+          ld_or_zero(Xc[c] + zn * plane + xy[i], cv[c] && inside[i] && zn < nz, nr[c][i], ni[c][i]);
       __syncthreads();
       if (active) {
         const T g = G[z];
-        // x taps per point; y taps from one LDS column shared by the YB points
-        T ar[YB], ai[YB];
 #pragma unroll
-        for (int i = 0; i < YB; ++i) {
-          const T d = diag0 + vz[i];
-          ar[i] = d * qr[i][(s + R) % Q] + g * qi[i][(s + R) % Q];
-          ai[i] = d * qi[i][(s + R) % Q] - g * qr[i][(s + R) % Q];
-        }
-        const cplx<T>* Lc = L + (ly * YB + R) * LW + lx + R;  // point 0
-        cplx<T> col[YB + 2 * R];
+        for (int c = 0; c < CB; ++c) {
+          const cplx<T>* L = Lb + c * (LW * LH);
+          // x taps per point; y taps from one LDS column shared by the YB points
+          T ar[YB], ai[YB];
 #pragma unroll
-        for (int j = 0; j < YB + 2 * R; ++j) col[j] = Lc[(j - R) * LW];
-#pragma unroll
-        for (int i = 0; i < YB; ++i) {
-          const cplx<T>* Li = Lc + i * LW;
-#pragma unroll
-          for (int m = 1; m <= R; ++m) {
-            const cplx<T> xa = Li[-m], xb = Li[m], c = col[R + i - m], e = col[R + i + m];
-            const int lo = (s + R - m) % Q, hi2 = (s + R + m) % Q;
-            const T sr = (qr[i][lo] + qr[i][hi2]) + ((xa.re + xb.re) + (c.re + e.re));
-            const T si = (qi[i][lo] + qi[i][hi2]) + ((xa.im + xb.im) + (c.im + e.im));
-            ar[i] = fma(cf[m], sr, ar[i]);
-            ai[i] = fma(cf[m], si, ai[i]);
+          for (int i = 0; i < YB; ++i) {
+            const T d = diag0 + vz[i];
+            ar[i] = d * qr[c][i][(s + R) % Q] + g * qi[c][i][(s + R) % Q];
+            ai[i] = d * qi[c][i][(s + R) % Q] - g * qr[c][i][(s + R) % Q];
           }
-          if (inside[i]) Y[z * plane + xy[i]] = cplx<T>{ar[i], ai[i]};
+          const cplx<T>* Lc = L + (ly * YB + R) * LW + lx + R;  // point 0
+          cplx<T> colv[YB + 2 * R];
+#pragma unroll
+          for (int j = 0; j < YB + 2 * R; ++j) colv[j] = Lc[(j - R) * LW];
+#pragma unroll
+          for (int i = 0; i < YB; ++i) {
+            const cplx<T>* Li = Lc + i * LW;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+              const cplx<T> xa = Li[-m], xb = Li[m], u = colv[R + i - m], e = colv[R + i + m];
+              const int lo = (s + R - m) % Q, hi2 = (s + R + m) % Q;
+              const T sr = (qr[c][i][lo] + qr[c][i][hi2]) + ((xa.re + xb.re) + (u.re + e.re));
+              const T si = (qi[c][i][lo] + qi[c][i][hi2]) + ((xa.im + xb.im) + (u.im + e.im));
+              ar[i] = fma(cf[m], sr, ar[i]);
+              ai[i] = fma(cf[m], si, ai[i]);
+            }
+            if (cv[c] && inside[i]) Yc[c][z * plane + xy[i]] = cplx<T>{ar[i], ai[i]};
+          }
         }
       }
       // plane z + R + PD enters the queue in the slot after the newest
 #pragma unroll
-      for (int i = 0; i < YB; ++i) {
-        qr[i][(s + 2 * R + PD) % Q] = nr[i];
-        qi[i][(s + 2 * R + PD) % Q] = ni[i];
-      }
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int i = 0; i < YB; ++i) {
+          qr[c][i][(s + 2 * R + PD) % Q] = nr[c][i];
+          qi[c][i][(s + 2 * R + PD) % Q] = ni[c][i];
+        }
     }
   }
 }
@@ -268,8 +304,10 @@ void stencil_geometry(StencilArgs<T>& a, int nx, int ny, int nz, int nwin) {
   stencil_apply_geometry(a, nx, ny, nz, gm);
 }
 
-bool stencil_geometry_valid(const StencilGeom& g, int radius) {
+bool stencil_geometry_valid(const StencilGeom& g, int radius, int elem) {
   if (g.nt != 256 && g.nt != 512) return false;
+  // two columns per thread only for complex64 (complex128 would spill)
+  if (g.cb != 1 && !(g.cb == 2 && elem == 8)) return false;
   if (g.tx < 1 || g.nt % g.tx != 0 || (g.yb != 1 && g.yb != 2) || g.zchunk < 1 || (g.xcd != 0 && g.xcd != 1))
     return false;
   if (radius < 1 || radius > 6) return false;
@@ -301,6 +339,7 @@ template <typename T>
 void stencil_apply_geometry(StencilArgs<T>& a, int nx, int ny, int nz, const StencilGeom& gm) {
   a.tx = gm.tx;
   a.nt = gm.nt;
+  a.cb = gm.cb;
   a.ty = gm.tx > 0 ? gm.nt / gm.tx : 0;
   a.yb = gm.yb;
   a.xcd = gm.xcd;
@@ -309,13 +348,13 @@ void stencil_apply_geometry(StencilArgs<T>& a, int nx, int ny, int nz, const Ste
   a.tiles = ((nx + a.tx - 1) / a.tx) * ((ny + TY - 1) / TY);
 }
 
-template <typename T, int R, int YB, int NT>
+template <typename T, int R, int YB, int NT, int CB>
 void launch_r(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
-  const size_t lds = size_t(2) * (a.tx + 2 * R) * (a.ty * YB + 2 * R) * sizeof(cplx<T>);
+  const size_t lds = size_t(2) * CB * (a.tx + 2 * R) * (a.ty * YB + 2 * R) * sizeof(cplx<T>);
   if (lds > size_t(64) * 1024) {
     static std::atomic<size_t> granted{0};
     if (lds > granted.load()) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T, R, YB, NT>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T, R, YB, NT, CB>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) throw DeviceError(std::string("stencil: LDS attribute: ") + hipGetErrorString(e));
       size_t cur = granted.load();
@@ -323,28 +362,38 @@ void launch_r(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
       }
     }
   }
-  hipLaunchKernelGGL((stencil_kernel<T, R, YB, NT>), grid, dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((stencil_kernel<T, R, YB, NT, CB>), grid, dim3(NT), lds, s, a);
+}
+
+template <typename T, int R, int NT, int CB>
+void launch_y(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
+  if (a.yb == 2) launch_r<T, R, 2, NT, CB>(a, grid, s);
+  else launch_r<T, R, 1, NT, CB>(a, grid, s);
 }
 
 template <typename T, int R>
 void launch_yb(const StencilArgs<T>& a, dim3 grid, hipStream_t s) {
-  if (a.nt == 256) {
-    if (a.yb == 2) launch_r<T, R, 2, 256>(a, grid, s);
-    else launch_r<T, R, 1, 256>(a, grid, s);
-  } else {
-    if (a.yb == 2) launch_r<T, R, 2, 512>(a, grid, s);
-    else launch_r<T, R, 1, 512>(a, grid, s);
+  if constexpr (sizeof(T) == 4) {
+    if (a.cb == 2) {
+      if (a.nt == 256) launch_y<T, R, 256, 2>(a, grid, s);
+      else launch_y<T, R, 512, 2>(a, grid, s);
+      return;
+    }
   }
+  if (a.nt == 256) launch_y<T, R, 256, 1>(a, grid, s);
+  else launch_y<T, R, 512, 1>(a, grid, s);
 }
 
 template <typename T>
 void launch_stencil(StencilArgs<T> a, int nwin, int max_nz, hipStream_t s) {
   if (nwin <= 0 || a.ncols <= 0) return;
-  if (!stencil_geometry_valid(StencilGeom{a.tx, a.yb, a.zchunk, a.xcd, a.nt}, a.radius))
+  if (!stencil_geometry_valid(StencilGeom{a.tx, a.yb, a.zchunk, a.xcd, a.nt, a.cb}, a.radius,
+                              int(sizeof(cplx<T>))))
     throw DeviceError("stencil: invalid launch geometry");
   a.nzc = (max_nz + a.zchunk - 1) / a.zchunk;
-  a.nblocks = int64_t(a.tiles) * a.nzc * nwin * a.ncols;
-  dim3 grid(unsigned(a.tiles), unsigned(a.nzc), unsigned(nwin * a.ncols));
+  const int ncg = (a.ncols + a.cb - 1) / a.cb;
+  a.nblocks = int64_t(a.tiles) * a.nzc * nwin * ncg;
+  dim3 grid(unsigned(a.tiles), unsigned(a.nzc), unsigned(nwin * ncg));
   if (a.xcd) {
     const int64_t padded = ((a.nblocks + 7) / 8) * 8;
     // the dispatch counts work-items in 32 bits

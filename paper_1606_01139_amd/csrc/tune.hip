@@ -23,8 +23,8 @@ std::string entry_json(const StencilTuneEntry& x) {
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "{\"nx\": %d, \"ny\": %d, \"nz\": %d, \"cols\": %d, \"elem\": %d, \"radius\": %d, \"tx\": %d, "
-                "\"yb\": %d, \"zchunk\": %d, \"xcd\": %d, \"nt\": %d, \"us\": %.3f}",
-                x.nx, x.ny, x.nz, x.cols, x.elem, x.radius, x.g.tx, x.g.yb, x.g.zchunk, x.g.xcd, x.g.nt, x.us);
+                "\"yb\": %d, \"zchunk\": %d, \"xcd\": %d, \"nt\": %d, \"cb\": %d, \"us\": %.3f}",
+                x.nx, x.ny, x.nz, x.cols, x.elem, x.radius, x.g.tx, x.g.yb, x.g.zchunk, x.g.xcd, x.g.nt, x.g.cb, x.us);
   return buf;
 }
 
@@ -73,12 +73,13 @@ int load_tuning(const std::string& path) {
     bool ok = true;
     for (int i = 0; i < 10; ++i) ok = ok && field(obj, keys[i], v[i]);
     if (!ok) throw InvalidArg("malformed tuning entry: " + obj);
-    double xcd = 0.0, nt = 512.0;  // optional keys: launch order, 512 threads
+    double xcd = 0.0, nt = 512.0, cb = 1.0;  // optional keys: launch order, 512 threads, one column
     (void)field(obj, "xcd", xcd);
     (void)field(obj, "nt", nt);
+    (void)field(obj, "cb", cb);
     StencilTuneEntry x{int(v[0]), int(v[1]), int(v[2]), int(v[3]), int(v[4]), int(v[5]),
-                       StencilGeom{int(v[6]), int(v[7]), int(v[8]), int(xcd), int(nt)}, v[9]};
-    if (x.cols < 1 || (x.elem != 8 && x.elem != 16) || !stencil_geometry_valid(x.g, x.radius))
+                       StencilGeom{int(v[6]), int(v[7]), int(v[8]), int(xcd), int(nt), int(cb)}, v[9]};
+    if (x.cols < 1 || (x.elem != 8 && x.elem != 16) || !stencil_geometry_valid(x.g, x.radius, x.elem))
       throw InvalidArg("invalid tuning entry: " + obj);
     got.push_back(x);
     p = b + 1;
@@ -131,10 +132,11 @@ StencilTuneEntry tune_t(tsg_ctx* c, int ncols, int reps, int* n_tried) {
       for (int yb : {1, 2})
         for (int zc : {16, 24, 32, 48, 64, 96, 128, 192}) {
           if (zc > c->nz && zc != 16) continue;
-          for (int xcd : {0, 1}) {
-            const StencilGeom g{tx, yb, std::min(zc, c->nz), xcd, nt};
-            if (stencil_geometry_valid(g, c->R)) cand.push_back(g);
-          }
+          for (int xcd : {0, 1})
+            for (int cb : {1, 2}) {
+              const StencilGeom g{tx, yb, std::min(zc, c->nz), xcd, nt, cb};
+              if (stencil_geometry_valid(g, c->R, int(sizeof(cplx<T>)))) cand.push_back(g);
+            }
         }
     }
   StencilTuneEntry best{c->nx, c->ny, c->nz, ncols, int(sizeof(cplx<T>)), c->R, def, 1e300};

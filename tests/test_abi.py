@@ -94,13 +94,15 @@ def test_tuning_file_round_trip_and_rejections(pkg, tmp_path):
     good = tmp_path / "t.json"
     good.write_text('{"stencil": [\n {"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 16, "radius": 6, "tx": 32, '
                     '"yb": 2, "zchunk": 16, "us": 1.5},\n {"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 8, '
-                    '"radius": 6, "tx": 16, "yb": 1, "zchunk": 9, "xcd": 1, "nt": 256, "us": 1.0}]}\n')
+                    '"radius": 6, "tx": 16, "yb": 1, "zchunk": 9, "xcd": 1, "nt": 256, "cb": 2, "us": 1.0}]}\n')
     assert load_tuning(str(good)) == 2
     # launches find their entry by complex element size: 16 bytes for
     # complex128, 8 for complex64; other keys fall back to the built-in rule
     from paper_1606_01139_amd.binding import stencil_geometry, C128, C64
-    assert stencil_geometry(7, 5, 9, 3, C128) == {"tx": 32, "yb": 2, "zchunk": 9, "xcd": 0, "nt": 512, "tuned": True}
-    assert stencil_geometry(7, 5, 9, 3, C64) == {"tx": 16, "yb": 1, "zchunk": 9, "xcd": 1, "nt": 256, "tuned": True}
+    assert stencil_geometry(7, 5, 9, 3, C128) == {"tx": 32, "yb": 2, "zchunk": 9, "xcd": 0, "nt": 512, "cb": 1,
+                                                  "tuned": True}
+    assert stencil_geometry(7, 5, 9, 3, C64) == {"tx": 16, "yb": 1, "zchunk": 9, "xcd": 1, "nt": 256, "cb": 2,
+                                                 "tuned": True}
     assert not stencil_geometry(7, 5, 9, 4, C128)["tuned"]
     assert not stencil_geometry(7, 5, 9, 3, C128, radius=4)["tuned"]
     with pytest.raises(TsgError):
@@ -111,9 +113,10 @@ def test_tuning_file_round_trip_and_rejections(pkg, tmp_path):
     with pytest.raises(TsgError) as e:
         load_tuning(str(bad))
     assert e.value.status == TSG_EINVAL
-    # an unknown order flag, an unsupported block size, and a 64-wide tile on
-    # 256 threads (its radius-6 halo exceeds three cells per thread)
-    for extra in ('"xcd": 2', '"nt": 384', '"tx": 64, "nt": 256'):
+    # an unknown order flag, an unsupported block size, a 64-wide tile on
+    # 256 threads (its radius-6 halo exceeds three cells per thread), and two
+    # columns per thread for complex128 (only complex64 has that kernel)
+    for extra in ('"xcd": 2', '"nt": 384', '"tx": 64, "nt": 256', '"cb": 2', '"cb": 3'):
         f = tmp_path / "x.json"
         body = '"nx": 7, "ny": 5, "nz": 9, "cols": 3, "elem": 16, "radius": 6, "yb": 1, "zchunk": 16, "us": 1.0'
         if '"tx"' not in extra:

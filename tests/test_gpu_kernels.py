@@ -106,7 +106,7 @@ def test_stencil_tuned_geometries_match_oracle(torch_cuda, tmp_path, tx, yb, zc,
     assert load_tuning(str(f)) == 1
     from paper_1606_01139_amd.binding import stencil_geometry, C128, C64
     used = stencil_geometry(nx, ny, nz, B, C128 if dtype == "c128" else C64)
-    assert used == {"tx": tx, "yb": yb, "zchunk": min(zc, nz), "xcd": xcd, "nt": nt, "tuned": True}, used
+    assert used == {"tx": tx, "yb": yb, "zchunk": min(zc, nz), "xcd": xcd, "nt": nt, "cb": 1, "tuned": True}, used
     V, ab, gL, gR = _fields(nx, ny, nz, 8)
     N = nx * ny * nz
     rng = np.random.default_rng(9)
@@ -122,6 +122,38 @@ def test_stencil_tuned_geometries_match_oracle(torch_cuda, tmp_path, tx, yb, zc,
     Y = Yd.cpu().numpy().T.astype(np.complex128)
     tol = 1e-13 if dtype == "c128" else 1e-6
     assert np.abs(Y - ref).max() <= tol * np.abs(ref).max()
+    oper.close()
+
+
+# two columns per thread (complex64): odd and even column counts (the last
+# group of an odd count has one column), both block sizes and orders
+@pytest.mark.parametrize("tx,yb,zc,xcd,nt,B", [(32, 1, 16, 0, 512, 3), (64, 2, 7, 1, 512, 4), (16, 2, 24, 1, 256, 5),
+                                              (32, 2, 48, 0, 256, 1)])
+def test_stencil_two_columns_per_thread_match_oracle(torch_cuda, tmp_path, tx, yb, zc, xcd, nt, B):
+    torch = torch_cuda
+    from oracle import operator as op
+    from paper_1606_01139_amd import Operator
+    from paper_1606_01139_amd.binding import load_tuning, stencil_geometry, C64
+    nx, ny, nz = 37, 29, 21
+    print(f"stencil two columns per thread tx={tx} yb={yb} zchunk={zc} xcd={xcd} nt={nt} B={B}", flush=True)
+    f = tmp_path / "tune.json"
+    f.write_text('{"stencil": [{"nx": %d, "ny": %d, "nz": %d, "cols": %d, "elem": 8, "radius": 6, "tx": %d, '
+                 '"yb": %d, "zchunk": %d, "xcd": %d, "nt": %d, "cb": 2, "us": 0}]}' % (nx, ny, nz, B, tx, yb, zc, xcd, nt))
+    assert load_tuning(str(f)) == 1
+    used = stencil_geometry(nx, ny, nz, B, C64)
+    assert used == {"tx": tx, "yb": yb, "zchunk": min(zc, nz), "xcd": xcd, "nt": nt, "cb": 2, "tuned": True}, used
+    V, ab, gL, gR = _fields(nx, ny, nz, 8)
+    N = nx * ny * nz
+    rng = np.random.default_rng(19)
+    X = (rng.standard_normal((N, B)) + 1j * rng.standard_normal((N, B))).astype(np.complex64)
+    ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X.astype(np.complex128), 6)
+    oper = Operator(nx, ny, nz, 0.5, V, ab)
+    Xd = _to_dev(torch, X, 0)
+    Yd = _to_dev(torch, np.zeros_like(X), 0)
+    oper.apply(Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().T.astype(np.complex128)
+    assert np.abs(Y - ref).max() <= 1e-6 * np.abs(ref).max()
     oper.close()
 
 
@@ -141,7 +173,7 @@ def test_stencil_autotuner_picks_a_candidate_and_keeps_parity(torch_cuda, tmp_pa
     assert load_tuning(str(out)) >= 1
     from paper_1606_01139_amd.binding import stencil_geometry
     used = stencil_geometry(nx, ny, nz, B, 0)
-    assert used["tuned"] and all(used[k] == geo[k] for k in ("tx", "yb", "zchunk", "xcd", "nt")), (used, geo)
+    assert used["tuned"] and all(used[k] == geo[k] for k in ("tx", "yb", "zchunk", "xcd", "nt", "cb")), (used, geo)
     N = nx * ny * nz
     X = np.random.default_rng(12).standard_normal((N, B)) + 0.5j
     ref = op.apply_operator(nx, ny, nz, 0.5, V, gL, gR, X, 6)
