@@ -436,6 +436,39 @@ def test_c2_full_size_vectors(c2_solved):
     assert np.abs(T - Tref).max() <= 1e-6
 
 
+def test_c5_first_window_matches_oracle_fixture(torch_cuda):
+    """The large grid (c5: 64 x 64 x 160, N = 655,360) on its first planned
+    window, in the c5 precision (complex64 bulk, FP64 finish), against the
+    oracle's stored window (tests/golden/c5_window0.json, written by
+    make_c5_window0.py from oracle/ only): E_min, the planned shift and
+    count, and the 64 eigenvalues element by element at 1e-10 relative.
+    The interior windows of this size do not converge within any practical
+    restart budget (DESIGN, c5 measurements), so this is the window the
+    oracle can pin."""
+    import json
+    import os
+    from paper_1606_01139_amd import FP32_BULK, Operator, PLAN_SEMICLASSICAL, default_opts
+    from synth.workloads import workload
+    print("c5 first window vs oracle fixture", flush=True)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c5_window0.json")) as f:
+        ref = json.load(f)
+    w = workload("c5")
+    g = w.grid
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, w.absorber.as_tuple())
+    opts = default_opts(precision=FP32_BULK, tol=1e-8)
+    wins, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    assert abs(erange[0] - ref["e_min"]) <= 1e-10 * abs(ref["e_min"])
+    assert wins[0][1] == ref["nev"] and abs(wins[0][0] - ref["shift"]) <= 1e-8, (wins[0], ref["shift"])
+    n = oper.solve_partition(ref["shift"], ref["nev"], opts)
+    assert n == ref["nev"]
+    eps, _ = oper.partition(0)
+    worst = _match_one_to_one(eps, np.array(ref["re"]) + 1j * np.array(ref["im"]), 1e-10)
+    st = oper.stats(0)
+    print(f"c5 window 0: {n} pairs, restarts {st.restarts_bulk} complex64 + {st.restarts} FP64, "
+          f"worst relative difference {worst:.2e}", flush=True)
+    oper.close()
+
+
 def test_restart_cap_reports_noconv_and_keeps_converged_subset(torch_cuda):
     """max_restarts = 1 stops every window after its first cycle: the solve
     returns TSG_ENOCONV and each partition keeps only its pairs at backward
