@@ -1,7 +1,8 @@
 """GPU parity of the transmission adjoint (tsg_transmission_vjp) against the
-oracle's exact gradient (full eigenbasis of a small system), and of the
-torch.autograd front end against central finite differences of the GPU
-pipeline itself."""
+oracle's exact gradient (full eigenbasis of a small system; the projected
+tier on a medium grid), of the torch.autograd front end against central
+finite differences of the GPU pipeline itself, and at the full c4 size
+against the oracle's windows and central differences."""
 import numpy as np
 import pytest
 
@@ -182,3 +183,67 @@ def test_vjp_matches_projected_oracle_on_a_medium_grid(torch_cuda):
     assert err <= 1e-6
     np.testing.assert_allclose(dab, gr["abs"], rtol=1e-6, atol=1e-6 * np.abs(gr["abs"]).max())
     oper.close()
+
+
+def test_c4_first_windows_and_gradient_against_oracle_and_differences(torch_cuda):
+    """The differentiation grid (c4: 48 x 48 x 96, N = 221,184) on its first
+    two planned windows, FP64 to backward error 1e-12: E_min, the shifts and
+    counts, and the combined set against the oracle's stored windows
+    (tests/golden/c4_windows.json, from oracle/ only) at 1e-10; then the
+    gradient of sum_e w_e T(E_e) from tsg_transmission_vjp against central
+    differences (step 1e-5) of the GPU pipeline itself: along one random
+    direction in V(r), the check that stands in for every grid point, and
+    for the left absorber amplitude, each to 1e-5 relative."""
+    import json
+    import os
+    import time
+    from paper_1606_01139_amd import Operator, PLAN_SEMICLASSICAL, default_opts
+    from synth.workloads import workload
+    print("c4 first windows and gradient", flush=True)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c4_windows.json")) as f:
+        ref = json.load(f)
+    w = workload("c4")
+    g = w.grid
+    ab = np.array(w.absorber.as_tuple())
+    opts = default_opts(tol=1e-12)
+    oper = Operator(g.nx, g.ny, g.nz, g.h, w.V, ab)
+    plan, erange = oper.plan_windows(w.n_windows * w.nev_per_window, w.n_windows, PLAN_SEMICLASSICAL, opts)
+    assert abs(erange[0] - ref["e_min"]) <= 1e-10 * abs(ref["e_min"])
+    wins = [(x["shift"], x["nev"]) for x in ref["windows"]]
+    for (s, k), (s2, k2) in zip(plan[:len(wins)], wins):
+        assert k == k2 and abs(s - s2) <= 1e-8, (s, s2)
+    t0 = time.perf_counter()
+    n, holes, status = oper.solve_all_partitions(wins, opts)
+    print(f"c4 first windows: {n} pairs in {time.perf_counter() - t0:.1f} s", flush=True)
+    eps = oper.eigenvalues()
+    comb = np.array(ref["combined"]["re"]) + 1j * np.array(ref["combined"]["im"])
+    assert len(eps) == len(comb)
+    d = np.abs(eps - comb) / np.maximum(np.abs(comb), 1.0)
+    print(f"combined set: worst relative difference {d.max():.2e}", flush=True)
+    assert d.max() <= 1e-10
+    E = np.linspace(eps.real.min() - 0.02, eps.real.max() + 0.02, 6)
+    wts = np.random.default_rng(4).uniform(0.5, 1.5, len(E))
+    t0 = time.perf_counter()
+    dV, dab = oper.transmission_vjp(E, wts)
+    print(f"vjp in {time.perf_counter() - t0:.1f} s", flush=True)
+    oper.close()
+
+    def loss(V, a):
+        o = Operator(g.nx, g.ny, g.nz, g.h, V, a)
+        o.solve_all_partitions(wins, opts)
+        val = float(wts @ o.transmission(E))
+        o.close()
+        return val
+
+    step = 1e-5
+    dirn = np.random.default_rng(6).standard_normal(g.n)
+    dirn /= np.abs(dirn).max()
+    fd = (loss(w.V + step * dirn, ab) - loss(w.V - step * dirn, ab)) / (2 * step)
+    got = float(dV @ dirn)
+    print(f"directional derivative: vjp {got:.10e}, central difference {fd:.10e}", flush=True)
+    assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-6)
+    da = np.zeros(6)
+    da[0] = step
+    fd_a = (loss(w.V, ab + da) - loss(w.V, ab - da)) / (2 * step)
+    print(f"d/d amp_L: vjp {dab[0]:.10e}, central difference {fd_a:.10e}", flush=True)
+    assert abs(dab[0] - fd_a) <= 1e-5 * max(abs(fd_a), 1e-6)

@@ -73,3 +73,4 @@ def test_c5_first_middle_last_windows_against_oracle_operator():
             assert be <= 1e-8
             assert abs(u @ u - 1.0) <= 1e-10
     oper.close()
+
