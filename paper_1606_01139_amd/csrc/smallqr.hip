@@ -26,6 +26,11 @@
 // the log onto them, many workgroups per window over bands of columns.  Each
 // record carries the ihi of its step; column j takes the records whose ihi is
 // below j, a suffix of the log.
+// Within a sweep the same holds for most of the active block: no later step
+// of the sweep reads the rows above the bulge train, and none reads a column
+// well to the right of it before the train arrives.  Those updates go to
+// helper workgroups of the same launch on other CUs (see chase_helper), so
+// that the chase itself only touches the rows and columns around the train.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -70,13 +75,14 @@ struct RotRec {
   c128 s;
 };
 static_assert(sizeof(RotRec) == 32, "RotRec layout");
-constexpr int kQCap = 32 * kFin * kFin;  // Q store entries before the chase flushes the log
 
 // Per-window log, in c128 units: a 2-entry header (steps, Q blocks), the
 // step records, the Q store.  The capacity covers 80 multishift sweeps; a
 // chase that needs more flushes the log onto Z itself and starts over.
 __host__ __device__ inline int64_t log_steps_cap(int m) { return int64_t(80) * (m + 3 * kShifts); }
 __host__ __device__ inline int64_t log_qstore_offset(int m) { return 2 + log_steps_cap(m) * kShifts * 2; }
+constexpr int kQCap = 32 * kFin * kFin;  // Q store entries before the chase flushes the log
+__host__ __device__ inline int64_t log_sync_offset(int m) { return log_qstore_offset(m) + kQCap; }
 
 __device__ inline double cabs1(c128 z) { return fabs(z.re) + fabs(z.im); }
 
@@ -135,6 +141,8 @@ struct QRShared {
   // column p of rows p+1 and p+2 after bulge j's right rotation at p: the
   // two values its next rotation is built from
   c128 fx[kMaxShift], fy[kMaxShift];
+  int hflag;               // helper protocol: result of thread 0's wait
+  unsigned long long hp;   // helper protocol: the published word thread 0 read
 };
 
 // Single-shift QR on the n x n block B (LDS, row-major) until all its
@@ -407,24 +415,270 @@ __device__ __attribute__((noinline)) void flush_log_cols(c128* H, int m, const R
   }
 }
 
+// ---------------------------------------------------------------- helpers
+// Each helper owns a band of kHelpBand rows and the band of columns with the
+// same indices.  In a sweep that uses them (a deferred sweep):
+//   * row r is the helper's from step srow(r) on: all later right rotations
+//     of the sweep act on it only above the train;
+//   * column c is the helper's before step scol(c): until then the left
+//     rotations reach it only to the right of the train.  The chase owns the
+//     columns up to e(s) = lo + kTake (s / kTake + 2) at step s, so it takes
+//     them back kTake at a time, each block before the train gets near it.
+// The helper replays the logged rotations of each chunk of published steps
+// onto the parts of its rows and columns that chunk touches, staged in LDS
+// (lane j of a row or column applies record j of each step), and reports the
+// steps done.  The chase publishes every step's records, waits for the helpers
+// owning a block of columns before it takes it, and for all of them at the end
+// of the sweep.  A helper announces itself when it starts; a sweep is deferred
+// only if every helper of the window has, so the chase never waits on a
+// workgroup that is not running, and helpers wait only on the chase.  Every
+// wait gives up after kSpinTicks (the window then fails with info > 0).
+constexpr int kHelpBand = 32;     // rows and columns per helper
+constexpr int kMaxHelpers = 64;
+constexpr int kHelpChunk = 32;    // steps a helper replays per LDS pass
+constexpr int kTake = 32;         // columns the chase takes back at a time
+constexpr int kHelpSpan = 3 * (kShifts - 1) + kHelpChunk + 2;  // rows (columns) one pass touches
+constexpr int kDeferMin = 128;    // smallest active block whose sweeps are deferred
+constexpr int kPub = 8;           // the chase publishes its records every kPub steps
+constexpr unsigned long long kSpinTicks = 1000000000ull;  // 10 s of the 100 MHz wall clock
+static_assert(2 * kHelpBand * kShifts == kQT, "helper lanes: one band of rows, one of columns");
+static_assert(kHelpChunk <= kTake, "a helper's row pass stays left of its deferred columns");
+static_assert(kTake % kPub == 0, "the step before each take is published");
+static_assert(size_t(kHelpChunk) * kShifts * sizeof(RotRec) + 2 * size_t(kHelpBand) * kHelpSpan * sizeof(c128) <=
+                  2 * size_t(kFin) * kFin * sizeof(c128),
+              "helper LDS");
+
+// Per-window state shared by the chase and its helpers (after the log).
+struct ChaseSync {
+  unsigned long long pub;                // (sweep << 32) | steps whose records are out
+  unsigned long long prog[kMaxHelpers];  // per helper: (sweep << 32) | steps replayed
+  int present;                           // helpers running
+  int state;                             // 0 chasing, 1 finished, 2 failed
+  int lo, ihi, ns, nsteps, s0, pad;      // the current deferred sweep (s0: log index of its step 0)
+};
+constexpr int64_t kSyncC128 = int64_t((sizeof(ChaseSync) + sizeof(c128) - 1) / sizeof(c128));
+
+__device__ inline unsigned long long ld_agent(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_agent(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_agent(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Shared data on the helpers' side goes through 64-bit device-coherent
+// accesses, so that a helper never has to invalidate its L2 (which is also
+// the chase's when both run on one XCD) to see what the chase wrote.
+__device__ inline c128 ld_shared(const c128* p) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  return c128{__longlong_as_double((long long)ld_agent(q)), __longlong_as_double((long long)ld_agent(q + 1))};
+}
+__device__ inline void st_shared(c128* p, c128 v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  st_agent(q, (unsigned long long)__double_as_longlong(v.re));
+  st_agent(q + 1, (unsigned long long)__double_as_longlong(v.im));
+}
+__device__ inline RotRec ld_shared(const RotRec* p) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  const unsigned long long a = ld_agent(q), b = ld_agent(q + 1), c = ld_agent(q + 2), d = ld_agent(q + 3);
+  RotRec R;
+  R.c = __longlong_as_double((long long)a);
+  R.p = int(b & 0xffffffffull);
+  R.pad = int(b >> 32);
+  R.s = c128{__longlong_as_double((long long)c), __longlong_as_double((long long)d)};
+  return R;
+}
+
+// Every thread's earlier stores have completed (reached the L2), then thread
+// 0 writes the L2 back (agent-scope release) and stores v to *p.  Called by
+// the whole workgroup.
+__device__ inline void publish(unsigned long long* p, unsigned long long v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads and stores are done
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_agent(p, v);
+  }
+}
+
+// Thread 0: polls until done() holds (false after kSpinTicks); with acquire,
+// then an agent-scope acquire fence (the chase, before it reads what helpers
+// wrote), so that the workgroup sees it once it has passed a barrier.
+template <typename F>
+__device__ inline bool spin_wait(F done, bool acquire) {
+  const unsigned long long start = wall_clock64();
+  while (!done()) {
+    if (wall_clock64() - start > kSpinTicks) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// First step of a deferred sweep from which row r is the helper's.
+__device__ inline int helper_srow(int r, int lo, int ns) { return r < lo ? 0 : r - lo + 3 * (ns - 1) + 1; }
+// Step at which the chase takes column c back (0: the chase's all sweep).
+__device__ inline int helper_scol(int c, int lo, int ihi) {
+  return (c < lo || c > ihi) ? 0 : kTake * max(0, (c - lo + kTake - 1) / kTake - 2);
+}
+
+// One pass of helper h over steps [sa, sb) of the deferred sweep: the steps'
+// right rotations on its rows and left rotations on its columns, the parts
+// they touch ([base, top], by the bulge positions lo + s - 3 j) held in LDS.
+__device__ void helper_pass(c128* H, int m, const RotRec* rec, int s0, int lo, int ihi, int ns, int b0, int sa,
+                            int sb, c128* lds) {
+  const int t = threadIdx.x;
+  RotRec* rl = reinterpret_cast<RotRec*>(lds);
+  c128* rows = lds + int64_t(kHelpChunk) * kShifts * (sizeof(RotRec) / sizeof(c128));
+  c128* cols = rows + kHelpBand * kHelpSpan;
+  const int base = max(lo, lo + sa - 3 * (ns - 1));
+  const int top = min(ihi, lo + sb);
+  const int W = top - base + 1;
+  for (int e = t; e < (sb - sa) * kShifts; e += kQT) rl[e] = ld_shared(rec + int64_t(s0 + sa) * kShifts + e);
+  for (int e = t; e < 2 * kHelpBand * W; e += kQT) {
+    const int side = e / (kHelpBand * W), i = (e / W) % kHelpBand, q = e % W, x = b0 + i;
+    if (side == 0) {
+      if (x < m && helper_srow(x, lo, ns) < sb) rows[i * kHelpSpan + q] = ld_shared(H + int64_t(x) * m + base + q);
+    } else {
+      if (x < m && helper_scol(x, lo, ihi) > sa) cols[i * kHelpSpan + q] = ld_shared(H + int64_t(base + q) * m + x);
+    }
+  }
+  __syncthreads();
+  {
+    const int j = t % kShifts, side = t / (kHelpBand * kShifts), i = (t / kShifts) % kHelpBand, x = b0 + i;
+    c128* seg = (side == 0 ? rows : cols) + i * kHelpSpan;
+    int s_from = sb, s_to = sb;  // steps this lane's row or column takes
+    if (side == 0) {
+      if (x < m && helper_srow(x, lo, ns) < sb) s_from = max(sa, helper_srow(x, lo, ns));
+    } else if (x < m && helper_scol(x, lo, ihi) > sa) {
+      s_from = sa;
+      s_to = min(sb, helper_scol(x, lo, ihi));
+    }
+    for (int s = sa; s < sb; ++s) {
+      if (s >= s_from && s < s_to) {
+        const RotRec R = rl[(s - sa) * kShifts + j];
+        if (R.p >= 0) {
+          c128* a = seg + (R.p - base);
+          const c128 u = a[0], v = a[1];
+          if (side == 0) {  // right rotation, as the chase applies it to rows
+            a[0] = R.c * u + conj(R.s) * v;
+            a[1] = R.c * v - R.s * u;
+          } else {          // left rotation, as the chase applies it to columns
+            a[0] = R.c * u + R.s * v;
+            a[1] = R.c * v - conj(R.s) * u;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < 2 * kHelpBand * W; e += kQT) {
+    const int side = e / (kHelpBand * W), i = (e / W) % kHelpBand, q = e % W, x = b0 + i;
+    if (side == 0) {
+      if (x < m && helper_srow(x, lo, ns) < sb) st_shared(H + int64_t(x) * m + base + q, rows[i * kHelpSpan + q]);
+    } else {
+      if (x < m && helper_scol(x, lo, ihi) > sa) st_shared(H + int64_t(base + q) * m + x, cols[i * kHelpSpan + q]);
+    }
+  }
+  __syncthreads();
+}
+
+// Helper h of a window: announces itself, then serves every deferred sweep
+// the chase publishes until the chase has finished (or a wait gives up).
+__device__ void chase_helper(c128* H, int m, const RotRec* rec, ChaseSync* sy, int h, QRShared& S, c128* lds) {
+  const int t = threadIdx.x;
+  if (t == 0) __hip_atomic_fetch_add(&sy->present, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long seen = 0;  // last sweep served
+  for (;;) {
+    if (t == 0) {
+      unsigned long long p = 0;
+      int st = 0;
+      const bool ok = spin_wait([&] {
+        p = ld_agent(&sy->pub);
+        st = ld_agent(&sy->state);
+        return (p >> 32) > seen || st != 0;
+      }, false);
+      if (!ok) st_agent(&sy->state, 2);
+      S.hp = p;
+      S.hflag = (ok && (p >> 32) > seen) ? 0 : 1;
+    }
+    __syncthreads();
+    const int stop = S.hflag;
+    const unsigned long long p0 = S.hp;
+    __syncthreads();
+    if (stop) return;
+    seen = p0 >> 32;
+    const int lo = ld_agent(&sy->lo), ihi = ld_agent(&sy->ihi), ns = ld_agent(&sy->ns);
+    const int nsteps = ld_agent(&sy->nsteps), s0 = ld_agent(&sy->s0);
+    int done = 0, avail = int(p0 & 0xffffffffull);
+    while (done < nsteps) {
+      if (avail <= done) {
+        if (t == 0) {
+          unsigned long long p = 0;
+          int st = 0;
+          const bool ok = spin_wait([&] {
+            p = ld_agent(&sy->pub);
+            st = ld_agent(&sy->state);
+            return (p >> 32) != seen || int(p & 0xffffffffull) > done || st != 0;
+          }, false);
+          if (!ok) st_agent(&sy->state, 2);
+          S.hp = p;
+          S.hflag = (ok && (p >> 32) == seen && int(p & 0xffffffffull) > done) ? 0 : 1;
+        }
+        __syncthreads();
+        const int bad = S.hflag;
+        avail = int(S.hp & 0xffffffffull);
+        __syncthreads();
+        if (bad) return;
+      }
+      for (int sa = done; sa < avail; sa += kHelpChunk)
+        helper_pass(H, m, rec, s0, lo, ihi, ns, h * kHelpBand, sa, min(avail, sa + kHelpChunk), lds);
+      done = avail;
+      publish(&sy->prog[h], (seen << 32) | (unsigned long long)(unsigned)done);
+    }
+  }
+}
+
+// Clears each window's ChaseSync before the chase (a kernel, not a memset, so
+// that the sequence can be captured in a graph).
+__global__ void chase_sync_init_kernel(c128* logall, int64_t wsl, int m, const int* __restrict__ wmap) {
+  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  if (w < 0) return;
+  c128* z = logall + int64_t(w) * wsl + log_sync_offset(m);
+  for (int64_t e = threadIdx.x; e < kSyncC128; e += blockDim.x) z[e] = c128{0.0, 0.0};
+}
+
 __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int m, c128* Zall, int64_t wsz,
                                                     c128* logall, int64_t wsl, int64_t cap, c128* theta, int64_t wst,
                                                     int* info, const int* __restrict__ wmap, int prof,
-                                                    int nshift_max) {
-  extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2)
+                                                    int nshift_max, int nh) {
+  extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2); a helper's staging
   __shared__ QRShared S;
-  const int w = wmap ? wmap[blockIdx.x] : blockIdx.x;
+  // role-major: the chases of all window slots, then helper 0 of each, ...
+  // (consecutive workgroups go to consecutive XCDs, so with 8 slots a chase
+  // and its helpers share one XCD and each chase has an L2 of its own)
+  const int nslot = int(gridDim.x) / (1 + nh);
+  const int slot = int(blockIdx.x) % nslot, role = int(blockIdx.x) / nslot;
+  const int w = wmap ? wmap[slot] : slot;
   if (w < 0) return;  // idle slot (whole workgroup)
   c128* H = Hall + int64_t(w) * wsh;
   c128* Z = Zall + int64_t(w) * wsz;
   c128* th = theta + int64_t(w) * wst;
+  c128* lg = logall + int64_t(w) * wsl;
+  RotRec* rec = reinterpret_cast<RotRec*>(lg + 2);
+  c128* qs = lg + log_qstore_offset(m);
+  ChaseSync* sy = reinterpret_cast<ChaseSync*>(lg + log_sync_offset(m));
+  if (role > 0) {
+    chase_helper(H, m, rec, sy, role - 1, S, lds);
+    return;
+  }
   // the Hessenberg step leaves its reflectors below the subdiagonal
   for (int64_t e = threadIdx.x; e < int64_t(m) * m; e += kQT)
     if (e / m > e % m + 1) H[e] = c128{0.0, 0.0};
   __syncthreads();
-  c128* lg = logall + int64_t(w) * wsl;
-  RotRec* rec = reinterpret_cast<RotRec*>(lg + 2);
-  c128* qs = lg + log_qstore_offset(m);
   int nstep = 0, nq = 0;  // steps logged, Q store entries used: the same in every thread
   auto make_room = [&](int qneed) {
     if (nstep < cap && nq + qneed <= kQCap) return;
@@ -438,6 +692,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   const double ulp = 2.220446049250313e-16;
   int ihi = m - 1;
   int sweeps = 0;
+  unsigned long long dsweep = 0;  // deferred sweeps published
   const int maxsweeps = 20 * m + 20;
   bool failed = false;
   unsigned long long tp = wall_clock64();
@@ -545,8 +800,35 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     }
     // pipelined chase: bulge j sits at position lo + step - 3 j
     const int nsteps = (ihi - lo) + 3 * (ns - 1);
+    // defer the sweep's far updates to the helpers if all of them are
+    // running and the log holds the whole sweep (they address it by index)
+    bool defer = false, aborted = false;
+    if (nh > 0 && n >= kDeferMin && cap >= nsteps) {
+      if (nstep + nsteps > cap || nq > kQCap) {
+        __syncthreads();
+        flush_log(Z, m, rec, nstep, qs);
+        flush_log_cols(H, m, rec, nstep, qs);
+        nstep = 0;
+        nq = 0;
+      }
+      if (t == 0) S.hflag = ld_agent(&sy->present) == nh ? 1 : 0;
+      __syncthreads();
+      defer = S.hflag != 0;
+      __syncthreads();
+    }
+    if (defer) {
+      ++dsweep;
+      if (t == 0) {
+        st_agent(&sy->lo, lo);
+        st_agent(&sy->ihi, ihi);
+        st_agent(&sy->ns, ns);
+        st_agent(&sy->nsteps, nsteps);
+        st_agent(&sy->s0, nstep);
+      }
+      publish(&sy->pub, dsweep << 32);
+    }
     for (int step = 0; step < nsteps; ++step) {
-      make_room(0);
+      if (!defer) make_room(0);
       if (t < ns) {
         const int p = lo + step - 3 * t;
         if (p >= lo && p < ihi) {
@@ -579,6 +861,30 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         rec[int64_t(nstep) * kShifts + t] = R;
       }
       ++nstep;
+      // columns up to ecol are the chase's at this step; in a deferred sweep
+      // it takes the next kTake of them from the helpers every kTake steps
+      int ecol = ihi;
+      if (defer) {
+        if ((step + 1) % kPub == 0 || step + 1 == nsteps)
+          publish(&sy->pub, (dsweep << 32) | (unsigned long long)(unsigned)(step + 1));
+        ecol = min(ihi, lo + kTake * (step / kTake + 2));
+        const int cfirst = lo + kTake * (step / kTake + 1) + 1;
+        if (step > 0 && step % kTake == 0 && cfirst <= ecol) {
+          if (t == 0) {
+            const unsigned long long need = (dsweep << 32) | (unsigned long long)(unsigned)step;
+            const bool ok = spin_wait([&] {
+              for (int hh = cfirst / kHelpBand; hh <= ecol / kHelpBand; ++hh)
+                if (ld_agent(&sy->prog[hh]) < need) return false;
+              return true;
+            }, true);
+            S.hflag = ok ? 0 : 1;
+          }
+          __syncthreads();
+          aborted = S.hflag != 0;
+          __syncthreads();
+          if (aborted) break;
+        }
+      }
       tick(2);
       // active bulges form the contiguous range [ja, jb]
       // bulge j is at p = lo + step - 3 j, active while lo <= p <= ihi - 1
@@ -592,8 +898,9 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       // thread loads a batch of independent items before storing any.
       {
         const int cstart = nact > 0 ? max(lo + step - 3 * jb - 1, lo) : lo;
-        // columns beyond ihi are left to the column replay
-        const int W = max(0, ihi + 1 - cstart);
+        // columns beyond ihi are left to the column replay, those beyond
+        // ecol to the helpers
+        const int W = max(0, ecol + 1 - cstart);
         const int total = nact * W;
         for (int base = t; base < total; base += kQT * kBatch) {
           // every item loads (a skipped one from H's first elements) so that
@@ -634,7 +941,9 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       {
         // rows below the deepest active bulge's last one are untouched
         const int Rh = nact > 0 ? min(lo + step - 3 * ja + 2, ihi) + 1 : 0;
-        const int total = Rh * nact;
+        // in a deferred sweep the rows above the topmost bulge are the helpers'
+        const int rlo = defer ? max(lo, lo + step - 3 * (ns - 1)) : 0;
+        const int total = max(0, Rh - rlo) * nact;
         for (int base = t; base < total; base += kQT * kBatch) {
           // every item loads (a skipped one from H's first elements) so that
           // the batch's loads are all in flight before the first is used
@@ -645,7 +954,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
           for (int q = 0; q < kBatch; ++q) {
             const int idx = base + q * kQT;
             const bool in = idx < total;
-            const int r = in ? idx / nact : 0;
+            const int r = in ? rlo + idx / nact : 0;
             const int j = in ? ja + idx % nact : ja;
             const int p = in ? S.bp[j] : -1;
             const bool ok = p >= 0 && r <= min(p + 2, ihi);
@@ -673,12 +982,29 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
       tick(4);
       if (prof && t == 0) atomicAdd(&g_k4prof[7], 1ull);
     }
+    if (defer && !aborted) {
+      // the helpers' rows and columns are needed from here on
+      if (t == 0) {
+        const unsigned long long need = (dsweep << 32) | (unsigned long long)(unsigned)nsteps;
+        const bool ok = spin_wait([&] {
+          for (int hh = 0; hh < nh; ++hh)
+            if (ld_agent(&sy->prog[hh]) < need) return false;
+          return true;
+        }, true);
+        S.hflag = ok ? 0 : 1;
+      }
+      __syncthreads();
+      aborted = S.hflag != 0;
+      __syncthreads();
+    }
+    if (aborted) { failed = true; break; }
   }
   if (t == 0) {
     info[w] = failed ? max(ihi + 1, 1) : 0;
     int* hdr = reinterpret_cast<int*>(lg);
     hdr[0] = nstep;
     hdr[1] = nq;
+    st_agent(&sy->state, failed ? 2 : 1);  // releases the helpers
   }
   if (failed) {
     for (int i = t; i <= ihi; i += kQT) th[i] = H[int64_t(i) * m + i];
@@ -801,7 +1127,7 @@ __global__ __launch_bounds__(256) void hreplay_kernel(c128* Hall, int64_t wsh, i
 
 size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
 
-int64_t schur_log_size(int m) { return log_qstore_offset(m) + int64_t(kQCap); }
+int64_t schur_log_size(int m) { return log_sync_offset(m) + kSyncC128; }
 
 void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, int64_t wsl, c128* theta,
                   int64_t wst, int* info, int nwin, hipStream_t st, const int* wmap) {
@@ -824,8 +1150,24 @@ void launch_schur(c128* H, int64_t wsh, int m, c128* Z, int64_t wsz, c128* log, 
     const long v = std::atol(e);
     if (v >= 1 && v < cap) cap = v;
   }
-  hipLaunchKernelGGL(schur_kernel, dim3(nwin), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, log, wsl, cap,
-                     theta, wst, info, wmap, prof, kShifts);
+  // helpers per window: one per kHelpBand rows and columns, when every
+  // window's chase and helpers fit on the device at once (otherwise the CUs
+  // serve more windows' chases instead); the TSG_SCHUR_HELPERS environment
+  // variable set to 0 turns them off (for testing that path)
+  static const int n_cu = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      n = 0;
+    return n;
+  }();
+  int nh = (m + kHelpBand - 1) / kHelpBand;
+  if (m < kDeferMin || nh > kMaxHelpers || int64_t(nwin) * (1 + nh) > n_cu) nh = 0;
+  if (const char* e = std::getenv("TSG_SCHUR_HELPERS"))
+    if (std::atoi(e) == 0) nh = 0;
+  if (nh > 0) hipLaunchKernelGGL(chase_sync_init_kernel, dim3(nwin), dim3(64), 0, st, log, wsl, m, wmap);
+  hipLaunchKernelGGL(schur_kernel, dim3(nwin * (1 + nh)), dim3(kQT), schur_lds_bytes(), st, H, wsh, m, Z, wsz, log,
+                     wsl, cap, theta, wst, info, wmap, prof, kShifts, nh);
   // rows of Z per replay workgroup: as many as 150 KiB of LDS hold next to
   // the staged records, at most 256 / kShifts
   const size_t rec_bytes = size_t(kChunk) * kShifts * sizeof(RotRec);

@@ -232,6 +232,43 @@ def test_dense_eig_rejects_basis_above_maximum(torch_cuda):
     assert "896" in str(err.value)
 
 
+def test_dense_eig_chase_helpers_match_single_workgroup_chase(torch_cuda, monkeypatch):
+    # From m = 128 on, each window's Schur chase runs with helper workgroups
+    # that replay the rotations above and to the right of the bulge train;
+    # TSG_SCHUR_HELPERS=0 keeps the whole chase in one workgroup.  Both apply
+    # the same rotations to every element in the same order, so the spectra
+    # agree to rounding, and both must be eigenpairs of H.  8 x 450 is the
+    # shape of the c2 solve (50 pairs per window, 8 windows).
+    torch = torch_cuda
+    from scipy.optimize import linear_sum_assignment
+    from paper_1606_01139_amd import dense_eig
+    rng = np.random.default_rng(450)
+    m, batch = 450, 8
+    Hs = []
+    for _ in range(batch):
+        X = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        Hs.append((X + X.conj().T) / 2 - 0.05j * (X @ X.conj().T) / m)
+    H = np.stack(Hs)
+    print("dense_eig 8 x 450, chase with helpers", flush=True)
+    monkeypatch.delenv("TSG_SCHUR_HELPERS", raising=False)
+    th0, Y0, info0 = dense_eig(torch.tensor(H, device="cuda"))
+    torch.cuda.synchronize()
+    print("dense_eig 8 x 450, one workgroup per chase", flush=True)
+    monkeypatch.setenv("TSG_SCHUR_HELPERS", "0")
+    th1, Y1, info1 = dense_eig(torch.tensor(H, device="cuda"))
+    torch.cuda.synchronize()
+    monkeypatch.delenv("TSG_SCHUR_HELPERS")
+    assert (info0.cpu().numpy() == 0).all() and (info1.cpu().numpy() == 0).all()
+    th0, th1, Y0 = th0.cpu().numpy(), th1.cpu().numpy(), Y0.cpu().numpy()
+    for b in range(batch):
+        nrm = np.linalg.norm(H[b], 2)
+        d = np.abs(th0[b][:, None] - th1[b][None, :])
+        r, c = linear_sum_assignment(d)
+        assert d[r, c].max() <= 1e-12 * nrm
+        R = H[b] @ Y0[b] - Y0[b] * th0[b][None, :]
+        assert np.abs(R).max() <= 1e-11 * nrm
+
+
 def test_dense_eig_log_flush_path_is_identical(torch_cuda, monkeypatch):
     # The Schur chase logs its rotations and a second kernel applies them to
     # the Schur vectors; when the log is full the chase applies it itself.
