@@ -358,7 +358,7 @@ tsg_status tsg_load_tuning(const char* path, int32_t* n_entries);
  * complete when that stream reaches this point.  Every call on one GPU shares
  * the array: calls that overlap on one GPU (other streams or threads) race.
  * Limit: batch * (2 m^2 + rotation log(m)) complex128 values must fit in the
- * 64 MiB (m = 450: 2 matrices; m = 300: 3; m = 128: 6; m = 64: 9).
+ * 64 MiB (m = 450: 2 matrices; m = 300: 3; m = 128: 8; m = 64: 12).
  * Errors: TSG_EINVAL (null pointer, m out of range, or more than fits in the
  * scratch; nothing launched), TSG_EDEVICE. */
 tsg_status tsg_dense_eig_noalloc(void* H, int32_t m, int32_t batch, void* theta, void* Y, int32_t* info,

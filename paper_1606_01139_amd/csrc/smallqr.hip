@@ -45,7 +45,9 @@ namespace {
 #define TSG_SCHUR_THREADS 1024
 #endif
 constexpr int kQT = TSG_SCHUR_THREADS;  // threads per workgroup
-constexpr int kFin = 64;      // largest block finished in LDS
+// largest block finished in LDS (measured at 8 x 450: 32 is 1-2% faster than
+// 64, the multishift sweeps being quicker than the one-wavefront QR from there)
+constexpr int kFin = 32;
 constexpr int kMaxShift = 64;
 // Shifts per multishift sweep.  Measured on gfx950 (m = 304, 8 matrices):
 // 12-16 shifts are fastest (about 0.7x the time of 48), since the shift
@@ -444,9 +446,12 @@ constexpr unsigned long long kSpinTicks = 1000000000ull;  // 10 s of the 100 MHz
 static_assert(2 * kHelpBand * kShifts == kQT, "helper lanes: one band of rows, one of columns");
 static_assert(kHelpChunk <= kTake, "a helper's row pass stays left of its deferred columns");
 static_assert(kTake % kPub == 0, "the step before each take is published");
-static_assert(size_t(kHelpChunk) * kShifts * sizeof(RotRec) + 2 * size_t(kHelpBand) * kHelpSpan * sizeof(c128) <=
-                  2 * size_t(kFin) * kFin * sizeof(c128),
-              "helper LDS");
+// dynamic LDS of the chase kernel: the LDS finish (block and unitary) or a
+// helper's staging (records, rows, columns), whichever is larger
+constexpr size_t kSchurLds =
+    std::max(2 * size_t(kFin) * kFin * sizeof(c128),
+             size_t(kHelpChunk) * kShifts * sizeof(RotRec) + 2 * size_t(kHelpBand) * kHelpSpan * sizeof(c128));
+static_assert(kSchurLds <= size_t(150) * 1024, "chase LDS");
 
 // Per-window state shared by the chase and its helpers (after the log).
 struct ChaseSync {
@@ -655,7 +660,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
                                                     c128* logall, int64_t wsl, int64_t cap, c128* theta, int64_t wst,
                                                     int* info, const int* __restrict__ wmap, int prof,
                                                     int nshift_max, int nh) {
-  extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2); a helper's staging
+  extern __shared__ c128 lds[];  // B (kFin^2) and Q (kFin^2), or a helper's staging
   __shared__ QRShared S;
   // role-major: the chases of all window slots, then helper 0 of each, ...
   // (consecutive workgroups go to consecutive XCDs, so with 8 slots a chase
@@ -1125,7 +1130,7 @@ __global__ __launch_bounds__(256) void hreplay_kernel(c128* Hall, int64_t wsh, i
 
 }  // namespace
 
-size_t schur_lds_bytes() { return size_t(2) * kFin * kFin * sizeof(c128); }
+size_t schur_lds_bytes() { return kSchurLds; }
 
 int64_t schur_log_size(int m) { return log_sync_offset(m) + kSyncC128; }
 

@@ -191,9 +191,13 @@ def test_c4_first_windows_and_gradient_against_oracle_and_differences(torch_cuda
     counts, and the combined set against the oracle's stored windows
     (tests/golden/c4_windows.json, from oracle/ only) at 1e-10; then the
     gradient of sum_e w_e T(E_e) from tsg_transmission_vjp against central
-    differences (step 1e-5) of the GPU pipeline itself: along one random
-    direction in V(r), the check that stands in for every grid point, and
-    for the left absorber amplitude, each to 1e-5 relative."""
+    differences of the GPU pipeline itself: along one random direction in
+    V(r), the check that stands in for every grid point, and for the left
+    absorber amplitude, each to 1e-5 relative.  The loss the differences
+    take carries the eigensolve's rounding (about 1e-14 relative), which a
+    step of 1e-5 turns into about 1e-5 of the derivative; so the steps are
+    h = 1e-4 and 2h, Richardson-extrapolated, (4 D(h) - D(2h)) / 3, which
+    removes the O(h^2) truncation error those steps bring."""
     import json
     import os
     import time
@@ -235,15 +239,21 @@ def test_c4_first_windows_and_gradient_against_oracle_and_differences(torch_cuda
         o.close()
         return val
 
-    step = 1e-5
+    def richardson(f, h):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(2 * h) - f(-2 * h)) / (4 * h)
+        return (4 * d1 - d2) / 3, d1
+
+    step = 1e-4
     dirn = np.random.default_rng(6).standard_normal(g.n)
     dirn /= np.abs(dirn).max()
-    fd = (loss(w.V + step * dirn, ab) - loss(w.V - step * dirn, ab)) / (2 * step)
+    fd, fd1 = richardson(lambda t: loss(w.V + t * dirn, ab), step)
     got = float(dV @ dirn)
-    print(f"directional derivative: vjp {got:.10e}, central difference {fd:.10e}", flush=True)
+    print(f"directional derivative: vjp {got:.10e}, central difference {fd1:.10e}, extrapolated {fd:.10e}",
+          flush=True)
     assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-6)
     da = np.zeros(6)
-    da[0] = step
-    fd_a = (loss(w.V, ab + da) - loss(w.V, ab - da)) / (2 * step)
-    print(f"d/d amp_L: vjp {dab[0]:.10e}, central difference {fd_a:.10e}", flush=True)
+    da[0] = 1.0
+    fd_a, fd_a1 = richardson(lambda t: loss(w.V, ab + t * da), step)
+    print(f"d/d amp_L: vjp {dab[0]:.10e}, central difference {fd_a1:.10e}, extrapolated {fd_a:.10e}", flush=True)
     assert abs(dab[0] - fd_a) <= 1e-5 * max(abs(fd_a), 1e-6)

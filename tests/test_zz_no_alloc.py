@@ -54,7 +54,7 @@ def test_noalloc_dense_eig_matches_allocating_call(torch_cuda):
 def test_noalloc_dense_eig_refuses_batches_beyond_the_scratch(torch_cuda):
     torch = torch_cuda
     from paper_1606_01139_amd.binding import dense_eig_noalloc, TsgError, TSG_EINVAL
-    batch, m = 3, 450  # 3 x 29 MB of workspace > 64 MiB
+    batch, m = 3, 450  # 3 x 27.5 MB of workspace > 64 MiB
     H = torch.zeros((batch, m, m), dtype=torch.complex128, device="cuda")
     th = torch.zeros((batch, m), dtype=torch.complex128, device="cuda")
     Y = torch.zeros((batch, m, m), dtype=torch.complex128, device="cuda")
