@@ -77,6 +77,10 @@ struct RotRec {
   c128 s;
 };
 static_assert(sizeof(RotRec) == 32, "RotRec layout");
+// Set in record 1's ihi field of every step of a sweep whose far updates went
+// to helper workgroups: they have applied its left rotations to the columns
+// beyond ihi and its right rotations to Z, so the replays skip the step.
+constexpr int kDeferredStep = 1 << 30;
 
 // Per-window log, in c128 units: a 2-entry header (steps, Q blocks), the
 // step records, the Q store.  The capacity covers 80 multishift sweeps; a
@@ -343,6 +347,7 @@ __device__ __attribute__((noinline)) void flush_log(c128* Z, int m, const RotRec
     c128* row = Z + int64_t(min(r, m - 1)) * m;
     for (int st = 0; st < nstep; ++st) {
       const RotRec* R = rec + int64_t(st) * kShifts;
+      if (R[1].pad & kDeferredStep) continue;  // uniform: the helpers did it
       if (R[0].p <= -2) {
         c128 acc[kQAcc];
         if (r < m) qblock_row(row, R[0], qs, j, acc);
@@ -402,6 +407,7 @@ __device__ __attribute__((noinline)) void flush_log_cols(c128* H, int m, const R
     c128* col = H + min(c, m - 1);
     for (int st = 0; st < nstep; ++st) {
       const RotRec* R = rec + int64_t(st) * kShifts;
+      if (R[1].pad & kDeferredStep) continue;  // uniform: the helpers did it
       const bool take = mine && R[0].pad < c;
       if (R[0].p <= -2) {
         c128 acc[kQAcc];
@@ -525,15 +531,19 @@ __device__ inline bool spin_wait(F done, bool acquire) {
 // First step of a deferred sweep from which row r is the helper's.
 __device__ inline int helper_srow(int r, int lo, int ns) { return r < lo ? 0 : r - lo + 3 * (ns - 1) + 1; }
 // Step at which the chase takes column c back (0: the chase's all sweep).
+// A column beyond ihi is never read again, so it takes the whole sweep's
+// left rotations from its helper (the column replay skips deferred steps).
 __device__ inline int helper_scol(int c, int lo, int ihi) {
-  return (c < lo || c > ihi) ? 0 : kTake * max(0, (c - lo + kTake - 1) / kTake - 2);
+  if (c < lo) return 0;
+  if (c > ihi) return 0x7fffffff;
+  return kTake * max(0, (c - lo + kTake - 1) / kTake - 2);
 }
 
 // One pass of helper h over steps [sa, sb) of the deferred sweep: the steps'
 // right rotations on its rows and left rotations on its columns, the parts
 // they touch ([base, top], by the bulge positions lo + s - 3 j) held in LDS.
-__device__ void helper_pass(c128* H, int m, const RotRec* rec, int s0, int lo, int ihi, int ns, int b0, int sa,
-                            int sb, c128* lds) {
+__device__ void helper_pass(c128* H, c128* Z, int m, const RotRec* rec, int s0, int lo, int ihi, int ns, int b0,
+                            int sa, int sb, c128* lds) {
   const int t = threadIdx.x;
   RotRec* rl = reinterpret_cast<RotRec*>(lds);
   c128* rows = lds + int64_t(kHelpChunk) * kShifts * (sizeof(RotRec) / sizeof(c128));
@@ -589,11 +599,42 @@ __device__ void helper_pass(c128* H, int m, const RotRec* rec, int s0, int lo, i
     }
   }
   __syncthreads();
+  // the band's rows of Z take every right rotation of the steps (the Z
+  // replay skips deferred steps), in the rows' staging
+  for (int e = t; e < kHelpBand * W; e += kQT) {
+    const int i = e / W, q = e % W, x = b0 + i;
+    if (x < m) rows[i * kHelpSpan + q] = ld_shared(Z + int64_t(x) * m + base + q);
+  }
+  __syncthreads();
+  if (t < kHelpBand * kShifts) {
+    const int j = t % kShifts, i = t / kShifts;
+    c128* seg = rows + i * kHelpSpan;
+    const bool on = b0 + i < m;
+    for (int s = sa; s < sb; ++s) {
+      if (on) {
+        const RotRec R = rl[(s - sa) * kShifts + j];
+        if (R.p >= 0) {
+          c128* a = seg + (R.p - base);
+          const c128 u = a[0], v = a[1];
+          a[0] = R.c * u + conj(R.s) * v;
+          a[1] = R.c * v - R.s * u;
+        }
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < kHelpBand * W; e += kQT) {
+    const int i = e / W, q = e % W, x = b0 + i;
+    if (x < m) st_shared(Z + int64_t(x) * m + base + q, rows[i * kHelpSpan + q]);
+  }
+  __syncthreads();
 }
 
 // Helper h of a window: announces itself, then serves every deferred sweep
 // the chase publishes until the chase has finished (or a wait gives up).
-__device__ void chase_helper(c128* H, int m, const RotRec* rec, ChaseSync* sy, int h, QRShared& S, c128* lds) {
+__device__ void chase_helper(c128* H, c128* Z, int m, const RotRec* rec, ChaseSync* sy, int h, QRShared& S,
+                             c128* lds) {
   const int t = threadIdx.x;
   if (t == 0) __hip_atomic_fetch_add(&sy->present, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned long long seen = 0;  // last sweep served
@@ -640,7 +681,7 @@ __device__ void chase_helper(c128* H, int m, const RotRec* rec, ChaseSync* sy, i
         if (bad) return;
       }
       for (int sa = done; sa < avail; sa += kHelpChunk)
-        helper_pass(H, m, rec, s0, lo, ihi, ns, h * kHelpBand, sa, min(avail, sa + kHelpChunk), lds);
+        helper_pass(H, Z, m, rec, s0, lo, ihi, ns, h * kHelpBand, sa, min(avail, sa + kHelpChunk), lds);
       done = avail;
       publish(&sy->prog[h], (seen << 32) | (unsigned long long)(unsigned)done);
     }
@@ -677,7 +718,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
   c128* qs = lg + log_qstore_offset(m);
   ChaseSync* sy = reinterpret_cast<ChaseSync*>(lg + log_sync_offset(m));
   if (role > 0) {
-    chase_helper(H, m, rec, sy, role - 1, S, lds);
+    chase_helper(H, Z, m, rec, sy, role - 1, S, lds);
     return;
   }
   // the Hessenberg step leaves its reflectors below the subdiagonal
@@ -685,6 +726,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     if (e / m > e % m + 1) H[e] = c128{0.0, 0.0};
   __syncthreads();
   int nstep = 0, nq = 0;  // steps logged, Q store entries used: the same in every thread
+  bool nd_log = false;    // the log holds steps of a sweep without helpers
   auto make_room = [&](int qneed) {
     if (nstep < cap && nq + qneed <= kQCap) return;
     __syncthreads();
@@ -692,6 +734,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     flush_log_cols(H, m, rec, nstep, qs);
     nstep = 0;
     nq = 0;
+    nd_log = false;
   };
   const int t = threadIdx.x;
   const double ulp = 2.220446049250313e-16;
@@ -809,12 +852,16 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     // running and the log holds the whole sweep (they address it by index)
     bool defer = false, aborted = false;
     if (nh > 0 && n >= kDeferMin && cap >= nsteps) {
-      if (nstep + nsteps > cap || nq > kQCap) {
+      // the log must hold the whole sweep; and steps of sweeps without
+      // helpers still pending for the column replay are applied first, so
+      // that every column beyond ihi takes its rotations in log order
+      if (nstep + nsteps > cap || nq > kQCap || nd_log) {
         __syncthreads();
         flush_log(Z, m, rec, nstep, qs);
         flush_log_cols(H, m, rec, nstep, qs);
         nstep = 0;
         nq = 0;
+        nd_log = false;
       }
       if (t == 0) S.hflag = ld_agent(&sy->present) == nh ? 1 : 0;
       __syncthreads();
@@ -861,11 +908,12 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         RotRec R;
         R.c = t < ns ? S.bc[t] : 1.0;
         R.p = t < ns ? S.bp[t] : -1;
-        R.pad = ihi;
+        R.pad = (defer && t == 1) ? (ihi | kDeferredStep) : ihi;
         R.s = t < ns ? S.bs[t] : c128{0.0, 0.0};
         rec[int64_t(nstep) * kShifts + t] = R;
       }
       ++nstep;
+      if (!defer) nd_log = true;
       // columns up to ecol are the chase's at this step; in a deferred sweep
       // it takes the next kTake of them from the helpers every kTake steps
       int ecol = ihi;
@@ -1046,6 +1094,7 @@ __global__ __launch_bounds__(256) void zreplay_kernel(c128* Zall, int64_t wsz, i
     __syncthreads();
     for (int st = 0; st < nc; ++st) {
       const RotRec* R = chunk + st * kShifts;
+      if (R[1].pad & kDeferredStep) continue;  // uniform: the helpers did it
       if (R[0].p <= -2) {
         c128 acc[kQAcc];
         if (mine) qblock_row(row, R[0], qs, j, acc);
@@ -1108,6 +1157,7 @@ __global__ __launch_bounds__(256) void hreplay_kernel(c128* Hall, int64_t wsh, i
     __syncthreads();
     for (int st = 0; st < n; ++st) {
       const RotRec* R = chunk + st * kShifts;
+      if (R[1].pad & kDeferredStep) continue;  // uniform: the helpers did it
       const bool take = mine && R[0].pad < c;
       if (R[0].p <= -2) {
         c128 acc[kQAcc];
