@@ -726,7 +726,7 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
     if (e / m > e % m + 1) H[e] = c128{0.0, 0.0};
   __syncthreads();
   int nstep = 0, nq = 0;  // steps logged, Q store entries used: the same in every thread
-  bool nd_log = false;    // the log holds steps of a sweep without helpers
+  bool nd_log = false;    // the log holds steps of a sweep without helpers on a block of >= kDeferMin rows
   auto make_room = [&](int qneed) {
     if (nstep < cap && nq + qneed <= kQCap) return;
     __syncthreads();
@@ -913,7 +913,11 @@ __global__ __launch_bounds__(kQT) void schur_kernel(c128* Hall, int64_t wsh, int
         rec[int64_t(nstep) * kShifts + t] = R;
       }
       ++nstep;
-      if (!defer) nd_log = true;
+      // a sweep without helpers on a block the helpers could have taken: a
+      // later deferred sweep of the same block overlaps it (blocks below
+      // 128 rows never are: lo only grows within a block, and later blocks
+      // lie above it, so their rotations act on other rows and columns)
+      if (!defer && n >= kDeferMin) nd_log = true;
       // columns up to ecol are the chase's at this step; in a deferred sweep
       // it takes the next kTake of them from the helpers every kTake steps
       int ecol = ihi;
