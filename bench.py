@@ -201,7 +201,7 @@ def k4_flops(m):
 # Bytes in and out of the L2s per launch, from the FETCH_SIZE and WRITE_SIZE
 # counters, each scaled by what it reads for a plain 512 MiB copy (fetch x 2,
 # write x 1); only the shapes below were measured.
-K4_TRAFFIC_C2 = 74_949_946_384  # 8 x 450 x 450 complex128
+K4_TRAFFIC_C2 = 76_031_485_356  # 8 x 450 x 450 complex128
 STENCIL_TRAFFIC = {
     (32, 32, 64, 16, "c128"): 38_580_166,
     (64, 64, 160, 64, "c64"): 1_274_024_982,
