@@ -30,7 +30,8 @@
 // of the sweep reads the rows above the bulge train, and none reads a column
 // well to the right of it before the train arrives.  Those updates go to
 // helper workgroups of the same launch on other CUs (see chase_helper), so
-// that the chase itself only touches the rows and columns around the train.
+// that the chase itself only touches the rows and columns around the train;
+// the helpers also take the sweep's share of the two replays above.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -434,12 +435,15 @@ __device__ __attribute__((noinline)) void flush_log_cols(c128* H, int m, const R
 //     rotations reach it only to the right of the train.  The chase owns the
 //     columns up to e(s) = lo + kTake (s / kTake + 2) at step s, so it takes
 //     them back kTake at a time, each block before the train gets near it.
+//   * columns beyond ihi and the band's rows of Z take every rotation of the
+//     sweep from the helper (left ones, right ones), so the column and Z
+//     replays skip the sweep's steps (flagged kDeferredStep).
 // The helper replays the logged rotations of each chunk of published steps
 // onto the parts of its rows and columns that chunk touches, staged in LDS
 // (lane j of a row or column applies record j of each step), and reports the
-// steps done.  The chase publishes every step's records, waits for the helpers
-// owning a block of columns before it takes it, and for all of them at the end
-// of the sweep.  A helper announces itself when it starts; a sweep is deferred
+// steps done.  The chase publishes its records every kPub steps, waits for
+// the helpers owning a block of columns before it takes it, and for all of
+// them at the end of the sweep.  A helper announces itself when it starts; a sweep is deferred
 // only if every helper of the window has, so the chase never waits on a
 // workgroup that is not running, and helpers wait only on the chase.  Every
 // wait gives up after kSpinTicks (the window then fails with info > 0).
