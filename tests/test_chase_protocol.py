@@ -22,7 +22,12 @@ by what has been published, and checks that
     until the chase next waits for it) that the chase reads or writes, and
     no two helpers hold the same element at once.
 Columns beyond ihi take all left rotations (the column replay's share in a
-sweep without helpers)."""
+sweep without helpers).
+
+A second model follows one column of H beyond every ihi and one row of Z
+through a whole run of blocks, deferred steps taking effect when the
+helpers replay them and the rest when the replays run (or the chase
+flushes its log), and checks that the result is that of log order."""
 import random
 
 import numpy as np
@@ -173,3 +178,81 @@ def test_deferred_sweep_matches_plain_sweep(m, lo, ihi, ns):
     for seed in (1, 2):
         split = sweep(H, lo, ihi, shifts, True, random.Random(seed))
         assert np.array_equal(plain, split)
+
+
+def _order_model(m, blocks, flush_rule, rng):
+    """One column of H beyond every ihi and one row of Z under a whole
+    Schur run: blocks of (lo, ihi, sweeps, deferred, finished), each sweep
+    a list of steps of disjoint rotations on the block, a finished block
+    ended by a unitary on its rows (the LDS finish; a block that splits has
+    none, its parts follow).  Steps of deferred sweeps take effect when
+    the helpers replay them; the rest when the replays run after the kernel,
+    or when the chase flushes its log (before a deferred sweep, if the log
+    holds steps of an undeferred sweep of a block of 128 or more rows).
+    Returns (in log order, as the protocol applies them)."""
+    col_ref = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    zrow_ref = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    col, zrow = col_ref.copy(), zrow_ref.copy()
+    pending, nd_log = [], False
+
+    def apply(op, col, zrow):
+        kind, a, b = op
+        if kind == "rot":  # left rotation on rows (a, a+1); right rotation on Z columns (a, a+1)
+            c, s = b
+            col[a], col[a + 1] = left(c, s, col[a], col[a + 1])
+            zrow[a], zrow[a + 1] = right(c, s, zrow[a], zrow[a + 1])
+        else:  # unitary Q on rows / Z columns [a, a + n)
+            Q = b
+            n = Q.shape[0]
+            col[a:a + n] = Q.conj().T @ col[a:a + n]
+            zrow[a:a + n] = zrow[a:a + n] @ Q
+
+    def flush():
+        nonlocal pending, nd_log
+        for op in pending:
+            apply(op, col, zrow)
+        pending, nd_log = [], False
+
+    for (lo, ihi, nsweeps, deferred, finished) in blocks:
+        for _ in range(nsweeps):
+            if deferred and flush_rule and nd_log:
+                flush()
+            for s in range(8):
+                ps = range(lo + (s % 3), ihi, 3)
+                for p in ps:
+                    c, sj = givens(rng.standard_normal() + 1j * rng.standard_normal(),
+                                   rng.standard_normal() + 1j * rng.standard_normal())
+                    op = ("rot", p, (c, sj))
+                    apply(op, col_ref, zrow_ref)
+                    if deferred:
+                        apply(op, col, zrow)
+                    else:
+                        pending.append(op)
+            if not deferred and ihi - lo + 1 >= 128:
+                nd_log = True
+        if not finished:
+            continue
+        X = rng.standard_normal((ihi - lo + 1,) * 2) + 1j * rng.standard_normal((ihi - lo + 1,) * 2)
+        Q, _ = np.linalg.qr(X)
+        op = ("q", lo, Q)
+        apply(op, col_ref, zrow_ref)
+        pending.append(op)
+    flush()
+    return col_ref, zrow_ref, col, zrow
+
+
+def test_replays_keep_log_order():
+    # blocks in the order the chase meets them: [0, 299] swept first without
+    # helpers (they had not started), then with them, until it splits at 250
+    # and 200; [250, 299] and [200, 249], too small for helpers, are swept
+    # and finished; then [0, 199] with helpers
+    m = 300
+    blocks = [(0, 299, 1, False, False), (0, 299, 2, True, False), (250, 299, 2, False, True),
+              (200, 249, 1, False, True), (0, 199, 2, True, True)]
+    ref_c, ref_z, col, zrow = _order_model(m, blocks, True, np.random.default_rng(3))
+    np.testing.assert_allclose(col, ref_c, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(zrow, ref_z, rtol=0, atol=1e-12)
+    # without the flush the undeferred sweep of [0, 299] would be replayed
+    # after the deferred ones that overlap it
+    ref_c, ref_z, col, zrow = _order_model(m, blocks, False, np.random.default_rng(3))
+    assert np.abs(col - ref_c).max() > 1e-6
